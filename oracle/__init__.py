@@ -1,0 +1,196 @@
+"""FP64 CPU oracle for the Joseph projector (TEST INFRASTRUCTURE ONLY).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may use
+this package.  The GPU product path never imports it and shares no code with
+it.  The arithmetic lives in ``joseph64.c`` (plain C, double precision,
+OpenMP over rays); this module builds it with gcc and wraps it with ctypes
+for numpy arrays.
+
+Every function takes the same float32 ray endpoints (``[n, 3]``) and image
+geometry the GPU library takes, the image / projections in float64, and
+returns float64 results.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "joseph64.c")
+_LIB = os.path.join(_HERE, "liboracle64.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile ``joseph64.c`` into ``liboracle64.so`` (gcc, -O2, OpenMP, IEEE math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-fno-fast-math",
+               "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB)
+    P = ctypes.c_void_p
+    I64 = ctypes.c_int64
+    F = ctypes.c_float
+    I32 = ctypes.c_int32
+    geo = [P, P, I64, P, P, P]
+    tof = [F, F, F, F, I32]
+    lib.orc_fwd.argtypes = geo + [P, P]
+    lib.orc_back.argtypes = geo + [P, P]
+    lib.orc_fwd_tof_sino.argtypes = geo + tof + [P, P]
+    lib.orc_back_tof_sino.argtypes = geo + tof + [P, P]
+    lib.orc_fwd_tof_lm.argtypes = geo + tof + [P, P, P]
+    lib.orc_back_tof_lm.argtypes = geo + tof + [P, P, P]
+    lib.orc_count_samples.argtypes = geo + tof + [P, P]
+    lib.orc_count_samples.restype = I64
+    lib.orc_lm_osem.argtypes = [P, P, P, I64, P, P, P] + tof + [P, ctypes.c_double, I32, I32, P]
+    lib.orc_max_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _f32(a, shape_last=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    if shape_last is not None and (a.ndim != 2 or a.shape[1] != shape_last):
+        raise ValueError("expected an array of shape [n, %d]" % shape_last)
+    return a
+
+
+def _geom(origin, voxsize, dim):
+    o = np.ascontiguousarray(np.asarray(origin, dtype=np.float32).reshape(3))
+    h = np.ascontiguousarray(np.asarray(voxsize, dtype=np.float32).reshape(3))
+    d = np.ascontiguousarray(np.asarray(dim, dtype=np.int32).reshape(3))
+    return o, h, d
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _tofargs(tof):
+    """tof: object/dict with bin_width, sigma, n_sigmas, n_bins, (center_offset)."""
+    g = (lambda k, d=None: tof.get(k, d)) if isinstance(tof, dict) else (lambda k, d=None: getattr(tof, k, d))
+    return (ctypes.c_float(g("bin_width")), ctypes.c_float(g("sigma")), ctypes.c_float(g("n_sigmas")),
+            ctypes.c_float(g("center_offset", 0.0)), ctypes.c_int32(int(g("n_bins"))))
+
+
+def max_threads() -> int:
+    return int(_load().orc_max_threads())
+
+
+def fwd(xstart, xend, origin, voxsize, dim, img):
+    """Non-TOF forward projection. Returns float64 [n]."""
+    lib = _load()
+    xs, xe = _f32(xstart, 3), _f32(xend, 3)
+    o, h, d = _geom(origin, voxsize, dim)
+    x = np.ascontiguousarray(np.asarray(img, dtype=np.float64).reshape(tuple(d)))
+    out = np.zeros(xs.shape[0], dtype=np.float64)
+    lib.orc_fwd(_ptr(xs), _ptr(xe), xs.shape[0], _ptr(o), _ptr(h), _ptr(d), _ptr(x), _ptr(out))
+    return out
+
+
+def back(xstart, xend, origin, voxsize, dim, p):
+    """Non-TOF back projection (adjoint). Returns float64 image ``dim``."""
+    lib = _load()
+    xs, xe = _f32(xstart, 3), _f32(xend, 3)
+    o, h, d = _geom(origin, voxsize, dim)
+    y = np.ascontiguousarray(np.asarray(p, dtype=np.float64).reshape(xs.shape[0]))
+    out = np.zeros(tuple(d), dtype=np.float64)
+    lib.orc_back(_ptr(xs), _ptr(xe), xs.shape[0], _ptr(o), _ptr(h), _ptr(d), _ptr(out), _ptr(y))
+    return out
+
+
+def fwd_tof_sino(xstart, xend, origin, voxsize, dim, tof, img):
+    """TOF sinogram forward projection. Returns float64 [n, n_bins]."""
+    lib = _load()
+    xs, xe = _f32(xstart, 3), _f32(xend, 3)
+    o, h, d = _geom(origin, voxsize, dim)
+    ta = _tofargs(tof)
+    x = np.ascontiguousarray(np.asarray(img, dtype=np.float64).reshape(tuple(d)))
+    out = np.zeros((xs.shape[0], ta[4].value), dtype=np.float64)
+    lib.orc_fwd_tof_sino(_ptr(xs), _ptr(xe), xs.shape[0], _ptr(o), _ptr(h), _ptr(d), *ta, _ptr(x), _ptr(out))
+    return out
+
+
+def back_tof_sino(xstart, xend, origin, voxsize, dim, tof, p):
+    lib = _load()
+    xs, xe = _f32(xstart, 3), _f32(xend, 3)
+    o, h, d = _geom(origin, voxsize, dim)
+    ta = _tofargs(tof)
+    y = np.ascontiguousarray(np.asarray(p, dtype=np.float64).reshape(xs.shape[0], ta[4].value))
+    out = np.zeros(tuple(d), dtype=np.float64)
+    lib.orc_back_tof_sino(_ptr(xs), _ptr(xe), xs.shape[0], _ptr(o), _ptr(h), _ptr(d), *ta, _ptr(out), _ptr(y))
+    return out
+
+
+def _bins(b, n):
+    b = np.ascontiguousarray(np.asarray(b, dtype=np.int16).reshape(n))
+    return b
+
+
+def fwd_tof_lm(xstart, xend, origin, voxsize, dim, tof, bins, img):
+    """TOF listmode forward projection (only each event's bin). Returns float64 [n]."""
+    lib = _load()
+    xs, xe = _f32(xstart, 3), _f32(xend, 3)
+    o, h, d = _geom(origin, voxsize, dim)
+    ta = _tofargs(tof)
+    b = _bins(bins, xs.shape[0])
+    x = np.ascontiguousarray(np.asarray(img, dtype=np.float64).reshape(tuple(d)))
+    out = np.zeros(xs.shape[0], dtype=np.float64)
+    lib.orc_fwd_tof_lm(_ptr(xs), _ptr(xe), xs.shape[0], _ptr(o), _ptr(h), _ptr(d), *ta, _ptr(b), _ptr(x),
+                       _ptr(out))
+    return out
+
+
+def back_tof_lm(xstart, xend, origin, voxsize, dim, tof, bins, p):
+    lib = _load()
+    xs, xe = _f32(xstart, 3), _f32(xend, 3)
+    o, h, d = _geom(origin, voxsize, dim)
+    ta = _tofargs(tof)
+    b = _bins(bins, xs.shape[0])
+    y = np.ascontiguousarray(np.asarray(p, dtype=np.float64).reshape(xs.shape[0]))
+    out = np.zeros(tuple(d), dtype=np.float64)
+    lib.orc_back_tof_lm(_ptr(xs), _ptr(xe), xs.shape[0], _ptr(o), _ptr(h), _ptr(d), *ta, _ptr(b), _ptr(out),
+                        _ptr(y))
+    return out
+
+
+def count_samples(xstart, xend, origin, voxsize, dim, tof=None, bins=None, per_ray=False):
+    """Plane samples whose stencil touches the grid (TOF listmode: with non-zero weight)."""
+    lib = _load()
+    xs, xe = _f32(xstart, 3), _f32(xend, 3)
+    o, h, d = _geom(origin, voxsize, dim)
+    ta = _tofargs(tof) if tof is not None else _tofargs({"bin_width": 1.0, "sigma": 1.0, "n_sigmas": 1.0,
+                                                          "n_bins": 1})
+    b = _bins(bins, xs.shape[0]) if bins is not None else None
+    pr = np.zeros(xs.shape[0], dtype=np.int64) if per_ray else None
+    tot = lib.orc_count_samples(_ptr(xs), _ptr(xe), xs.shape[0], _ptr(o), _ptr(h), _ptr(d), *ta,
+                                _ptr(b) if b is not None else None, _ptr(pr) if pr is not None else None)
+    return (int(tot), pr) if per_ray else int(tot)
+
+
+def lm_osem(xstart, xend, bins, origin, voxsize, dim, tof, sens, bg, n_iter, n_sub, x0):
+    """Listmode TOF OSEM; returns the float64 image after n_iter x n_sub updates."""
+    lib = _load()
+    xs, xe = _f32(xstart, 3), _f32(xend, 3)
+    o, h, d = _geom(origin, voxsize, dim)
+    ta = _tofargs(tof)
+    b = _bins(bins, xs.shape[0])
+    s = np.ascontiguousarray(np.asarray(sens, dtype=np.float64).reshape(tuple(d)))
+    x = np.array(np.asarray(x0, dtype=np.float64).reshape(tuple(d)), copy=True, order="C")
+    lib.orc_lm_osem(_ptr(xs), _ptr(xe), _ptr(b), xs.shape[0], _ptr(o), _ptr(h), _ptr(d), *ta, _ptr(s),
+                    ctypes.c_double(bg), ctypes.c_int32(n_iter), ctypes.c_int32(n_sub), _ptr(x))
+    return x

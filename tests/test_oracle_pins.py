@@ -1,0 +1,413 @@
+"""Pins of the FP64 oracle against facts it does not compute itself.
+
+The paper prints no worked numerical example of a projection, so every pin
+is a closed form, an invariant, a textbook special case or an independent
+brute-force formulation (tests/brute.py).  Each test says which mistake it
+would catch.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import special, stats
+
+import oracle
+from brute import system_matrix, tof_weight_quadrature
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def f32(x):
+    return float(np.float32(x))
+
+
+def tofd(bin_width, sigma, n_sigmas, n_bins, center_offset=0.0):
+    return {"bin_width": f32(bin_width), "sigma": f32(sigma), "n_sigmas": f32(n_sigmas), "n_bins": int(n_bins),
+            "center_offset": f32(center_offset)}
+
+
+def random_rays(rng, n, origin, voxsize, dim, inside_frac=0.0, grid_step=None):
+    """Rays whose endpoints lie on a sphere around the grid (some optionally inside)."""
+    o = np.asarray(origin, float)
+    h = np.asarray(voxsize, float)
+    c = o + 0.5 * (np.asarray(dim) - 1) * h
+    r = 0.5 * np.linalg.norm(np.asarray(dim) * h) + 2.0
+    u = rng.normal(size=(n, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    v = rng.normal(size=(n, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    off = rng.uniform(-0.6, 0.6, size=(n, 3)) * (np.asarray(dim) * h)
+    xs = c + off * 0.5 + r * u
+    xe = c + off * 0.5 - r * u + 0.3 * r * v
+    k = int(inside_frac * n)
+    if k:
+        xs[:k] = c + rng.uniform(-0.45, 0.45, size=(k, 3)) * (np.asarray(dim) * h)
+    if grid_step:
+        xs = np.round(xs / grid_step) * grid_step
+        xe = np.round(xe / grid_step) * grid_step
+    return xs.astype(np.float32), xe.astype(np.float32)
+
+
+# ---------------------------------------------------------------- closed forms
+
+def test_axis_aligned_uniform_chord():
+    """Pin 1: a ray along an axis through a uniform image of value 1 gives n_p * h_p
+    (ray length inside the slab between the outer voxel centres' planes, one voxel per plane).
+    Catches a wrong incidence-angle factor, a dropped plane, or an off-by-one in the plane loop."""
+    dim = (7, 5, 4)
+    vs = (1.5, 2.0, 2.5)
+    origin = (-4.5, -4.0, -3.75)
+    img = np.ones(dim)
+    for p in range(3):
+        inplane = [a for a in range(3) if a != p]
+        xs = np.zeros((1, 3), np.float32)
+        xe = np.zeros((1, 3), np.float32)
+        xs[0, p], xe[0, p] = -100.0, 100.0
+        for a in inplane:  # an in-plane point strictly inside the centre hull
+            xs[0, a] = xe[0, a] = origin[a] + 0.37 * vs[a] * (dim[a] - 1)
+        val = oracle.fwd(xs, xe, origin, vs, dim, img)[0]
+        assert val == pytest.approx(dim[p] * vs[p], rel=1e-14)
+        # reversed direction
+        val2 = oracle.fwd(xe, xs, origin, vs, dim, img)[0]
+        assert val2 == pytest.approx(dim[p] * vs[p], rel=1e-14)
+
+
+def test_affine_image_exact():
+    """Pin 2: bilinear interpolation reproduces affine images and the plane sum is a
+    midpoint rule, so for x_v = a + b.c_v and a ray inside the centre hull,
+    p = n_p * ell * (a + b . X(t_mid)), X(t_mid) the ray point on the middle plane.
+    Catches a wrong interpolation weight, a transposed in-plane axis, or a wrong ell."""
+    rng = np.random.default_rng(11)
+    dim = (9, 8, 7)
+    vs = (1.25, 2.0, 1.5)
+    origin = (3.0, -7.0, 1.0)
+    idx = np.stack(np.meshgrid(*[np.arange(n) for n in dim], indexing="ij"), -1)
+    centres = np.asarray(origin) + idx * np.asarray(vs)
+    alpha, beta = 2.5, np.array([0.3, -0.7, 1.1])
+    img = alpha + centres @ beta
+    lo = np.asarray(origin)
+    hi = lo + (np.asarray(dim) - 1) * np.asarray(vs)
+    for trial in range(40):
+        p = trial % 3
+        inplane = [a for a in range(3) if a != p]
+        s = np.zeros(3)
+        e = np.zeros(3)
+        s[p], e[p] = lo[p] - 30.0, hi[p] + 30.0
+        if trial % 2:
+            s[p], e[p] = e[p], s[p]
+        # in-plane coordinates chosen so that the whole chord between the outer planes stays in the hull
+        for a in inplane:
+            a0, a1 = rng.uniform(lo[a] + 0.1 * (hi[a] - lo[a]), hi[a] - 0.1 * (hi[a] - lo[a]), size=2)
+            # extend linearly to the endpoints, keeping the slope small enough to stay principal
+            tlo = (lo[p] - s[p]) / (e[p] - s[p])
+            thi = (hi[p] - s[p]) / (e[p] - s[p])
+            slope = (a1 - a0) / (thi - tlo)
+            s[a] = a0 - slope * tlo
+            e[a] = a0 + slope * (1.0 - tlo)
+        xs = s.astype(np.float32)[None]
+        xe = e.astype(np.float32)[None]
+        d = xe[0].astype(float) - xs[0].astype(float)
+        if np.argmax(np.abs(d)) != p:
+            continue
+        ell = vs[p] * np.linalg.norm(d) / abs(d[p])
+        zmid = lo[p] + 0.5 * (dim[p] - 1) * vs[p]
+        tmid = (zmid - xs[0, p]) / d[p]
+        X = xs[0].astype(float) + tmid * d
+        expect = dim[p] * ell * (alpha + X @ beta)
+        got = oracle.fwd(xs, xe, origin, vs, dim, img)[0]
+        assert got == pytest.approx(expect, rel=1e-12)
+
+
+def test_gaussian_blob_converges_to_line_integral():
+    """Pin 9: for a smooth blob, Joseph's sum approaches the continuous line integral
+    (closed form for a Gaussian: tau sqrt(2 pi) exp(-dist^2 / (2 tau^2))) with O(h^2)
+    error.  Catches any error in the ell normalisation that a self-consistent test cannot."""
+    tau = 6.0
+    c = np.array([1.3, -0.7, 0.4])
+    rng = np.random.default_rng(5)
+    dirs = rng.normal(size=(6, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    offs = rng.normal(size=(6, 3)) * 3.0
+    errs = []
+    for h in (2.0, 1.0, 0.5):
+        n = int(round(80.0 / h)) + 1
+        dim = (n, n, n)
+        origin = tuple(-0.5 * (n - 1) * h for _ in range(3))
+        ax = origin[0] + h * np.arange(n)
+        X, Y, Z = np.meshgrid(ax, ax, ax, indexing="ij")
+        img = np.exp(-((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2) / (2 * tau * tau))
+        xs = (offs + 150.0 * dirs).astype(np.float32)
+        xe = (offs - 150.0 * dirs).astype(np.float32)
+        got = oracle.fwd(xs, xe, origin, (h, h, h), dim, img)
+        d = xe.astype(float) - xs.astype(float)
+        u = d / np.linalg.norm(d, axis=1, keepdims=True)
+        w = c - xs.astype(float)
+        dist2 = np.sum(w * w, 1) - np.sum(w * u, 1) ** 2
+        exact = tau * math.sqrt(2 * math.pi) * np.exp(-dist2 / (2 * tau * tau))
+        errs.append(np.max(np.abs(got - exact) / exact))
+    assert errs[-1] < 2e-3
+    assert errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0  # second order
+
+
+# ------------------------------------------------------------- brute force
+
+GRIDS = [
+    ((5, 4, 3), (1.0, 1.5, 2.0), (-2.0, -2.25, -2.0)),
+    ((3, 6, 4), (2.0, 1.0, 1.25), (0.5, -3.0, 1.0)),
+]
+
+
+@pytest.mark.parametrize("gi", range(len(GRIDS)))
+def test_nontof_matches_bruteforce(gi):
+    """Pin 3 (non-TOF): oracle fwd and back == independent tent-function system matrix.
+    Covers all principal axes, both directions, rays missing or grazing the grid and
+    endpoints inside the grid (segment semantics).  Catches index, sign and transposition errors."""
+    dim, vs, origin = GRIDS[gi]
+    rng = np.random.default_rng(100 + gi)
+    xs, xe = random_rays(rng, 60, origin, vs, dim, inside_frac=0.25)
+    # add exact 45-degree ties and axis-aligned rays along voxel-centre lines (stencil edge cases)
+    extra_s = np.array([[-20, -20, 0.3], [-20, 0.1, -20], [0.5, -20, -20], [-20, origin[1], origin[2]],
+                        [origin[0] + vs[0] * (dim[0] - 1), -20, origin[2] + vs[2] * (dim[2] - 1)]], np.float32)
+    extra_e = np.array([[20, 20, 0.3], [20, 0.1, 20], [0.5, 20, 20], [20, origin[1], origin[2]],
+                        [origin[0] + vs[0] * (dim[0] - 1), 20, origin[2] + vs[2] * (dim[2] - 1)]], np.float32)
+    xs = np.concatenate([xs, extra_s])
+    xe = np.concatenate([xe, extra_e])
+    A = system_matrix(xs, xe, origin, vs, dim)
+    x = rng.uniform(0, 1, size=dim)
+    y = rng.uniform(0, 1, size=xs.shape[0])
+    np.testing.assert_allclose(oracle.fwd(xs, xe, origin, vs, dim, x), A @ x.ravel(), rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(oracle.back(xs, xe, origin, vs, dim, y).ravel(), A.T @ y, rtol=1e-12, atol=1e-12)
+    assert np.count_nonzero(A.sum(1)) > 40  # most rays do hit the grid
+
+
+@pytest.mark.parametrize("gi", range(len(GRIDS)))
+def test_tof_matches_bruteforce(gi):
+    """Pin 3 (TOF sinogram and listmode): oracle == brute force whose TOF weights come from
+    quadrature of the truncated Gaussian over each bin (no erf).  Catches a wrong bin centre,
+    sign of the TOF coordinate, sigma scaling or truncation."""
+    dim, vs, origin = GRIDS[gi]
+    rng = np.random.default_rng(200 + gi)
+    xs, xe = random_rays(rng, 30, origin, vs, dim, inside_frac=0.2)
+    tof = tofd(bin_width=2.5, sigma=1.7, n_sigmas=2.5, n_bins=9, center_offset=0.4)
+    A = system_matrix(xs, xe, origin, vs, dim, tof=tof, mode="sino")
+    x = rng.uniform(0, 1, size=dim)
+    y = rng.uniform(0, 1, size=(xs.shape[0], tof["n_bins"]))
+    np.testing.assert_allclose(oracle.fwd_tof_sino(xs, xe, origin, vs, dim, tof, x),
+                               np.einsum("lbv,v->lb", A, x.ravel()), rtol=1e-11, atol=1e-12)
+    np.testing.assert_allclose(oracle.back_tof_sino(xs, xe, origin, vs, dim, tof, y).ravel(),
+                               np.einsum("lbv,lb->v", A, y), rtol=1e-11, atol=1e-12)
+    bins = rng.integers(-1, tof["n_bins"] + 1, size=xs.shape[0]).astype(np.int16)  # incl. out of range
+    Alm = system_matrix(xs, xe, origin, vs, dim, tof=tof, mode="lm", bins=bins)
+    ylm = rng.uniform(0, 1, size=xs.shape[0])
+    np.testing.assert_allclose(oracle.fwd_tof_lm(xs, xe, origin, vs, dim, tof, bins, x), Alm @ x.ravel(),
+                               rtol=1e-11, atol=1e-12)
+    np.testing.assert_allclose(oracle.back_tof_lm(xs, xe, origin, vs, dim, tof, bins, ylm).ravel(),
+                               Alm.T @ ylm, rtol=1e-11, atol=1e-12)
+
+
+def test_count_samples_bruteforce():
+    """The work counter: planes on the segment whose 2x2 stencil has a neighbour in the grid."""
+    dim, vs, origin = GRIDS[0]
+    rng = np.random.default_rng(7)
+    xs, xe = random_rays(rng, 50, origin, vs, dim, inside_frac=0.2)
+    tot, per = oracle.count_samples(xs, xe, origin, vs, dim, per_ray=True)
+    for l in range(xs.shape[0]):
+        d32 = (xe[l] - xs[l]).astype(np.float32)
+        p = int(np.argmax(np.abs(d32)))
+        inplane = [a for a in range(3) if a != p]
+        cnt = 0
+        for k in range(dim[p]):
+            t = (origin[p] + k * vs[p] - float(xs[l, p])) / (float(xe[l, p]) - float(xs[l, p]))
+            if t < 0 or t > 1:
+                continue
+            X = xs[l].astype(float) + t * (xe[l].astype(float) - xs[l].astype(float))
+            idx = [(X[a] - origin[a]) / vs[a] for a in inplane]
+            ok = all(math.floor(i) + 1 >= 0 and math.floor(i) <= dim[a] - 1 for i, a in zip(idx, inplane))
+            cnt += ok
+        assert per[l] == cnt
+    assert tot == per.sum()
+
+
+# ---------------------------------------------------------------- invariants
+
+def test_adjoint_identity_all_variants():
+    """Pin 4: <A x, y> == <x, A^T y> in fp64 for the three variants."""
+    rng = np.random.default_rng(3)
+    dim, vs, origin = (12, 10, 6), (2.0, 2.0, 3.0), (-11.0, -9.0, -7.5)
+    xs, xe = random_rays(rng, 400, origin, vs, dim, inside_frac=0.1)
+    tof = tofd(6.0, 5.0, 3.0, 11)
+    x = rng.uniform(size=dim)
+    y = rng.uniform(size=xs.shape[0])
+    ys = rng.uniform(size=(xs.shape[0], 11))
+    bins = rng.integers(0, 11, size=xs.shape[0]).astype(np.int16)
+    pairs = [
+        (oracle.fwd(xs, xe, origin, vs, dim, x), y, oracle.back(xs, xe, origin, vs, dim, y)),
+        (oracle.fwd_tof_sino(xs, xe, origin, vs, dim, tof, x), ys, oracle.back_tof_sino(xs, xe, origin, vs, dim, tof, ys)),
+        (oracle.fwd_tof_lm(xs, xe, origin, vs, dim, tof, bins, x), y,
+         oracle.back_tof_lm(xs, xe, origin, vs, dim, tof, bins, y)),
+    ]
+    for Ax, yy, ATy in pairs:
+        lhs = float(np.sum(Ax * yy))
+        rhs = float(np.sum(x * ATy))
+        assert lhs == pytest.approx(rhs, rel=1e-12)
+        assert lhs > 0
+
+
+def test_tof_bin_sum_reproduces_nontof():
+    """Pin 5: for a LOR whose samples all lie well inside the TOF bin range, the TOF weights
+    telescope: sum_t p_t = erf(n_sigmas / sqrt(2)) * p_nonTOF (not renormalised truncation).
+    With n_sigmas = 8 the factor is 1 - 1.2e-15."""
+    rng = np.random.default_rng(4)
+    dim, vs, origin = (20, 18, 8), (2.0, 2.0, 2.0), (-19.0, -17.0, -7.0)
+    xs, xe = random_rays(rng, 50, origin, vs, dim)
+    x = rng.uniform(size=dim)
+    pn = oracle.fwd(xs, xe, origin, vs, dim, x)
+    for nsig, factor in ((3.0, special.erf(3.0 / math.sqrt(2.0))), (8.0, 1.0)):
+        tof = tofd(4.0, 3.0, nsig, 41)  # bins cover +-82 mm, samples lie within ~40 mm
+        pt = oracle.fwd_tof_sino(xs, xe, origin, vs, dim, tof, x)
+        factor = special.erf(f32(nsig) * f32(3.0) / (math.sqrt(2.0) * f32(3.0)))
+        np.testing.assert_allclose(pt.sum(1), factor * pn, rtol=1e-13, atol=1e-13)
+    with open(os.path.join(GOLDEN, "closed_forms.json")) as fh:
+        gold = json.load(fh)
+    assert special.erf(3.0 / math.sqrt(2.0)) == pytest.approx(gold["tof_mass_3sigma"]["value"], rel=1e-15)
+
+
+def test_single_voxel_textbook_tof_weight():
+    """Pin 6: one hot voxel on an axis-aligned ray through its centre gives
+    p_t = ell * w_t(s) with w_t the Gaussian-cdf difference over the bin (scipy's normal cdf),
+    for bins where the truncation does not bite.  Catches a wrong TOF coordinate origin or sign."""
+    dim, vs, origin = (21, 3, 3), (2.0, 2.0, 2.0), (-20.0, -2.0, -2.0)
+    img = np.zeros(dim)
+    img[15, 1, 1] = 1.0  # centre at x = +10 mm
+    xs = np.array([[-60.0, 0.0, 0.0]], np.float32)
+    xe = np.array([[40.0, 0.0, 0.0]], np.float32)  # midpoint x = -10, so s = +20 mm
+    tof = tofd(5.0, 4.0, 6.0, 15)
+    pt = oracle.fwd_tof_sino(xs, xe, origin, vs, dim, tof, img)[0]
+    s = 20.0
+    for t in range(15):
+        c = (t - 7) * 5.0
+        if abs(s - c) + 2.5 < 6.0 * 4.0 - 1e-9:
+            expect = 2.0 * (stats.norm.cdf((s - c + 2.5) / 4.0) - stats.norm.cdf((s - c - 2.5) / 4.0))
+            assert pt[t] == pytest.approx(expect, rel=1e-12, abs=1e-15)
+    # integral of the kernel over s equals bin width * truncated mass (pin of the convolution)
+    grid = np.linspace(-40, 40, 8001)
+    w = np.array([tof_weight_quadrature(si, 0.0, 5.0, 4.0, 3.0) for si in grid])
+    assert np.trapezoid(w, grid) == pytest.approx(5.0 * special.erf(3.0 / math.sqrt(2)), rel=1e-6)
+
+
+def test_listmode_equals_sinogram_bin():
+    """Pin 7: TOF listmode projection of bin t is bit-identical to column t of the sinogram
+    projection, and listmode back projection to the sinogram back projection of that column."""
+    rng = np.random.default_rng(8)
+    dim, vs, origin = (10, 9, 5), (2.0, 2.0, 2.0), (-9.0, -8.0, -4.0)
+    xs, xe = random_rays(rng, 80, origin, vs, dim)
+    tof = tofd(3.0, 2.5, 3.0, 13)
+    x = rng.uniform(size=dim)
+    sino = oracle.fwd_tof_sino(xs, xe, origin, vs, dim, tof, x)
+    y = rng.uniform(size=xs.shape[0])
+    for t in (0, 5, 12):
+        bins = np.full(xs.shape[0], t, np.int16)
+        assert np.array_equal(oracle.fwd_tof_lm(xs, xe, origin, vs, dim, tof, bins, x), sino[:, t])
+        ys = np.zeros((xs.shape[0], 13))
+        ys[:, t] = y
+        np.testing.assert_allclose(oracle.back_tof_lm(xs, xe, origin, vs, dim, tof, bins, y),
+                                   oracle.back_tof_sino(xs, xe, origin, vs, dim, tof, ys), rtol=1e-15, atol=0)
+    # out-of-range listmode bins contribute nothing
+    bad = np.array([-1, 13, 200, -32768] * 20, np.int16)[: xs.shape[0]]
+    assert not np.any(oracle.fwd_tof_lm(xs, xe, origin, vs, dim, tof, bad, x))
+
+
+def test_symmetries():
+    """Pin 8: swapping start/end leaves non-TOF unchanged and mirrors TOF bins (offset 0);
+    a joint translation of rays and grid, and a joint permutation of coordinate and image axes,
+    leave every variant unchanged."""
+    rng = np.random.default_rng(9)
+    dim, vs, origin = (11, 9, 7), (2.0, 1.5, 2.5), (-10.0, -6.0, -7.5)
+    # coordinates on a 1/64 mm lattice so that the translated inputs stay exact in float32
+    xs, xe = random_rays(rng, 120, origin, vs, dim, grid_step=1.0 / 64)
+    tof = tofd(3.0, 2.0, 3.0, 15)
+    x = rng.uniform(size=dim)
+    p = oracle.fwd(xs, xe, origin, vs, dim, x)
+    np.testing.assert_allclose(oracle.fwd(xe, xs, origin, vs, dim, x), p, rtol=1e-13)
+    pt = oracle.fwd_tof_sino(xs, xe, origin, vs, dim, tof, x)
+    np.testing.assert_allclose(oracle.fwd_tof_sino(xe, xs, origin, vs, dim, tof, x), pt[:, ::-1], rtol=1e-12,
+                               atol=1e-14)
+    shift = np.array([37.0, -12.0, 5.0], np.float32)
+    o2 = tuple(np.asarray(origin) + shift)
+    np.testing.assert_allclose(oracle.fwd(xs + shift, xe + shift, o2, vs, dim, x), p, rtol=1e-12)
+    np.testing.assert_allclose(oracle.fwd_tof_sino(xs + shift, xe + shift, o2, vs, dim, tof, x), pt, rtol=1e-11,
+                               atol=1e-13)
+    perm = (2, 0, 1)
+    xsP, xeP = xs[:, perm].copy(), xe[:, perm].copy()
+    dimP = tuple(dim[a] for a in perm)
+    vsP = tuple(vs[a] for a in perm)
+    oP = tuple(origin[a] for a in perm)
+    xP = np.ascontiguousarray(np.transpose(x, perm))
+    np.testing.assert_allclose(oracle.fwd(xsP, xeP, oP, vsP, dimP, xP), p, rtol=1e-12)
+    np.testing.assert_allclose(oracle.fwd_tof_sino(xsP, xeP, oP, vsP, dimP, tof, xP), pt, rtol=1e-11, atol=1e-13)
+    y = rng.uniform(size=xs.shape[0])
+    bP = oracle.back(xsP, xeP, oP, vsP, dimP, y)
+    np.testing.assert_allclose(np.transpose(bP, np.argsort(perm)), oracle.back(xs, xe, origin, vs, dim, y),
+                               rtol=1e-12, atol=1e-14)
+
+
+def test_degenerate_rays():
+    """Zero-length and non-finite rays contribute nothing; a ray missing the grid gives 0."""
+    dim, vs, origin = (4, 4, 4), (1.0, 1.0, 1.0), (-1.5, -1.5, -1.5)
+    x = np.ones(dim)
+    xs = np.array([[1, 1, 1], [np.nan, 0, 0], [-50, 30, 0], [0, 0, np.inf]], np.float32)
+    xe = np.array([[1, 1, 1], [5, 0, 0], [50, 30, 0], [0, 0, 5]], np.float32)
+    assert not np.any(oracle.fwd(xs, xe, origin, vs, dim, x))
+    assert not np.any(oracle.back(xs, xe, origin, vs, dim, np.ones(4)))
+    assert oracle.fwd(xs[:0], xe[:0], origin, vs, dim, x).shape == (0,)
+
+
+# ---------------------------------------------------------------------- OSEM
+
+def _osem_problem(seed=12, n_ev=300):
+    rng = np.random.default_rng(seed)
+    dim, vs, origin = (6, 5, 4), (2.0, 2.0, 2.0), (-5.0, -4.0, -3.0)
+    xs, xe = random_rays(rng, n_ev, origin, vs, dim)
+    tof = tofd(3.0, 2.5, 3.0, 9)
+    bins = rng.integers(2, 7, size=n_ev).astype(np.int16)
+    # sensitivity from a separate "scanner" ray set
+    ss, se = random_rays(np.random.default_rng(seed + 1), 2000, origin, vs, dim)
+    sens = oracle.back(ss, se, origin, vs, dim, np.ones(ss.shape[0]))
+    return xs, xe, bins, dim, vs, origin, tof, sens
+
+
+def test_osem_matches_dense_algebra():
+    """The OSEM oracle equals the same update written with the brute-force matrix and numpy
+    algebra: x <- x * A_j^T (1 / (A_j x + bg)) / (sens / n_sub), zero where sens == 0."""
+    xs, xe, bins, dim, vs, origin, tof, sens = _osem_problem()
+    sens = sens.copy()
+    sens.ravel()[::7] = 0.0  # some voxels without sensitivity
+    A = system_matrix(xs, xe, origin, vs, dim, tof=tof, mode="lm", bins=bins)
+    bg, n_iter, n_sub = 0.1, 2, 3
+    x = (sens > 0).astype(float).ravel()
+    s = sens.ravel()
+    for _ in range(n_iter):
+        for j in range(n_sub):
+            Aj = A[j::n_sub]
+            ybar = Aj @ x + bg
+            acc = Aj.T @ (1.0 / ybar)
+            x = np.where(s > 0, x * acc / np.where(s > 0, s / n_sub, 1.0), 0.0)
+    got = oracle.lm_osem(xs, xe, bins, origin, vs, dim, tof, sens, bg, n_iter, n_sub, (sens > 0).astype(float))
+    np.testing.assert_allclose(got.ravel(), x, rtol=1e-11, atol=1e-14)
+    assert np.all(got >= 0) and np.all(got.ravel()[s == 0] == 0)
+
+
+def test_osem_count_conservation():
+    """Pin 10: with zero background, one EM update satisfies sum_v sens_v x_v^new = number of
+    events with positive expectation a_e . x (exact invariant of the multiplicative update),
+    for a flat and for a random positive starting image."""
+    xs, xe, bins, dim, vs, origin, tof, sens = _osem_problem(seed=21, n_ev=400)
+    rng = np.random.default_rng(22)
+    for x0 in ((sens > 0).astype(float), rng.uniform(0.5, 2.0, size=dim) * (sens > 0)):
+        one = oracle.lm_osem(xs, xe, bins, origin, vs, dim, tof, sens, 0.0, 1, 1, x0)
+        ybar = oracle.fwd_tof_lm(xs, xe, origin, vs, dim, tof, bins, x0)
+        n_pos = int(np.count_nonzero(ybar > 0))
+        assert n_pos > 300
+        assert float(np.sum(sens * one)) == pytest.approx(n_pos, rel=1e-12)
