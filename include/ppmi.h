@@ -1,0 +1,177 @@
+/*
+ * ppmi.h -- C ABI of libppmi.so: Joseph ray-driven forward and back
+ * projection (non-TOF, TOF sinogram, TOF listmode) and a batched, fused
+ * listmode-OSEM subset update, as hand-written HIP kernels for gfx950.
+ *
+ * The operations are those of Schramm & Thielemans, "PARALLELPROJ - An
+ * open-source framework for fast calculation of projections in tomography"
+ * (arXiv 2212.12519):
+ *   - Sec. 2.1 and Fig. 1: Joseph's method -- step plane by plane along the
+ *     image axis most parallel to the ray, bilinearly interpolate the four
+ *     voxels around each ray/plane intersection, sum, and correct for the
+ *     incidence angle; TOF weights from a Gaussian convolved with the bin
+ *     rect (a difference of two error functions) evaluated at the distance
+ *     to the TOF-bin centre;
+ *   - Sec. 2.2: generic lists of ray start/end points as input; TOF
+ *     sinogram projections fill every bin of a ray in one traversal, TOF
+ *     listmode projections only the event's bin; back projections are the
+ *     exact adjoints and scatter with atomic adds;
+ *   - Sec. 2.6: the TOF Gaussian is truncated beyond +-n_sigmas sigma (3 in
+ *     the paper); listmode OSEM with ordered subsets.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *   Coordinates: float32, array of structures [n][3] = (x, y, z) in mm.
+ *   Image: float32, C order [dim[0]][dim[1]][dim[2]] (axis 2 fastest); the
+ *     centre of voxel (i, j, k) is origin + (i, j, k) * voxsize.  Voxels
+ *     outside the grid read as zero.  dim[0]*dim[1]*dim[2] < 2^31.
+ *   Principal axis: argmax_a |end_a - start_a| in mm (float32 differences,
+ *     first axis on ties).  The ray is the segment start -> end: plane k is
+ *     visited iff its ray parameter t in [0, 1].
+ *   TOF: a plane sample at ray parameter t sits at s = (t - 1/2) |end - start|
+ *     mm from the LOR midpoint (positive towards `end`).  Bin b has centre
+ *     c_b = (b - (n_bins - 1)/2) * bin_width + center_offset and weight
+ *       w_b(s) = G(s - c_b + bin_width/2) - G(s - c_b - bin_width/2),
+ *       G(x)   = erf(clip(x, -n_sigmas*sigma, n_sigmas*sigma) / (sqrt(2) sigma)) / 2
+ *     (the Gaussian is truncated before the convolution; no renormalisation).
+ *   Pointers: every array argument is a DEVICE pointer owned by the caller;
+ *     the geometry / TOF structs are HOST pointers read during the call.
+ *     The library allocates nothing and keeps no state between calls.
+ *   Streams: `stream` is a hipStream_t (NULL = the default stream).  Calls
+ *     are asynchronous: they enqueue kernels and return.  Calls on different
+ *     streams are independent.  Every call may be captured into a HIP graph.
+ *   Forward projections overwrite their output.  Back projections ADD into
+ *     the image (the caller zeroes it), which allows chunked / subset calls.
+ *     Their result depends on the order of floating-point atomic adds.
+ *   Zero-length or non-finite rays, and listmode bins outside [0, n_bins),
+ *     contribute nothing (no error: they are data).  n == 0 is a no-op.
+ *
+ * Errors: every function returns PP_OK (0) or a PP_E* code; nothing is
+ *   launched when an argument check fails.  PP_EHIP reports a failed launch;
+ *   faults during kernel execution surface at the caller's next
+ *   synchronisation.  pp_strerror() describes a code.
+ */
+#ifndef PPMI_H
+#define PPMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PP_ABI_VERSION 1
+
+enum pp_status {
+    PP_OK = 0,
+    PP_EINVAL_PTR = 1,  /* a required pointer is NULL */
+    PP_EINVAL_GEOM = 2, /* dim <= 0, voxel count >= 2^31, voxsize <= 0 or non-finite, origin non-finite */
+    PP_EINVAL_TOF = 3,  /* n_bins not in [1, 256], bin_width/sigma/n_sigmas <= 0 or non-finite */
+    PP_EINVAL_N = 4,    /* negative count, or a count/slot argument out of range */
+    PP_EHIP = 5         /* the HIP runtime rejected a launch */
+};
+
+typedef struct pp_image {
+    float origin[3];  /* mm: centre of voxel (0, 0, 0) */
+    float voxsize[3]; /* mm, > 0 (non-isotropic allowed) */
+    int32_t dim[3];   /* voxels per axis, > 0 */
+} pp_image_t;
+
+typedef struct pp_tof {
+    float bin_width;     /* mm, > 0 */
+    float sigma;         /* mm, > 0 (FWHM / 2.355) */
+    float n_sigmas;      /* truncation in sigmas, > 0 */
+    float center_offset; /* mm, shift of every bin centre along the LOR */
+    int32_t n_bins;      /* 1 .. 256 */
+} pp_tof_t;
+
+/* Non-TOF forward projection (Sec. 2.1, Fig. 1).
+ * p[l] = ell_l * sum_k bilinear(img, plane k of ray l), l in [0, n_lors).
+ * xstart, xend: [n_lors][3]; img: [dim0][dim1][dim2]; p: [n_lors] (overwritten). */
+int pp_fwd(const float* xstart, const float* xend, int64_t n_lors, const pp_image_t* geom, const float* img,
+           float* p, void* stream);
+
+/* Non-TOF back projection, the exact adjoint of pp_fwd (Sec. 2.2): img += A^T p. */
+int pp_back(const float* xstart, const float* xend, int64_t n_lors, const pp_image_t* geom, float* img,
+            const float* p, void* stream);
+
+/* TOF sinogram forward projection (Sec. 2.1, 2.2): all n_bins of every ray in
+ * one traversal.  p: [n_lors][n_bins] (bin fastest), overwritten. */
+int pp_fwd_tof_sino(const float* xstart, const float* xend, int64_t n_lors, const pp_image_t* geom,
+                    const pp_tof_t* tof, const float* img, float* p, void* stream);
+
+/* TOF sinogram back projection, adjoint of pp_fwd_tof_sino: img += A^T p, p: [n_lors][n_bins]. */
+int pp_back_tof_sino(const float* xstart, const float* xend, int64_t n_lors, const pp_image_t* geom,
+                     const pp_tof_t* tof, float* img, const float* p, void* stream);
+
+/* TOF listmode forward projection (Sec. 2.2): only bin tof_bin[e] of event e.
+ * Only the planes within n_sigmas*sigma + bin_width/2 of the bin centre are
+ * visited (the weight is exactly zero elsewhere).  tof_bin: int16 [n_events];
+ * p: [n_events], overwritten (0 for out-of-range bins). */
+int pp_fwd_tof_lm(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n_events,
+                  const pp_image_t* geom, const pp_tof_t* tof, const float* img, float* p, void* stream);
+
+/* TOF listmode back projection, adjoint of pp_fwd_tof_lm: img += A^T p. */
+int pp_back_tof_lm(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n_events,
+                   const pp_image_t* geom, const pp_tof_t* tof, float* img, const float* p, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batched listmode TOF OSEM (the paper's listmode OSEM of Sec. 2.6, run for
+ * many short frames at once).  One "step" of a frame is one ordered-subset
+ * update with subset j = {events e : e mod n_sub == j}:
+ *     acc  = sum_{e in subset j} a_e / (a_e . x + bg)      (pp_lm_osem_accumulate)
+ *     x_v <- x_v * acc_v / (sens_v / n_sub) if sens_v > 0, else 0;  acc <- 0
+ *                                                           (pp_lm_osem_update)
+ * An event whose expectation a_e . x + bg is not positive contributes nothing.
+ * The slot table lives in DEVICE memory and is read by the kernels at run
+ * time, so one captured graph of steps serves any mix of frames: the host
+ * rewrites slots between replays.  pp_lm_osem_update advances `subset`
+ * ((subset + 1) mod n_sub) and decrements `steps_left` of every slot it
+ * updates; slots with active == 0 or steps_left <= 0 are skipped by both
+ * calls.  All frames of one call share the image grid and TOF parameters.
+ * Each frame owns its x, acc (zero before its first step) and events, so a
+ * frame's result does not depend on the other frames of the batch (up to
+ * the order of atomic adds).
+ * ------------------------------------------------------------------------ */
+typedef struct pp_osem_slot {
+    const float* xstart;     /* [n_events][3] */
+    const float* xend;       /* [n_events][3] */
+    const int16_t* tof_bin;  /* [n_events] */
+    float* x;                /* [n_vox] current image, updated in place */
+    float* acc;              /* [n_vox] accumulator, zero between steps */
+    const float* sens;       /* [n_vox] sensitivity image */
+    int64_t n_events;
+    int64_t chunk_begin;     /* first work chunk of this slot (pp_osem_chunks prefix sum) */
+    float bg;                /* additive expectation per event (contamination) */
+    int32_t n_sub;           /* subsets of this frame, >= 1 */
+    int32_t subset;          /* subset of the next step, in [0, n_sub) */
+    int32_t steps_left;      /* steps still to run; 0 = finished */
+    int32_t active;          /* 0 = empty slot */
+    int32_t reserved;
+} pp_osem_slot_t;
+
+/* Work chunks a slot needs per step (events of the largest subset / 256,
+ * rounded up).  The host sets chunk_begin of slot s to the sum over slots
+ * r < s of pp_osem_chunks(n_events_r, n_sub_r) (0 for inactive slots). */
+int64_t pp_osem_chunks(int64_t n_events, int32_t n_sub);
+
+/* Fused forward -> 1/(ybar) -> back projection of the current subset of
+ * every live slot into its acc.  d_slots: DEVICE array of n_slots entries. */
+int pp_lm_osem_accumulate(const pp_osem_slot_t* d_slots, int32_t n_slots, const pp_image_t* geom,
+                          const pp_tof_t* tof, void* stream);
+
+/* Multiplicative image update of every live slot, then acc <- 0, subset
+ * advanced, steps_left decremented.  n_vox must equal the grid's voxel count. */
+int pp_lm_osem_update(pp_osem_slot_t* d_slots, int32_t n_slots, int64_t n_vox, void* stream);
+
+/* Sets n floats at dst to value (a kernel, safe inside captured graphs). */
+int pp_fill(float* dst, int64_t n, float value, void* stream);
+
+const char* pp_strerror(int code);
+int pp_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PPMI_H */

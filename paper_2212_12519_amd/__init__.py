@@ -1,0 +1,16 @@
+"""MI355X-native Joseph projector (non-TOF, TOF sinogram, TOF listmode) and
+batched listmode OSEM, after Schramm & Thielemans, arXiv 2212.12519.
+
+The compute path is libppmi.so (hand-written HIP for gfx950, C ABI in
+include/ppmi.h); this package is its Python binding plus the autograd
+wrappers and the OSEM serving loop built on it.
+"""
+from ._lib import ImageGeom, PPError, TofParams, load
+from .projectors import (back, back_tof_lm, back_tof_sino, fwd, fwd_tof_lm, fwd_tof_sino, pp_back,
+                         pp_back_tof_lm, pp_back_tof_sino, pp_fill, pp_fwd, pp_fwd_tof_lm, pp_fwd_tof_sino)
+
+__all__ = [
+    "ImageGeom", "TofParams", "PPError", "load",
+    "pp_fwd", "pp_back", "pp_fwd_tof_sino", "pp_back_tof_sino", "pp_fwd_tof_lm", "pp_back_tof_lm", "pp_fill",
+    "fwd", "back", "fwd_tof_sino", "back_tof_sino", "fwd_tof_lm", "back_tof_lm",
+]

@@ -1,0 +1,177 @@
+"""ctypes binding of libppmi.so (declared in include/ppmi.h).
+
+Argument marshalling only: torch tensors are checked (device, dtype, shape,
+contiguity) and passed as raw device pointers together with torch's current
+HIP stream.  Every computation happens in the library's HIP kernels; there is
+no CPU fallback -- if the library is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libppmi.so")
+_lib = None
+
+PP_OK, PP_EINVAL_PTR, PP_EINVAL_GEOM, PP_EINVAL_TOF, PP_EINVAL_N, PP_EHIP = range(6)
+
+
+class PPError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ppmi error {code}: {msg}")
+        self.code = code
+
+
+class CImage(ctypes.Structure):
+    _fields_ = [("origin", ctypes.c_float * 3), ("voxsize", ctypes.c_float * 3), ("dim", ctypes.c_int32 * 3)]
+
+
+class CTof(ctypes.Structure):
+    _fields_ = [("bin_width", ctypes.c_float), ("sigma", ctypes.c_float), ("n_sigmas", ctypes.c_float),
+                ("center_offset", ctypes.c_float), ("n_bins", ctypes.c_int32)]
+
+
+class COsemSlot(ctypes.Structure):
+    _fields_ = [("xstart", ctypes.c_void_p), ("xend", ctypes.c_void_p), ("tof_bin", ctypes.c_void_p),
+                ("x", ctypes.c_void_p), ("acc", ctypes.c_void_p), ("sens", ctypes.c_void_p),
+                ("n_events", ctypes.c_int64), ("chunk_begin", ctypes.c_int64), ("bg", ctypes.c_float),
+                ("n_sub", ctypes.c_int32), ("subset", ctypes.c_int32), ("steps_left", ctypes.c_int32),
+                ("active", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+assert ctypes.sizeof(COsemSlot) == 88, ctypes.sizeof(COsemSlot)
+
+
+@dataclass(frozen=True)
+class ImageGeom:
+    """dim (n0, n1, n2), voxsize mm, origin = centre of voxel (0,0,0) in mm (default: centred grid)."""
+    dim: tuple
+    voxsize: tuple
+    origin: tuple = None
+
+    def __post_init__(self):
+        object.__setattr__(self, "dim", tuple(int(v) for v in self.dim))
+        object.__setattr__(self, "voxsize", tuple(float(v) for v in self.voxsize))
+        if self.origin is None:
+            object.__setattr__(self, "origin", tuple(-(n - 1) / 2.0 * h for n, h in zip(self.dim, self.voxsize)))
+        else:
+            object.__setattr__(self, "origin", tuple(float(v) for v in self.origin))
+
+    @property
+    def n_vox(self):
+        return self.dim[0] * self.dim[1] * self.dim[2]
+
+    def c(self):
+        return CImage((ctypes.c_float * 3)(*self.origin), (ctypes.c_float * 3)(*self.voxsize),
+                      (ctypes.c_int32 * 3)(*self.dim))
+
+
+@dataclass(frozen=True)
+class TofParams:
+    bin_width: float
+    sigma: float
+    n_sigmas: float
+    n_bins: int
+    center_offset: float = 0.0
+
+    def c(self):
+        return CTof(self.bin_width, self.sigma, self.n_sigmas, self.center_offset, int(self.n_bins))
+
+
+def as_geom(g) -> ImageGeom:
+    if isinstance(g, ImageGeom):
+        return g
+    return ImageGeom(tuple(g.dim), tuple(g.voxsize), tuple(g.origin))
+
+
+def as_tof(t) -> TofParams:
+    if isinstance(t, TofParams):
+        return t
+    return TofParams(float(t.bin_width), float(t.sigma), float(t.n_sigmas), int(t.n_bins),
+                     float(getattr(t, "center_offset", 0.0)))
+
+
+def load():
+    """Load libppmi.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2212_12519_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I64, I32, INT = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int
+    G = ctypes.POINTER(CImage)
+    T = ctypes.POINTER(CTof)
+    sig = {
+        "pp_fwd": [P, P, I64, G, P, P, P],
+        "pp_back": [P, P, I64, G, P, P, P],
+        "pp_fwd_tof_sino": [P, P, I64, G, T, P, P, P],
+        "pp_back_tof_sino": [P, P, I64, G, T, P, P, P],
+        "pp_fwd_tof_lm": [P, P, P, I64, G, T, P, P, P],
+        "pp_back_tof_lm": [P, P, P, I64, G, T, P, P, P],
+        "pp_lm_osem_accumulate": [P, I32, G, T, P],
+        "pp_lm_osem_update": [P, I32, I64, P],
+        "pp_fill": [P, I64, ctypes.c_float, P],
+    }
+    for name, argt in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = argt
+        f.restype = INT
+    lib.pp_osem_chunks.argtypes = [I64, I32]
+    lib.pp_osem_chunks.restype = I64
+    lib.pp_strerror.argtypes = [INT]
+    lib.pp_strerror.restype = ctypes.c_char_p
+    lib.pp_abi_version.restype = INT
+    _lib = lib
+    return lib
+
+
+def check(code):
+    if code != PP_OK:
+        raise PPError(code, load().pp_strerror(code).decode())
+
+
+def stream_of(t: torch.Tensor):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _dev(*ts):
+    dev = None
+    for t in ts:
+        if t is None:
+            continue
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+            raise TypeError("libppmi takes GPU tensors only")
+        if not t.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+        if dev is None:
+            dev = t.device
+        elif t.device != dev:
+            raise ValueError("tensors on different devices")
+    return dev
+
+
+def _rays(xstart, xend):
+    if xstart.dtype != torch.float32 or xend.dtype != torch.float32:
+        raise TypeError("ray endpoints must be float32")
+    if xstart.dim() != 2 or xstart.shape[1] != 3 or xend.shape != xstart.shape:
+        raise ValueError("ray endpoints must be [n, 3] each")
+    return xstart.shape[0]
+
+
+def _img(img, geom):
+    if img.dtype != torch.float32 or img.numel() != geom.n_vox:
+        raise ValueError(f"image must be float32 with {geom.n_vox} voxels")
+
+
+def _bins(bins, n):
+    if bins.dtype != torch.int16 or bins.numel() != n:
+        raise ValueError("tof_bin must be int16 [n]")

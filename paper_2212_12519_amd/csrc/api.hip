@@ -1,0 +1,200 @@
+// C ABI of libppmi.so: argument checks, kernel-side geometry, dispatch.
+// The declarations, conventions and error codes are documented in ppmi.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+
+#include "joseph.hpp"
+#include "launch.hpp"
+
+using namespace ppmi;
+
+namespace {
+
+thread_local char g_hip_msg[256] = "";
+
+int hip_status(hipError_t e) {
+    if (e == hipSuccess) return PP_OK;
+    std::snprintf(g_hip_msg, sizeof g_hip_msg, "HIP error %d: %s", (int)e, hipGetErrorString(e));
+    return PP_EHIP;
+}
+
+bool finite3(const float* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+int make_geom(const pp_image_t* gi, GeomK& g) {
+    if (!gi) return PP_EINVAL_PTR;
+    if (!finite3(gi->origin) || !finite3(gi->voxsize)) return PP_EINVAL_GEOM;
+    int64_t nv = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (gi->dim[a] <= 0 || !(gi->voxsize[a] > 0.0f)) return PP_EINVAL_GEOM;
+        nv *= gi->dim[a];
+        if (nv > (int64_t(1) << 30)) return PP_EINVAL_GEOM;
+    }
+    for (int a = 0; a < 3; ++a) {
+        g.o[a] = gi->origin[a];
+        g.h[a] = gi->voxsize[a];
+        g.n[a] = gi->dim[a];
+    }
+    g.stride[2] = 1;
+    g.stride[1] = gi->dim[2];
+    g.stride[0] = gi->dim[1] * gi->dim[2];
+    return PP_OK;
+}
+
+int make_tof(const pp_tof_t* ti, TofK& t) {
+    if (!ti) return PP_EINVAL_PTR;
+    if (ti->n_bins < 1 || ti->n_bins > 256) return PP_EINVAL_TOF;
+    if (!std::isfinite(ti->bin_width) || !(ti->bin_width > 0.0f) || !std::isfinite(ti->sigma) ||
+        !(ti->sigma > 0.0f) || !std::isfinite(ti->n_sigmas) || !(ti->n_sigmas > 0.0f) ||
+        !std::isfinite(ti->center_offset))
+        return PP_EINVAL_TOF;
+    const double bw = ti->bin_width, sig = ti->sigma, ns = ti->n_sigmas;
+    t.bw = bw;
+    t.c0 = -0.5 * (double)(ti->n_bins - 1) * bw + (double)ti->center_offset;
+    t.trunc = (float)(ns * sig);
+    t.win = ns * sig + 0.5 * bw;
+    t.inv_sqrt2_sig = (float)(1.0 / (std::sqrt(2.0) * sig));
+    t.nb = ti->n_bins;
+    return PP_OK;
+}
+
+// grid limit: 2^31 - 1 workgroups of 64..256 threads
+constexpr int64_t kMaxRays = (int64_t(1) << 31) * 64 - 64;
+
+int check_n(int64_t n) { return (n < 0 || n > kMaxRays) ? PP_EINVAL_N : PP_OK; }
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+int device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 256;
+    return cus;
+}
+
+}  // namespace
+
+#define PP_TRY(expr)                   \
+    do {                               \
+        int _rc = (expr);              \
+        if (_rc != PP_OK) return _rc;  \
+    } while (0)
+
+extern "C" {
+
+int pp_abi_version(void) { return PP_ABI_VERSION; }
+
+const char* pp_strerror(int code) {
+    switch (code) {
+        case PP_OK: return "ok";
+        case PP_EINVAL_PTR: return "a required pointer is NULL";
+        case PP_EINVAL_GEOM: return "invalid image geometry (dim <= 0, >= 2^30 voxels, voxsize <= 0 or non-finite)";
+        case PP_EINVAL_TOF: return "invalid TOF parameters (n_bins not in [1,256], or width/sigma/n_sigmas <= 0)";
+        case PP_EINVAL_N: return "count or slot argument out of range";
+        case PP_EHIP: return g_hip_msg[0] ? g_hip_msg : "HIP launch error";
+        default: return "unknown status code";
+    }
+}
+
+int pp_fwd(const float* xstart, const float* xend, int64_t n, const pp_image_t* geom, const float* img, float* p,
+           void* stream) {
+    GeomK g;
+    PP_TRY(make_geom(geom, g));
+    PP_TRY(check_n(n));
+    if (n == 0) return PP_OK;
+    if (!xstart || !xend || !img || !p) return PP_EINVAL_PTR;
+    return hip_status(launch_fwd(xstart, xend, n, g, img, p, as_stream(stream)));
+}
+
+int pp_back(const float* xstart, const float* xend, int64_t n, const pp_image_t* geom, float* img, const float* p,
+            void* stream) {
+    GeomK g;
+    PP_TRY(make_geom(geom, g));
+    PP_TRY(check_n(n));
+    if (n == 0) return PP_OK;
+    if (!xstart || !xend || !img || !p) return PP_EINVAL_PTR;
+    return hip_status(launch_back(xstart, xend, n, g, img, p, as_stream(stream)));
+}
+
+int pp_fwd_tof_sino(const float* xstart, const float* xend, int64_t n, const pp_image_t* geom, const pp_tof_t* tof,
+                    const float* img, float* p, void* stream) {
+    GeomK g;
+    TofK t;
+    PP_TRY(make_geom(geom, g));
+    PP_TRY(make_tof(tof, t));
+    PP_TRY(check_n(n));
+    if (n == 0) return PP_OK;
+    if (!xstart || !xend || !img || !p) return PP_EINVAL_PTR;
+    return hip_status(launch_fwd_tof_sino(xstart, xend, n, g, t, img, p, as_stream(stream)));
+}
+
+int pp_back_tof_sino(const float* xstart, const float* xend, int64_t n, const pp_image_t* geom, const pp_tof_t* tof,
+                     float* img, const float* p, void* stream) {
+    GeomK g;
+    TofK t;
+    PP_TRY(make_geom(geom, g));
+    PP_TRY(make_tof(tof, t));
+    PP_TRY(check_n(n));
+    if (n == 0) return PP_OK;
+    if (!xstart || !xend || !img || !p) return PP_EINVAL_PTR;
+    return hip_status(launch_back_tof_sino(xstart, xend, n, g, t, img, p, as_stream(stream)));
+}
+
+int pp_fwd_tof_lm(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n, const pp_image_t* geom,
+                  const pp_tof_t* tof, const float* img, float* p, void* stream) {
+    GeomK g;
+    TofK t;
+    PP_TRY(make_geom(geom, g));
+    PP_TRY(make_tof(tof, t));
+    PP_TRY(check_n(n));
+    if (n == 0) return PP_OK;
+    if (!xstart || !xend || !tof_bin || !img || !p) return PP_EINVAL_PTR;
+    return hip_status(launch_fwd_tof_lm(xstart, xend, tof_bin, n, g, t, img, p, as_stream(stream)));
+}
+
+int pp_back_tof_lm(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n, const pp_image_t* geom,
+                   const pp_tof_t* tof, float* img, const float* p, void* stream) {
+    GeomK g;
+    TofK t;
+    PP_TRY(make_geom(geom, g));
+    PP_TRY(make_tof(tof, t));
+    PP_TRY(check_n(n));
+    if (n == 0) return PP_OK;
+    if (!xstart || !xend || !tof_bin || !img || !p) return PP_EINVAL_PTR;
+    return hip_status(launch_back_tof_lm(xstart, xend, tof_bin, n, g, t, img, p, as_stream(stream)));
+}
+
+int64_t pp_osem_chunks(int64_t n_events, int32_t n_sub) { return osem_chunks(n_events, n_sub); }
+
+int pp_lm_osem_accumulate(const pp_osem_slot_t* d_slots, int32_t n_slots, const pp_image_t* geom,
+                          const pp_tof_t* tof, void* stream) {
+    GeomK g;
+    TofK t;
+    PP_TRY(make_geom(geom, g));
+    PP_TRY(make_tof(tof, t));
+    if (n_slots < 0 || n_slots > (1 << 20)) return PP_EINVAL_N;
+    if (n_slots == 0) return PP_OK;
+    if (!d_slots) return PP_EINVAL_PTR;
+    return hip_status(launch_osem_accumulate(d_slots, n_slots, g, t, device_cus() * 8, as_stream(stream)));
+}
+
+int pp_lm_osem_update(pp_osem_slot_t* d_slots, int32_t n_slots, int64_t n_vox, void* stream) {
+    if (n_slots < 0 || n_slots > (1 << 20) || n_vox <= 0 || n_vox > (int64_t(1) << 30)) return PP_EINVAL_N;
+    if (n_slots == 0) return PP_OK;
+    if (!d_slots) return PP_EINVAL_PTR;
+    const int64_t total = (int64_t)n_slots * n_vox;
+    int64_t blocks = (total + 255) / 256;
+    const int64_t cap = (int64_t)device_cus() * 16;
+    if (blocks > cap) blocks = cap;
+    return hip_status(launch_osem_update(d_slots, n_slots, n_vox, (int)blocks, as_stream(stream)));
+}
+
+int pp_fill(float* dst, int64_t n, float value, void* stream) {
+    if (n < 0) return PP_EINVAL_N;
+    if (n == 0) return PP_OK;
+    if (!dst) return PP_EINVAL_PTR;
+    return hip_status(launch_fill(dst, n, value, as_stream(stream)));
+}
+
+}  // extern "C"

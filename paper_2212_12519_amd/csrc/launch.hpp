@@ -1,0 +1,33 @@
+// Internal launch interface between the C ABI (api.cpp) and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ppmi.h"
+
+namespace ppmi {
+
+struct GeomK;
+struct TofK;
+
+hipError_t launch_fwd(const float* xs, const float* xe, int64_t n, const GeomK& g, const float* img, float* p,
+                      hipStream_t s);
+hipError_t launch_back(const float* xs, const float* xe, int64_t n, const GeomK& g, float* img, const float* p,
+                       hipStream_t s);
+hipError_t launch_fwd_tof_sino(const float* xs, const float* xe, int64_t n, const GeomK& g, const TofK& t,
+                               const float* img, float* p, hipStream_t s);
+hipError_t launch_back_tof_sino(const float* xs, const float* xe, int64_t n, const GeomK& g, const TofK& t,
+                                float* img, const float* p, hipStream_t s);
+hipError_t launch_fwd_tof_lm(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g,
+                             const TofK& t, const float* img, float* p, hipStream_t s);
+hipError_t launch_back_tof_lm(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g,
+                              const TofK& t, float* img, const float* p, hipStream_t s);
+
+int64_t osem_chunks(int64_t n_events, int32_t n_sub);
+hipError_t launch_osem_accumulate(const pp_osem_slot_t* slots, int n_slots, const GeomK& g, const TofK& t,
+                                  int n_blocks, hipStream_t s);
+hipError_t launch_osem_update(pp_osem_slot_t* slots, int n_slots, int64_t n_vox, int n_blocks, hipStream_t s);
+hipError_t launch_fill(float* dst, int64_t n, float value, hipStream_t s);
+
+}  // namespace ppmi

@@ -1,0 +1,120 @@
+// Batched listmode TOF OSEM on device-resident frames (the paper's listmode
+// OSEM of Sec. 2.6, run for many frames at once).
+//
+// k_osem_accumulate: one persistent grid walks the work chunks of all live
+// slots (a chunk = 256 events of one slot's current subset); each thread
+// projects its event forward through the slot's image, forms 1 / (ybar) and
+// back projects it into the slot's accumulator -- forward, ratio and back
+// projection fused, the event's coordinates read once.
+// k_osem_update: x <- x * acc / (sens / n_sub) (0 where sens == 0), acc <- 0.
+// k_osem_advance: next subset, one step fewer.
+#include <hip/hip_runtime.h>
+
+#include "joseph.hpp"
+#include "launch.hpp"
+
+namespace ppmi {
+
+constexpr int kOsemBlock = 256;
+
+__device__ __forceinline__ bool slot_live(const pp_osem_slot_t& s) { return s.active && s.steps_left > 0; }
+
+__host__ __device__ inline int64_t slot_chunks(int64_t n_events, int32_t n_sub) {
+    if (n_events <= 0 || n_sub <= 0) return 0;
+    const int64_t per_subset = (n_events + n_sub - 1) / n_sub;  // largest subset
+    return (per_subset + kOsemBlock - 1) / kOsemBlock;
+}
+
+__global__ void __launch_bounds__(kOsemBlock) k_osem_accumulate(const pp_osem_slot_t* __restrict__ slots,
+                                                                int n_slots, GeomK g, TofK t) {
+    const pp_osem_slot_t& last = slots[n_slots - 1];
+    const int64_t total = last.chunk_begin + (last.active ? slot_chunks(last.n_events, last.n_sub) : 0);
+    for (int64_t c = xcd_block(blockIdx.x, gridDim.x); c < total; c += gridDim.x) {
+        // largest slot index whose first chunk is <= c
+        int lo = 0, hi = n_slots - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (slots[mid].chunk_begin <= c) lo = mid; else hi = mid - 1;
+        }
+        const pp_osem_slot_t& s = slots[lo];
+        if (!slot_live(s)) continue;
+        const int64_t q = (c - s.chunk_begin) * kOsemBlock + threadIdx.x;
+        const int64_t e = (int64_t)s.subset + q * s.n_sub;
+        if (e >= s.n_events) continue;
+        const int b = s.tof_bin[e];
+        if (b < 0 || b >= t.nb) continue;
+        RayK r;
+        if (!ray_setup(s.xstart + 3 * e, s.xend + 3 * e, g, r)) continue;
+        const double centre = t.c0 + b * t.bw;
+        if (!tof_window(r, centre, t.win)) continue;
+        const float* __restrict__ x = s.x;
+        float fwd = 0.0f;
+        for (int k = r.k_lo; k <= r.k_hi; ++k) {
+            const float w = tof_weight(fma((double)k, r.ds, r.s0), centre, t);
+            fwd += w * stencil_gather(x, r, stencil_at(r, k));
+        }
+        const float ybar = r.ell * fwd + s.bg;
+        if (!(ybar > 0.0f)) continue;
+        const float cl = r.ell / ybar;
+        float* __restrict__ acc = s.acc;
+        for (int k = r.k_lo; k <= r.k_hi; ++k) {
+            const float w = tof_weight(fma((double)k, r.ds, r.s0), centre, t);
+            if (w != 0.0f) stencil_scatter(acc, r, stencil_at(r, k), w * cl);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kOsemBlock) k_osem_update(const pp_osem_slot_t* __restrict__ slots, int n_slots,
+                                                            int64_t n_vox) {
+    const int64_t total = (int64_t)n_slots * n_vox;
+    const int64_t stride = (int64_t)gridDim.x * kOsemBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kOsemBlock + threadIdx.x; i < total; i += stride) {
+        const int si = (int)(i / n_vox);
+        const int64_t v = i - (int64_t)si * n_vox;
+        const pp_osem_slot_t& s = slots[si];
+        if (!slot_live(s)) continue;
+        const float sv = s.sens[v];
+        const float a = s.acc[v];
+        s.x[v] = (sv > 0.0f) ? s.x[v] * a / (sv / (float)s.n_sub) : 0.0f;
+        s.acc[v] = 0.0f;
+    }
+}
+
+__global__ void k_osem_advance(pp_osem_slot_t* slots, int n_slots) {
+    for (int i = threadIdx.x; i < n_slots; i += blockDim.x) {
+        pp_osem_slot_t& s = slots[i];
+        if (!slot_live(s)) continue;
+        s.subset = (s.subset + 1) % s.n_sub;
+        s.steps_left -= 1;
+    }
+}
+
+__global__ void k_fill(float* __restrict__ dst, int64_t n, float value) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = value;
+}
+
+int64_t osem_chunks(int64_t n_events, int32_t n_sub) { return slot_chunks(n_events, n_sub); }
+
+hipError_t launch_osem_accumulate(const pp_osem_slot_t* slots, int n_slots, const GeomK& g, const TofK& t,
+                                  int n_blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_osem_accumulate, dim3(n_blocks), dim3(kOsemBlock), 0, s, slots, n_slots, g, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_osem_update(pp_osem_slot_t* slots, int n_slots, int64_t n_vox, int n_blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_osem_update, dim3(n_blocks), dim3(kOsemBlock), 0, s, slots, n_slots, n_vox);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_osem_advance, dim3(1), dim3(256), 0, s, slots, n_slots);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(float* dst, int64_t n, float value, hipStream_t s) {
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, s, dst, n, value);
+    return hipGetLastError();
+}
+
+}  // namespace ppmi

@@ -1,0 +1,223 @@
+// Joseph forward / back projection kernels for gfx950 (non-TOF, TOF sinogram,
+// TOF listmode).  One thread per ray; 256-thread workgroups (4 wave64s);
+// XCD-aware workgroup order.  See joseph.hpp for the traversal itself.
+#include <hip/hip_runtime.h>
+
+#include "joseph.hpp"
+#include "launch.hpp"
+
+namespace ppmi {
+
+constexpr int kBlock = 256;
+
+// ------------------------------------------------------------- non-TOF ----
+
+__global__ void __launch_bounds__(kBlock) k_fwd(const float* __restrict__ xs, const float* __restrict__ xe,
+                                                int64_t n, GeomK g, const float* __restrict__ img,
+                                                float* __restrict__ p) {
+    const int64_t l = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (l >= n) return;
+    RayK r;
+    float acc = 0.0f;
+    if (ray_setup(xs + 3 * l, xe + 3 * l, g, r)) {
+        for (int k = r.k_lo; k <= r.k_hi; ++k) acc += stencil_gather(img, r, stencil_at(r, k));
+        acc *= r.ell;
+    }
+    p[l] = acc;
+}
+
+__global__ void __launch_bounds__(kBlock) k_back(const float* __restrict__ xs, const float* __restrict__ xe,
+                                                 int64_t n, GeomK g, float* __restrict__ img,
+                                                 const float* __restrict__ p) {
+    const int64_t l = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (l >= n) return;
+    const float pl = p[l];
+    if (pl == 0.0f) return;
+    RayK r;
+    if (!ray_setup(xs + 3 * l, xe + 3 * l, g, r)) return;
+    const float c = r.ell * pl;
+    for (int k = r.k_lo; k <= r.k_hi; ++k) stencil_scatter(img, r, stencil_at(r, k), c);
+}
+
+// ------------------------------------------------------- TOF listmode ----
+
+__global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(const float* __restrict__ xs, const float* __restrict__ xe,
+                                                       const int16_t* __restrict__ bins, int64_t n, GeomK g,
+                                                       TofK t, const float* __restrict__ img,
+                                                       float* __restrict__ p) {
+    const int64_t l = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (l >= n) return;
+    const int b = bins[l];
+    float acc = 0.0f;
+    RayK r;
+    if (b >= 0 && b < t.nb && ray_setup(xs + 3 * l, xe + 3 * l, g, r)) {
+        const double c = t.c0 + b * t.bw;
+        if (tof_window(r, c, t.win)) {
+            for (int k = r.k_lo; k <= r.k_hi; ++k) {
+                const float w = tof_weight(fma((double)k, r.ds, r.s0), c, t);
+                acc += w * stencil_gather(img, r, stencil_at(r, k));
+            }
+            acc *= r.ell;
+        }
+    }
+    p[l] = acc;
+}
+
+__global__ void __launch_bounds__(kBlock) k_back_tof_lm(const float* __restrict__ xs, const float* __restrict__ xe,
+                                                        const int16_t* __restrict__ bins, int64_t n, GeomK g,
+                                                        TofK t, float* __restrict__ img,
+                                                        const float* __restrict__ p) {
+    const int64_t l = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (l >= n) return;
+    const int b = bins[l];
+    const float pl = p[l];
+    if (b < 0 || b >= t.nb || pl == 0.0f) return;
+    RayK r;
+    if (!ray_setup(xs + 3 * l, xe + 3 * l, g, r)) return;
+    const double c = t.c0 + b * t.bw;
+    if (!tof_window(r, c, t.win)) return;
+    const float cl = r.ell * pl;
+    for (int k = r.k_lo; k <= r.k_hi; ++k) {
+        const float w = tof_weight(fma((double)k, r.ds, r.s0), c, t);
+        if (w != 0.0f) stencil_scatter(img, r, stencil_at(r, k), w * cl);
+    }
+}
+
+// ------------------------------------------------------- TOF sinogram ----
+//
+// Each thread keeps its n_bins accumulators in LDS (column per thread, so a
+// wave touching the same bin hits 64 distinct banks).  Per plane sample only
+// the bins inside the TOF window are evaluated; neighbouring bins share their
+// edge, so a window of m bins costs m + 1 erf evaluations.  The block's
+// [rays][bins] output tile is contiguous in memory and is written with
+// coalesced stores at the end.
+
+__device__ __forceinline__ void tof_bin_range(double s, const TofK& t, int& b_lo, int& b_hi) {
+    const double lo = floor((s - t.win - t.c0) / t.bw);
+    const double hi = ceil((s + t.win - t.c0) / t.bw);
+    b_lo = (int)fmax(lo, 0.0);
+    b_hi = (int)fmin(hi, (double)(t.nb - 1));
+}
+
+__global__ void k_fwd_tof_sino(const float* __restrict__ xs, const float* __restrict__ xe, int64_t n, GeomK g,
+                               TofK t, const float* __restrict__ img, float* __restrict__ p) {
+    extern __shared__ float lds[];  // [nb][blockDim]
+    const int nt = blockDim.x;
+    const int64_t l0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * nt;
+    const int64_t l = l0 + threadIdx.x;
+    for (int b = 0; b < t.nb; ++b) lds[b * nt + threadIdx.x] = 0.0f;
+    RayK r;
+    if (l < n && ray_setup(xs + 3 * l, xe + 3 * l, g, r)) {
+        float* mine = lds + threadIdx.x;
+        for (int k = r.k_lo; k <= r.k_hi; ++k) {
+            const float v = stencil_gather(img, r, stencil_at(r, k));
+            if (v == 0.0f) continue;
+            const double s = fma((double)k, r.ds, r.s0);
+            int b_lo, b_hi;
+            tof_bin_range(s, t, b_lo, b_hi);
+            const double x_hi0 = s - (t.c0 + b_lo * t.bw) + 0.5 * t.bw;  // upper edge argument of bin b_lo
+            float g_hi = tof_cdf(x_hi0, t);
+            for (int b = b_lo; b <= b_hi; ++b) {
+                const float g_lo = tof_cdf(x_hi0 - (double)(b - b_lo + 1) * t.bw, t);
+                mine[b * nt] += (g_hi - g_lo) * v;
+                g_hi = g_lo;
+            }
+        }
+        const float ell = r.ell;
+        for (int b = 0; b < t.nb; ++b) mine[b * nt] *= ell;
+    }
+    __syncthreads();
+    const int64_t nrays = (n - l0 < nt) ? (n - l0) : nt;
+    const int64_t total = nrays * t.nb;
+    float* out = p + l0 * t.nb;
+    for (int64_t i = threadIdx.x; i < total; i += nt) {
+        const int ray = (int)(i / t.nb), b = (int)(i - (int64_t)ray * t.nb);
+        out[i] = lds[b * nt + ray];
+    }
+}
+
+__global__ void k_back_tof_sino(const float* __restrict__ xs, const float* __restrict__ xe, int64_t n, GeomK g,
+                                TofK t, float* __restrict__ img, const float* __restrict__ p) {
+    extern __shared__ float lds[];  // [nb][blockDim]: the block's projection tile, transposed
+    const int nt = blockDim.x;
+    const int64_t l0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * nt;
+    const int64_t l = l0 + threadIdx.x;
+    const int64_t nrays = (n - l0 < nt) ? (n - l0) : nt;
+    const int64_t total = nrays * t.nb;
+    const float* in = p + l0 * t.nb;
+    for (int64_t i = threadIdx.x; i < total; i += nt) {
+        const int ray = (int)(i / t.nb), b = (int)(i - (int64_t)ray * t.nb);
+        lds[b * nt + ray] = in[i];
+    }
+    __syncthreads();
+    if (l >= n) return;
+    RayK r;
+    if (!ray_setup(xs + 3 * l, xe + 3 * l, g, r)) return;
+    const float* mine = lds + threadIdx.x;
+    bool any = false;
+    for (int b = 0; b < t.nb; ++b) any |= (mine[b * nt] != 0.0f);
+    if (!any) return;
+    const float ell = r.ell;
+    for (int k = r.k_lo; k <= r.k_hi; ++k) {
+        const double s = fma((double)k, r.ds, r.s0);
+        int b_lo, b_hi;
+        tof_bin_range(s, t, b_lo, b_hi);
+        const double x_hi0 = s - (t.c0 + b_lo * t.bw) + 0.5 * t.bw;
+        float g_hi = tof_cdf(x_hi0, t);
+        float c = 0.0f;
+        for (int b = b_lo; b <= b_hi; ++b) {
+            const float g_lo = tof_cdf(x_hi0 - (double)(b - b_lo + 1) * t.bw, t);
+            c += (g_hi - g_lo) * mine[b * nt];
+            g_hi = g_lo;
+        }
+        if (c != 0.0f) stencil_scatter(img, r, stencil_at(r, k), ell * c);
+    }
+}
+
+// --------------------------------------------------------------- launch ----
+
+static unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+hipError_t launch_fwd(const float* xs, const float* xe, int64_t n, const GeomK& g, const float* img, float* p,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_fwd, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, xs, xe, n, g, img, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_back(const float* xs, const float* xe, int64_t n, const GeomK& g, float* img, const float* p,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_back, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, xs, xe, n, g, img, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_fwd_tof_lm(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g,
+                             const TofK& t, const float* img, float* p, hipStream_t s) {
+    hipLaunchKernelGGL(k_fwd_tof_lm, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, xs, xe, bins, n, g, t, img, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_back_tof_lm(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g,
+                              const TofK& t, float* img, const float* p, hipStream_t s) {
+    hipLaunchKernelGGL(k_back_tof_lm, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, xs, xe, bins, n, g, t, img, p);
+    return hipGetLastError();
+}
+
+static int sino_block(int nb) { return nb <= 64 ? 256 : 64; }  // LDS tile <= 64 KiB
+
+hipError_t launch_fwd_tof_sino(const float* xs, const float* xe, int64_t n, const GeomK& g, const TofK& t,
+                               const float* img, float* p, hipStream_t s) {
+    const int blk = sino_block(t.nb);
+    const size_t lds = (size_t)t.nb * blk * sizeof(float);
+    hipLaunchKernelGGL(k_fwd_tof_sino, dim3(grid_for(n, blk)), dim3(blk), lds, s, xs, xe, n, g, t, img, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_back_tof_sino(const float* xs, const float* xe, int64_t n, const GeomK& g, const TofK& t,
+                                float* img, const float* p, hipStream_t s) {
+    const int blk = sino_block(t.nb);
+    const size_t lds = (size_t)t.nb * blk * sizeof(float);
+    hipLaunchKernelGGL(k_back_tof_sino, dim3(grid_for(n, blk)), dim3(blk), lds, s, xs, xe, n, g, t, img, p);
+    return hipGetLastError();
+}
+
+}  // namespace ppmi

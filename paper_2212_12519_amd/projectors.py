@@ -1,0 +1,136 @@
+"""Python entry points with the names of the C ABI (include/ppmi.h).
+
+``pp_*`` take caller-allocated GPU tensors exactly like the C functions and
+launch on torch's current stream.  ``fwd``/``back``/... are conveniences that
+allocate the output with torch and call the ``pp_*`` function.
+"""
+from __future__ import annotations
+
+import torch
+
+from ._lib import _bins, _dev, _img, _rays, as_geom, as_tof, check, load, ptr, stream_of
+
+
+def pp_fwd(xstart, xend, geom, img, p):
+    """Non-TOF forward projection into p[n] (overwritten). Sec. 2.1 of the paper."""
+    g = as_geom(geom)
+    _dev(xstart, xend, img, p)
+    n = _rays(xstart, xend)
+    _img(img, g)
+    if p.dtype != torch.float32 or p.numel() != n:
+        raise ValueError("p must be float32 [n]")
+    gc = g.c()
+    check(load().pp_fwd(ptr(xstart), ptr(xend), n, gc, ptr(img), ptr(p), stream_of(p)))
+    return p
+
+
+def pp_back(xstart, xend, geom, img, p):
+    """Non-TOF back projection, img += A^T p (adjoint of pp_fwd)."""
+    g = as_geom(geom)
+    _dev(xstart, xend, img, p)
+    n = _rays(xstart, xend)
+    _img(img, g)
+    if p.dtype != torch.float32 or p.numel() != n:
+        raise ValueError("p must be float32 [n]")
+    check(load().pp_back(ptr(xstart), ptr(xend), n, g.c(), ptr(img), ptr(p), stream_of(img)))
+    return img
+
+
+def pp_fwd_tof_sino(xstart, xend, geom, tof, img, p):
+    """TOF sinogram forward projection into p[n, n_bins] (overwritten)."""
+    g, t = as_geom(geom), as_tof(tof)
+    _dev(xstart, xend, img, p)
+    n = _rays(xstart, xend)
+    _img(img, g)
+    if p.dtype != torch.float32 or p.numel() != n * t.n_bins:
+        raise ValueError("p must be float32 [n, n_bins]")
+    check(load().pp_fwd_tof_sino(ptr(xstart), ptr(xend), n, g.c(), t.c(), ptr(img), ptr(p), stream_of(p)))
+    return p
+
+
+def pp_back_tof_sino(xstart, xend, geom, tof, img, p):
+    """TOF sinogram back projection, img += A^T p."""
+    g, t = as_geom(geom), as_tof(tof)
+    _dev(xstart, xend, img, p)
+    n = _rays(xstart, xend)
+    _img(img, g)
+    if p.dtype != torch.float32 or p.numel() != n * t.n_bins:
+        raise ValueError("p must be float32 [n, n_bins]")
+    check(load().pp_back_tof_sino(ptr(xstart), ptr(xend), n, g.c(), t.c(), ptr(img), ptr(p), stream_of(img)))
+    return img
+
+
+def pp_fwd_tof_lm(xstart, xend, tof_bin, geom, tof, img, p):
+    """TOF listmode forward projection (event's bin only) into p[n] (overwritten)."""
+    g, t = as_geom(geom), as_tof(tof)
+    _dev(xstart, xend, tof_bin, img, p)
+    n = _rays(xstart, xend)
+    _bins(tof_bin, n)
+    _img(img, g)
+    if p.dtype != torch.float32 or p.numel() != n:
+        raise ValueError("p must be float32 [n]")
+    check(load().pp_fwd_tof_lm(ptr(xstart), ptr(xend), ptr(tof_bin), n, g.c(), t.c(), ptr(img), ptr(p),
+                               stream_of(p)))
+    return p
+
+
+def pp_back_tof_lm(xstart, xend, tof_bin, geom, tof, img, p):
+    """TOF listmode back projection, img += A^T p."""
+    g, t = as_geom(geom), as_tof(tof)
+    _dev(xstart, xend, tof_bin, img, p)
+    n = _rays(xstart, xend)
+    _bins(tof_bin, n)
+    _img(img, g)
+    if p.dtype != torch.float32 or p.numel() != n:
+        raise ValueError("p must be float32 [n]")
+    check(load().pp_back_tof_lm(ptr(xstart), ptr(xend), ptr(tof_bin), n, g.c(), t.c(), ptr(img), ptr(p),
+                                stream_of(img)))
+    return img
+
+
+def pp_fill(dst, value):
+    """dst[:] = value with the library's fill kernel (graph-capture safe)."""
+    _dev(dst)
+    if dst.dtype != torch.float32:
+        raise TypeError("float32 only")
+    check(load().pp_fill(ptr(dst), dst.numel(), float(value), stream_of(dst)))
+    return dst
+
+
+# ------------------------------------------------------------- conveniences
+
+def fwd(xstart, xend, geom, img):
+    p = torch.empty(xstart.shape[0], dtype=torch.float32, device=xstart.device)
+    return pp_fwd(xstart, xend, geom, img, p)
+
+
+def back(xstart, xend, geom, p, img=None):
+    g = as_geom(geom)
+    if img is None:
+        img = torch.zeros(g.dim, dtype=torch.float32, device=xstart.device)
+    return pp_back(xstart, xend, g, img, p)
+
+
+def fwd_tof_sino(xstart, xend, geom, tof, img):
+    t = as_tof(tof)
+    p = torch.empty((xstart.shape[0], t.n_bins), dtype=torch.float32, device=xstart.device)
+    return pp_fwd_tof_sino(xstart, xend, geom, t, img, p)
+
+
+def back_tof_sino(xstart, xend, geom, tof, p, img=None):
+    g = as_geom(geom)
+    if img is None:
+        img = torch.zeros(g.dim, dtype=torch.float32, device=xstart.device)
+    return pp_back_tof_sino(xstart, xend, g, tof, img, p)
+
+
+def fwd_tof_lm(xstart, xend, tof_bin, geom, tof, img):
+    p = torch.empty(xstart.shape[0], dtype=torch.float32, device=xstart.device)
+    return pp_fwd_tof_lm(xstart, xend, tof_bin, geom, tof, img, p)
+
+
+def back_tof_lm(xstart, xend, tof_bin, geom, tof, p, img=None):
+    g = as_geom(geom)
+    if img is None:
+        img = torch.zeros(g.dim, dtype=torch.float32, device=xstart.device)
+    return pp_back_tof_lm(xstart, xend, tof_bin, g, tof, img, p)

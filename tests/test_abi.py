@@ -1,0 +1,93 @@
+"""Host-side checks of libppmi.so (no GPU needed): it loads, exports every function that
+include/ppmi.h declares, and rejects bad arguments with the documented codes before
+touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ppmi.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(pp_[a-z0-9_]+)\s*\(", txt, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2212_12519_amd as pp
+
+    return pp.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 12, names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert lib.pp_abi_version() == 1
+
+
+def _geom(dim=(4, 4, 4), vs=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0)):
+    from paper_2212_12519_amd._lib import CImage
+
+    return CImage((ctypes.c_float * 3)(*origin), (ctypes.c_float * 3)(*vs), (ctypes.c_int32 * 3)(*dim))
+
+
+def _tof(bw=1.0, sig=1.0, ns=3.0, nb=5):
+    from paper_2212_12519_amd._lib import CTof
+
+    return CTof(bw, sig, ns, 0.0, nb)
+
+
+DUMMY = ctypes.c_void_p(16)  # never dereferenced: validation fails before any launch
+
+
+def test_error_codes(lib):
+    from paper_2212_12519_amd._lib import PP_EINVAL_GEOM, PP_EINVAL_N, PP_EINVAL_PTR, PP_EINVAL_TOF, PP_OK
+
+    g = _geom()
+    assert lib.pp_fwd(None, None, 0, g, None, None, None) == PP_OK  # n == 0: no-op
+    assert lib.pp_fwd(None, None, 5, g, None, None, None) == PP_EINVAL_PTR
+    assert lib.pp_fwd(DUMMY, DUMMY, -1, g, DUMMY, DUMMY, None) == PP_EINVAL_N
+    assert lib.pp_fwd(DUMMY, DUMMY, 5, None, DUMMY, DUMMY, None) == PP_EINVAL_PTR
+    for bad in (_geom(dim=(0, 4, 4)), _geom(vs=(1.0, 0.0, 1.0)), _geom(vs=(1.0, -2.0, 1.0)),
+                _geom(vs=(float("nan"), 1.0, 1.0)), _geom(origin=(float("inf"), 0.0, 0.0)),
+                _geom(dim=(2048, 2048, 512))):
+        assert lib.pp_fwd(DUMMY, DUMMY, 5, bad, DUMMY, DUMMY, None) == PP_EINVAL_GEOM
+        assert lib.pp_back(DUMMY, DUMMY, 5, bad, DUMMY, DUMMY, None) == PP_EINVAL_GEOM
+    for bad in (_tof(nb=0), _tof(nb=257), _tof(bw=0.0), _tof(sig=-1.0), _tof(ns=0.0), _tof(sig=float("nan"))):
+        assert lib.pp_fwd_tof_sino(DUMMY, DUMMY, 5, g, bad, DUMMY, DUMMY, None) == PP_EINVAL_TOF
+        assert lib.pp_back_tof_lm(DUMMY, DUMMY, DUMMY, 5, g, bad, DUMMY, DUMMY, None) == PP_EINVAL_TOF
+    assert lib.pp_fwd_tof_lm(DUMMY, DUMMY, None, 5, g, _tof(), DUMMY, DUMMY, None) == PP_EINVAL_PTR
+    assert lib.pp_fwd_tof_lm(DUMMY, DUMMY, DUMMY, 5, g, None, DUMMY, DUMMY, None) == PP_EINVAL_PTR
+    assert lib.pp_lm_osem_accumulate(DUMMY, -1, g, _tof(), None) == PP_EINVAL_N
+    assert lib.pp_lm_osem_accumulate(DUMMY, 0, g, _tof(), None) == PP_OK
+    assert lib.pp_lm_osem_update(DUMMY, 3, 0, None) == PP_EINVAL_N
+    assert lib.pp_lm_osem_update(None, 3, 64, None) == PP_EINVAL_PTR
+    assert lib.pp_fill(None, 10, ctypes.c_float(0.0), None) == PP_EINVAL_PTR
+    assert lib.pp_fill(None, -1, ctypes.c_float(0.0), None) == PP_EINVAL_N
+    for c in range(6):
+        assert lib.pp_strerror(c)
+
+
+def test_osem_chunks(lib):
+    assert lib.pp_osem_chunks(0, 8) == 0
+    assert lib.pp_osem_chunks(1, 8) == 1
+    assert lib.pp_osem_chunks(8 * 256, 8) == 1
+    assert lib.pp_osem_chunks(8 * 256 + 1, 8) == 2
+    assert lib.pp_osem_chunks(20_000_000, 8) == (2_500_000 + 255) // 256
+
+
+def test_python_binding_rejects_cpu_tensors():
+    import torch
+
+    import paper_2212_12519_amd as pp
+
+    x = torch.zeros((4, 3))
+    with pytest.raises(TypeError):
+        pp.fwd(x, x, pp.ImageGeom((2, 2, 2), (1, 1, 1)), torch.zeros(2, 2, 2))
