@@ -1,0 +1,240 @@
+"""Benchmark: TOF listmode forward + back projection throughput on one MI355X.
+
+Workload (one step = one pass of the projector pair over one batch):
+  40,000,000 seeded synthetic TOF listmode events drawn from the clinical
+  ellipsoid/lesion phantom (scanner radius 410 mm, 64 rings x 760 crystals,
+  ring difference <= 20, 400 radial bins), image 215 x 215 x 71 voxels of
+  1.65 x 1.65 x 2.0 mm, 29 TOF bins of 28 mm, Gaussian FWHM 58.5 mm truncated
+  at 3 sigma.  A step zeroes the back-projection image, runs pp_fwd_tof_lm
+  over all events and pp_back_tof_lm of the result.  Inputs are resident in
+  HBM before timing starts.
+
+Prints ONE JSON line (see the field list in the design notes): value =
+events / s over the timed steps, a live roofline figure for the dominant
+kernel (HIP events on the launch stream), the FP64 oracle timed on the host
+cores on a bounded sample, and secondary legs (clinical non-TOF and TOF
+sinogram projections, listmode-OSEM serving when available).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--events", type=int, default=None, help="override the 40M-event workload (testing only)")
+    ap.add_argument("--no-sino", action="store_true", help="skip the sinogram legs")
+    ap.add_argument("--no-serve", action="store_true", help="skip the OSEM serving leg")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
+    ap.add_argument("--only", default=None, help="profiling helper: lm | sino | serve")
+    return ap.parse_args()
+
+
+def timed_pairs(fn_a, fn_b, reset, steps, warmup):
+    """Run reset, a, b per step; returns (wall seconds, mean ms of a, mean ms of b) over `steps`."""
+    import torch
+
+    for _ in range(warmup):
+        reset()
+        fn_a()
+        fn_b()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for e in evs:
+        reset()
+        e[0].record()
+        fn_a()
+        e[1].record()
+        e[2].record()
+        fn_b()
+        e[3].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ta = sum(e[0].elapsed_time(e[1]) for e in evs) / steps
+    tb = sum(e[2].elapsed_time(e[3]) for e in evs) / steps
+    return wall, ta, tb
+
+
+def lm_leg(args, pp, C, dev):
+    import torch
+
+    from synth import generate_tof_lm_events
+
+    n_ev = args.events or C.N_EVENTS_LM
+    grid, tofs = C.GRID_CLIN, C.TOF_CLIN
+    img = C.phantom_clin(device=dev)
+    t0 = time.perf_counter()
+    xs, xe, bins = generate_tof_lm_events(C.SCANNER_CLIN, C.SINO_CLIN.n_rad, C.SINO_CLIN.max_rd, grid, img, n_ev,
+                                          seed=C.SEED_EVENTS, tof_bin_width=tofs.bin_width, tof_sigma=tofs.sigma,
+                                          n_tof_bins=tofs.n_bins, device=dev)
+    torch.cuda.synchronize()
+    log(f"generated {n_ev} events in {time.perf_counter() - t0:.1f} s")
+    G = pp.ImageGeom(grid.dim, grid.voxsize, grid.origin)
+    T = pp.TofParams(tofs.bin_width, tofs.sigma, tofs.n_sigmas, tofs.n_bins)
+    n_samples = int(pp.count_samples(xs, xe, G, bins, T).sum(dtype=torch.int64).item())
+    p = torch.empty(n_ev, dtype=torch.float32, device=dev)
+    bimg = torch.empty(grid.dim, dtype=torch.float32, device=dev)
+    wall, t_fwd, t_back = timed_pairs(lambda: pp.pp_fwd_tof_lm(xs, xe, bins, G, T, img, p),
+                                      lambda: pp.pp_back_tof_lm(xs, xe, bins, G, T, bimg, p),
+                                      lambda: pp.pp_fill(bimg, 0.0), args.steps, args.warmup)
+    log(f"TOF-LM: fwd {t_fwd:.2f} ms, back {t_back:.2f} ms, wall {1e3 * wall / args.steps:.2f} ms/step, "
+        f"{n_samples / n_ev:.1f} samples/event")
+    per_event = 24 + 2 + 4  # endpoints, bin, projection value
+    alg_bytes = per_event * n_ev + 16 * n_samples
+    dom_name, dom_ms = ("pp_back_tof_lm", t_back) if t_back >= t_fwd else ("pp_fwd_tof_lm", t_fwd)
+    achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
+    res = {
+        "n_events": n_ev, "wall_s": wall, "t_fwd_ms": t_fwd, "t_back_ms": t_back,
+        "samples_per_event": n_samples / n_ev, "alg_bytes_per_launch": alg_bytes,
+        "dominant": dom_name, "achieved_gbs": achieved,
+        "fwd_alg_gbs": alg_bytes / (t_fwd * 1e-3) / 1e9, "back_alg_gbs": alg_bytes / (t_back * 1e-3) / 1e9,
+    }
+    return res, (xs, xe, bins, img, G, T)
+
+
+def cpu_leg(args, lm_inputs, C):
+    import numpy as np
+
+    import oracle
+
+    xs, xe, bins, img, G, T = lm_inputs
+    tof = {"bin_width": T.bin_width, "sigma": T.sigma, "n_sigmas": T.n_sigmas, "n_bins": T.n_bins}
+    img64 = img.cpu().numpy().astype(np.float64)
+    g = C.GRID_CLIN
+
+    def run(n):
+        a, b, c = xs[:n].cpu().numpy(), xe[:n].cpu().numpy(), bins[:n].cpu().numpy()
+        t0 = time.perf_counter()
+        pv = oracle.fwd_tof_lm(a, b, g.origin, g.voxsize, g.dim, tof, c, img64)
+        oracle.back_tof_lm(a, b, g.origin, g.voxsize, g.dim, tof, c, pv)
+        return time.perf_counter() - t0
+
+    n0 = 100_000
+    t_cal = run(n0)
+    n = int(min(xs.shape[0], max(n0, n0 * args.cpu_seconds / max(t_cal, 1e-6))))
+    dt = run(n)
+    log(f"oracle: {n} events fwd+back in {dt:.1f} s on {oracle.max_threads()} threads")
+    return {"value": n / dt, "unit": "events/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"first {n} of the {xs.shape[0]} events, TOF-LM fwd+back, FP64 C/OpenMP oracle"}
+
+
+def sino_leg(args, pp, C, dev):
+    import torch
+
+    grid = C.GRID_CLIN
+    G = pp.ImageGeom(grid.dim, grid.voxsize, grid.origin)
+    t0 = time.perf_counter()
+    xs, xe = C.SINO_CLIN.lors(device=dev, radial_chunk=25)
+    img = C.phantom_clin(device=dev)
+    n = xs.shape[0]
+    torch.cuda.synchronize()
+    log(f"generated {n} sinogram LORs in {time.perf_counter() - t0:.1f} s")
+    n_samples = int(pp.count_samples(xs, xe, G).sum(dtype=torch.int64).item())
+    out = {}
+    p = torch.empty(n, dtype=torch.float32, device=dev)
+    bimg = torch.empty(grid.dim, dtype=torch.float32, device=dev)
+    reps = max(2, min(args.steps, 3))
+    wall, tf, tb = timed_pairs(lambda: pp.pp_fwd(xs, xe, G, img, p), lambda: pp.pp_back(xs, xe, G, bimg, p),
+                               lambda: pp.pp_fill(bimg, 0.0), reps, 1)
+    alg = (24 + 4) * n + 16 * n_samples
+    out["nontof"] = {"n_lors": n, "t_fwd_ms": tf, "t_back_ms": tb, "lors_per_s_fwd_back": n / ((tf + tb) * 1e-3),
+                     "samples_per_lor": n_samples / n, "fwd_alg_gbs": alg / (tf * 1e-3) / 1e9,
+                     "fwd_hbm_frac": alg / (tf * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "back_alg_gbs": alg / (tb * 1e-3) / 1e9}
+    log(f"sino non-TOF: fwd {tf:.1f} ms back {tb:.1f} ms")
+    del p
+    tofs = C.TOF_CLIN
+    T = pp.TofParams(tofs.bin_width, tofs.sigma, tofs.n_sigmas, tofs.n_bins)
+    pt = torch.empty((n, tofs.n_bins), dtype=torch.float32, device=dev)
+    wall, tf, tb = timed_pairs(lambda: pp.pp_fwd_tof_sino(xs, xe, G, T, img, pt),
+                               lambda: pp.pp_back_tof_sino(xs, xe, G, T, bimg, pt),
+                               lambda: pp.pp_fill(bimg, 0.0), reps, 1)
+    alg_t = (24 + 4 * tofs.n_bins) * n + 16 * n_samples
+    out["tof_sino"] = {"n_lors": n, "n_bins": tofs.n_bins, "t_fwd_ms": tf, "t_back_ms": tb,
+                       "lors_per_s_fwd_back": n / ((tf + tb) * 1e-3), "fwd_alg_gbs": alg_t / (tf * 1e-3) / 1e9,
+                       "fwd_hbm_frac": alg_t / (tf * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    log(f"sino TOF: fwd {tf:.1f} ms back {tb:.1f} ms")
+    del pt, xs, xe
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2212_12519_amd as pp
+    from synth import configs as C
+
+    pp.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    result = {"metric": "TOF listmode fwd+back events/s + OSEM frame p50/p99 latency vs plain"}
+    extra = {}
+    lm = lm_inputs = None
+    if args.only in (None, "lm"):
+        lm, lm_inputs = lm_leg(args, pp, C, dev)
+    if args.only == "lm":
+        print(json.dumps({"lm": lm}))
+        return
+    if args.only in (None, "sino") and not args.no_sino:
+        extra["sinogram"] = sino_leg(args, pp, C, dev)
+    if args.only == "sino":
+        print(json.dumps(extra))
+        return
+    if args.only in (None, "serve") and not args.no_serve:
+        try:
+            from paper_2212_12519_amd import serve  # noqa: F401
+        except ImportError:
+            serve = None
+        if serve is not None:
+            extra["osem_serving"] = serve.bench_leg(args, log)
+    cpu = None
+    if not args.no_cpu and lm_inputs is not None:
+        cpu = cpu_leg(args, lm_inputs, C)
+    value = lm["n_events"] * args.steps / lm["wall_s"]
+    ach = lm["achieved_gbs"]
+    result.update({
+        "value": value, "unit": "events/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * lm["wall_s"] / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "TOF listmode fwd+back, 40M events, clinical phantom 215x215x71 @ 1.65x1.65x2.0 mm, "
+                               "29 TOF bins x 28 mm, FWHM 58.5 mm, 3 sigma",
+                   "n_events": lm["n_events"], "image": list(C.GRID_CLIN.dim), "tof_bins": C.TOF_CLIN.n_bins},
+        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": lm["dominant"],
+                     "alg_bytes_per_launch": lm["alg_bytes_per_launch"]},
+        "cpu_baseline": cpu,
+        "lm": {k: lm[k] for k in ("t_fwd_ms", "t_back_ms", "samples_per_event", "fwd_alg_gbs",
+                                  "back_alg_gbs")},
+    })
+    result.update(extra)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

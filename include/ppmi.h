@@ -115,6 +115,14 @@ int pp_fwd_tof_lm(const float* xstart, const float* xend, const int16_t* tof_bin
 int pp_back_tof_lm(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n_events,
                    const pp_image_t* geom, const pp_tof_t* tof, float* img, const float* p, void* stream);
 
+/* Work counter (for throughput accounting, not part of the method): counts[l]
+ * = plane samples of ray l whose 2x2 stencil has at least one voxel inside
+ * the grid -- the samples a projection of that ray touches memory for.  With
+ * tof_bin != NULL (listmode; tof required) only samples strictly inside the
+ * event's TOF window count; out-of-range bins count 0.  counts: int32 [n]. */
+int pp_count_samples(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n,
+                     const pp_image_t* geom, const pp_tof_t* tof, int32_t* counts, void* stream);
+
 /* ------------------------------------------------------------------------
  * Batched listmode TOF OSEM (the paper's listmode OSEM of Sec. 2.6, run for
  * many short frames at once).  One "step" of a frame is one ordered-subset

@@ -116,6 +116,7 @@ def load():
         "pp_lm_osem_accumulate": [P, I32, G, T, P],
         "pp_lm_osem_update": [P, I32, I64, P],
         "pp_fill": [P, I64, ctypes.c_float, P],
+        "pp_count_samples": [P, P, P, I64, G, T, P, P],
     }
     for name, argt in sig.items():
         f = getattr(lib, name)

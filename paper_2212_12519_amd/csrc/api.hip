@@ -59,8 +59,8 @@ int make_tof(const pp_tof_t* ti, TofK& t) {
     return PP_OK;
 }
 
-// grid limit: 2^31 - 1 workgroups of 64..256 threads
-constexpr int64_t kMaxRays = (int64_t(1) << 31) * 64 - 64;
+// grid limit: 2^31 - 1 workgroups of >= 64 threads
+constexpr int64_t kMaxRays = ((int64_t(1) << 31) - 1) * 64;
 
 int check_n(int64_t n) { return (n < 0 || n > kMaxRays) ? PP_EINVAL_N : PP_OK; }
 
@@ -163,6 +163,18 @@ int pp_back_tof_lm(const float* xstart, const float* xend, const int16_t* tof_bi
     if (n == 0) return PP_OK;
     if (!xstart || !xend || !tof_bin || !img || !p) return PP_EINVAL_PTR;
     return hip_status(launch_back_tof_lm(xstart, xend, tof_bin, n, g, t, img, p, as_stream(stream)));
+}
+
+int pp_count_samples(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n, const pp_image_t* geom,
+                     const pp_tof_t* tof, int32_t* counts, void* stream) {
+    GeomK g;
+    TofK t{};
+    PP_TRY(make_geom(geom, g));
+    if (tof_bin) PP_TRY(make_tof(tof, t));
+    PP_TRY(check_n(n));
+    if (n == 0) return PP_OK;
+    if (!xstart || !xend || !counts) return PP_EINVAL_PTR;
+    return hip_status(launch_count(xstart, xend, tof_bin, n, g, t, counts, as_stream(stream)));
 }
 
 int64_t pp_osem_chunks(int64_t n_events, int32_t n_sub) { return osem_chunks(n_events, n_sub); }

@@ -24,6 +24,9 @@ hipError_t launch_fwd_tof_lm(const float* xs, const float* xe, const int16_t* bi
 hipError_t launch_back_tof_lm(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g,
                               const TofK& t, float* img, const float* p, hipStream_t s);
 
+hipError_t launch_count(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g,
+                        const TofK& t, int32_t* counts, hipStream_t s);
+
 int64_t osem_chunks(int64_t n_events, int32_t n_sub);
 hipError_t launch_osem_accumulate(const pp_osem_slot_t* slots, int n_slots, const GeomK& g, const TofK& t,
                                   int n_blocks, hipStream_t s);

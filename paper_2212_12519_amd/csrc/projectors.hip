@@ -174,6 +174,38 @@ __global__ void k_back_tof_sino(const float* __restrict__ xs, const float* __res
     }
 }
 
+// ------------------------------------------------------- work counter ----
+//
+// Plane samples per ray whose 2x2 stencil has at least one voxel inside the
+// grid; for TOF listmode (bins != nullptr) only samples strictly inside the
+// event's TOF window (non-zero weight).  Same traversal as the projectors.
+
+__global__ void __launch_bounds__(kBlock) k_count(const float* __restrict__ xs, const float* __restrict__ xe,
+                                                  const int16_t* __restrict__ bins, int64_t n, GeomK g, TofK t,
+                                                  int32_t* __restrict__ counts) {
+    const int64_t l = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (l >= n) return;
+    int cnt = 0;
+    RayK r;
+    bool ok = ray_setup(xs + 3 * l, xe + 3 * l, g, r);
+    double centre = 0.0;
+    if (ok && bins) {
+        const int b = bins[l];
+        ok = b >= 0 && b < t.nb;
+        centre = t.c0 + b * t.bw;
+        ok = ok && tof_window(r, centre, t.win);
+    }
+    if (ok) {
+        for (int k = r.k_lo; k <= r.k_hi; ++k) {
+            const Stencil st = stencil_at(r, k);
+            if (!((st.i0ok || st.i1ok) && (st.j0ok || st.j1ok))) continue;
+            if (bins && !(fabs(fma((double)k, r.ds, r.s0) - centre) < t.win)) continue;
+            ++cnt;
+        }
+    }
+    counts[l] = cnt;
+}
+
 // --------------------------------------------------------------- launch ----
 
 static unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
@@ -217,6 +249,12 @@ hipError_t launch_back_tof_sino(const float* xs, const float* xe, int64_t n, con
     const int blk = sino_block(t.nb);
     const size_t lds = (size_t)t.nb * blk * sizeof(float);
     hipLaunchKernelGGL(k_back_tof_sino, dim3(grid_for(n, blk)), dim3(blk), lds, s, xs, xe, n, g, t, img, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_count(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g,
+                        const TofK& t, int32_t* counts, hipStream_t s) {
+    hipLaunchKernelGGL(k_count, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, xs, xe, bins, n, g, t, counts);
     return hipGetLastError();
 }
 

@@ -10,7 +10,6 @@ import torch
 
 from ._lib import _bins, _dev, _img, _rays, as_geom, as_tof, check, load, ptr, stream_of
 
-
 def pp_fwd(xstart, xend, geom, img, p):
     """Non-TOF forward projection into p[n] (overwritten). Sec. 2.1 of the paper."""
     g = as_geom(geom)
@@ -95,6 +94,27 @@ def pp_fill(dst, value):
         raise TypeError("float32 only")
     check(load().pp_fill(ptr(dst), dst.numel(), float(value), stream_of(dst)))
     return dst
+
+
+def pp_count_samples(xstart, xend, tof_bin, geom, tof, counts):
+    """Work counter: plane samples per ray that touch the grid (listmode: inside the TOF window)."""
+    g = as_geom(geom)
+    _dev(xstart, xend, tof_bin, counts)
+    n = _rays(xstart, xend)
+    if counts.dtype != torch.int32 or counts.numel() != n:
+        raise ValueError("counts must be int32 [n]")
+    tc = None
+    if tof_bin is not None:
+        _bins(tof_bin, n)
+        tc = as_tof(tof).c()
+    check(load().pp_count_samples(ptr(xstart), ptr(xend), ptr(tof_bin), n, g.c(), tc, ptr(counts),
+                                  stream_of(counts)))
+    return counts
+
+
+def count_samples(xstart, xend, geom, tof_bin=None, tof=None):
+    counts = torch.empty(xstart.shape[0], dtype=torch.int32, device=xstart.device)
+    return pp_count_samples(xstart, xend, tof_bin, geom, tof, counts)
 
 
 # ------------------------------------------------------------- conveniences

@@ -302,3 +302,24 @@ def test_tof_lm_40m_events(gpu, lm40):
     bref = oracle.back_tof_lm(xs[:m].cpu().numpy(), xe[:m].cpu().numpy(), g["origin"], g["voxsize"], g["dim"], tof,
                               bins[:m].cpu().numpy(), y[:m].cpu().numpy())
     assert rel_l2(np64(b1), bref) <= BACK_TOL
+
+
+def test_work_counter_matches_oracle(gpu, small):
+    """The sample counter used for throughput accounting equals the oracle's count exactly."""
+    xs, xe, img, _ = small
+    g = geom_of(C.GRID_SMALL)
+    G = gpu.ImageGeom(g["dim"], g["voxsize"], g["origin"])
+    dev = torch.device("cuda")
+    cnt = gpu.count_samples(xs.to(dev), xe.to(dev), G)
+    tot, per = oracle.count_samples(xs.numpy(), xe.numpy(), g["origin"], g["voxsize"], g["dim"], per_ray=True)
+    assert np.array_equal(cnt.cpu().numpy().astype(np.int64), per)
+    t = C.TOF_CLIN
+    exs, exe, bins = generate_tof_lm_events(C.SCANNER_SMALL, C.SINO_SMALL.n_rad, C.SINO_SMALL.max_rd, C.GRID_SMALL,
+                                            img, 50_000, seed=33, tof_bin_width=t.bin_width, tof_sigma=t.sigma,
+                                            n_tof_bins=t.n_bins)
+    tof = tof_of(t)
+    T = gpu.TofParams(tof["bin_width"], tof["sigma"], tof["n_sigmas"], tof["n_bins"])
+    c2 = gpu.count_samples(exs.to(dev), exe.to(dev), G, bins.to(dev), T)
+    tot2, per2 = oracle.count_samples(exs.numpy(), exe.numpy(), g["origin"], g["voxsize"], g["dim"], tof=tof,
+                                      bins=bins.numpy(), per_ray=True)
+    assert np.array_equal(c2.cpu().numpy().astype(np.int64), per2)
