@@ -49,29 +49,32 @@ def parse():
     return ap.parse_args()
 
 
-def timed_pairs(fn_a, fn_b, reset, steps, warmup):
-    """Run reset, a, b per step; returns (wall seconds, mean ms of a, mean ms of b) over `steps`."""
+def timed_phases(phases, reset, steps, warmup):
+    """Per step: reset(), then each phase in turn, each bracketed by HIP events on the
+    current stream.  Returns (wall seconds over `steps`, [mean ms per phase])."""
     import torch
 
     for _ in range(warmup):
         reset()
-        fn_a()
-        fn_b()
+        for f in phases:
+            f()
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(phases) + 1)] for _ in range(steps)]
     t0 = time.perf_counter()
     for e in evs:
         reset()
         e[0].record()
-        fn_a()
-        e[1].record()
-        e[2].record()
-        fn_b()
-        e[3].record()
+        for j, f in enumerate(phases):
+            f()
+            e[j + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ta = sum(e[0].elapsed_time(e[1]) for e in evs) / steps
-    tb = sum(e[2].elapsed_time(e[3]) for e in evs) / steps
+    ms = [sum(e[j].elapsed_time(e[j + 1]) for e in evs) / steps for j in range(len(phases))]
+    return wall, ms
+
+
+def timed_pairs(fn_a, fn_b, reset, steps, warmup):
+    wall, (ta, tb) = timed_phases([fn_a, fn_b], reset, steps, warmup)
     return wall, ta, tb
 
 
@@ -94,17 +97,31 @@ def lm_leg(args, pp, C, dev):
     n_samples = int(pp.count_samples(xs, xe, G, bins, T).sum(dtype=torch.int64).item())
     p = torch.empty(n_ev, dtype=torch.float32, device=dev)
     bimg = torch.empty(grid.dim, dtype=torch.float32, device=dev)
-    wall, t_fwd, t_back = timed_pairs(lambda: pp.pp_fwd_tof_lm(xs, xe, bins, G, T, img, p),
-                                      lambda: pp.pp_back_tof_lm(xs, xe, bins, G, T, bimg, p),
-                                      lambda: pp.pp_fill(bimg, 0.0), args.steps, args.warmup)
-    log(f"TOF-LM: fwd {t_fwd:.2f} ms, back {t_back:.2f} ms, wall {1e3 * wall / args.steps:.2f} ms/step, "
+    order = torch.empty(n_ev, dtype=torch.int32, device=dev)
+    sort_ws = pp.presort_workspace(n_ev, dev)
+
+    # one step: presort the unsorted batch, forward project in that order, back project
+    wall, (t_sort, t_fwd, t_back) = timed_phases(
+        [lambda: pp.pp_lm_presort(xs, xe, bins, G, T, order, sort_ws),
+         lambda: pp.pp_fwd_tof_lm(xs, xe, bins, G, T, img, p, order),
+         lambda: pp.pp_back_tof_lm(xs, xe, bins, G, T, bimg, p, order)],
+        lambda: pp.pp_fill(bimg, 0.0), args.steps, args.warmup)
+    # the same projector pair in the events' own (unsorted) order (skipped when profiling the step)
+    t_fwd_u = t_back_u = float("nan")
+    if args.only is None:
+        _, t_fwd_u, t_back_u = timed_pairs(lambda: pp.pp_fwd_tof_lm(xs, xe, bins, G, T, img, p),
+                                           lambda: pp.pp_back_tof_lm(xs, xe, bins, G, T, bimg, p),
+                                           lambda: pp.pp_fill(bimg, 0.0), 2, 1)
+    log(f"TOF-LM: presort {t_sort:.2f} ms, fwd {t_fwd:.2f} ms, back {t_back:.2f} ms, wall "
+        f"{1e3 * wall / args.steps:.2f} ms/step; unsorted order: fwd {t_fwd_u:.2f} ms back {t_back_u:.2f} ms; "
         f"{n_samples / n_ev:.1f} samples/event")
     per_event = 24 + 2 + 4  # endpoints, bin, projection value
     alg_bytes = per_event * n_ev + 16 * n_samples
     dom_name, dom_ms = ("pp_back_tof_lm", t_back) if t_back >= t_fwd else ("pp_fwd_tof_lm", t_fwd)
     achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
     res = {
-        "n_events": n_ev, "wall_s": wall, "t_fwd_ms": t_fwd, "t_back_ms": t_back,
+        "n_events": n_ev, "wall_s": wall, "t_presort_ms": t_sort, "t_fwd_ms": t_fwd, "t_back_ms": t_back,
+        "unsorted_t_fwd_ms": t_fwd_u, "unsorted_t_back_ms": t_back_u,
         "samples_per_event": n_samples / n_ev, "alg_bytes_per_launch": alg_bytes,
         "dominant": dom_name, "achieved_gbs": achieved,
         "fwd_alg_gbs": alg_bytes / (t_fwd * 1e-3) / 1e9, "back_alg_gbs": alg_bytes / (t_back * 1e-3) / 1e9,
@@ -222,15 +239,15 @@ def main():
         "value": value, "unit": "events/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * lm["wall_s"] / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "TOF listmode fwd+back, 40M events, clinical phantom 215x215x71 @ 1.65x1.65x2.0 mm, "
-                               "29 TOF bins x 28 mm, FWHM 58.5 mm, 3 sigma",
+        "config": {"workload": "TOF listmode fwd+back, 40M unsorted events (step = presort + fwd + back), clinical "
+                               "phantom 215x215x71 @ 1.65x1.65x2.0 mm, 29 TOF bins x 28 mm, FWHM 58.5 mm, 3 sigma",
                    "n_events": lm["n_events"], "image": list(C.GRID_CLIN.dim), "tof_bins": C.TOF_CLIN.n_bins},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": lm["dominant"],
                      "alg_bytes_per_launch": lm["alg_bytes_per_launch"]},
         "cpu_baseline": cpu,
-        "lm": {k: lm[k] for k in ("t_fwd_ms", "t_back_ms", "samples_per_event", "fwd_alg_gbs",
-                                  "back_alg_gbs")},
+        "lm": {k: lm[k] for k in ("t_presort_ms", "t_fwd_ms", "t_back_ms", "unsorted_t_fwd_ms", "unsorted_t_back_ms",
+                                  "samples_per_event", "fwd_alg_gbs", "back_alg_gbs")},
     })
     result.update(extra)
     print(json.dumps(result), flush=True)

@@ -54,6 +54,7 @@
 #ifndef PPMI_H
 #define PPMI_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -87,13 +88,17 @@ typedef struct pp_tof {
 
 /* Non-TOF forward projection (Sec. 2.1, Fig. 1).
  * p[l] = ell_l * sum_k bilinear(img, plane k of ray l), l in [0, n_lors).
- * xstart, xend: [n_lors][3]; img: [dim0][dim1][dim2]; p: [n_lors] (overwritten). */
+ * xstart, xend: [n_lors][3]; img: [dim0][dim1][dim2]; p: [n_lors] (overwritten).
+ * order: NULL, or int32 [n_lors] -- the order in which rays are processed (a
+ * permutation of [0, n_lors), e.g. from pp_lm_presort; entries outside the
+ * range are skipped).  It changes speed, not results: outputs stay indexed
+ * by ray. */
 int pp_fwd(const float* xstart, const float* xend, int64_t n_lors, const pp_image_t* geom, const float* img,
-           float* p, void* stream);
+           float* p, const int32_t* order, void* stream);
 
 /* Non-TOF back projection, the exact adjoint of pp_fwd (Sec. 2.2): img += A^T p. */
 int pp_back(const float* xstart, const float* xend, int64_t n_lors, const pp_image_t* geom, float* img,
-            const float* p, void* stream);
+            const float* p, const int32_t* order, void* stream);
 
 /* TOF sinogram forward projection (Sec. 2.1, 2.2): all n_bins of every ray in
  * one traversal.  p: [n_lors][n_bins] (bin fastest), overwritten. */
@@ -109,11 +114,27 @@ int pp_back_tof_sino(const float* xstart, const float* xend, int64_t n_lors, con
  * visited (the weight is exactly zero elsewhere).  tof_bin: int16 [n_events];
  * p: [n_events], overwritten (0 for out-of-range bins). */
 int pp_fwd_tof_lm(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n_events,
-                  const pp_image_t* geom, const pp_tof_t* tof, const float* img, float* p, void* stream);
+                  const pp_image_t* geom, const pp_tof_t* tof, const float* img, float* p, const int32_t* order,
+                  void* stream);
 
 /* TOF listmode back projection, adjoint of pp_fwd_tof_lm: img += A^T p. */
 int pp_back_tof_lm(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n_events,
-                   const pp_image_t* geom, const pp_tof_t* tof, float* img, const float* p, void* stream);
+                   const pp_image_t* geom, const pp_tof_t* tof, float* img, const float* p, const int32_t* order,
+                   void* stream);
+
+/* Listmode presort (Sec. 4 of the paper suggests presorting listmode events
+ * to cut back-projection races): writes to `order` (int32 [n]) a permutation
+ * of [0, n) that groups events on the same or neighbouring LORs -- key:
+ * transaxial direction (axes 0, 1), transaxial distance from the grid centre,
+ * TOF bin (when tof_bin != NULL; tof then required), axial midpoint (axis 2);
+ * GPU radix sort.  Passing it as `order` to the listmode projections makes a
+ * wave's rays nearly coincident, so their gathers and atomic adds share cache
+ * lines.  workspace: device memory of pp_lm_presort_workspace_bytes(n) bytes,
+ * caller owned.  n <= 2^31 - 1. */
+size_t pp_lm_presort_workspace_bytes(int64_t n);
+int pp_lm_presort(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n,
+                  const pp_image_t* geom, const pp_tof_t* tof, int32_t* order, void* workspace,
+                  size_t workspace_bytes, void* stream);
 
 /* Work counter (for throughput accounting, not part of the method): counts[l]
  * = plane samples of ray l whose 2x2 stencil has at least one voxel inside

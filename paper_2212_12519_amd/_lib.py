@@ -107,12 +107,13 @@ def load():
     G = ctypes.POINTER(CImage)
     T = ctypes.POINTER(CTof)
     sig = {
-        "pp_fwd": [P, P, I64, G, P, P, P],
-        "pp_back": [P, P, I64, G, P, P, P],
+        "pp_fwd": [P, P, I64, G, P, P, P, P],
+        "pp_back": [P, P, I64, G, P, P, P, P],
         "pp_fwd_tof_sino": [P, P, I64, G, T, P, P, P],
         "pp_back_tof_sino": [P, P, I64, G, T, P, P, P],
-        "pp_fwd_tof_lm": [P, P, P, I64, G, T, P, P, P],
-        "pp_back_tof_lm": [P, P, P, I64, G, T, P, P, P],
+        "pp_fwd_tof_lm": [P, P, P, I64, G, T, P, P, P, P],
+        "pp_back_tof_lm": [P, P, P, I64, G, T, P, P, P, P],
+        "pp_lm_presort": [P, P, P, I64, G, T, P, P, ctypes.c_size_t, P],
         "pp_lm_osem_accumulate": [P, I32, G, T, P],
         "pp_lm_osem_update": [P, I32, I64, P],
         "pp_fill": [P, I64, ctypes.c_float, P],
@@ -122,6 +123,8 @@ def load():
         f = getattr(lib, name)
         f.argtypes = argt
         f.restype = INT
+    lib.pp_lm_presort_workspace_bytes.argtypes = [I64]
+    lib.pp_lm_presort_workspace_bytes.restype = ctypes.c_size_t
     lib.pp_osem_chunks.argtypes = [I64, I32]
     lib.pp_osem_chunks.restype = I64
     lib.pp_strerror.argtypes = [INT]
@@ -171,6 +174,13 @@ def _rays(xstart, xend):
 def _img(img, geom):
     if img.dtype != torch.float32 or img.numel() != geom.n_vox:
         raise ValueError(f"image must be float32 with {geom.n_vox} voxels")
+
+
+def _order(order, n):
+    if order is None:
+        return
+    if order.dtype != torch.int32 or order.numel() != n:
+        raise ValueError("order must be int32 [n]")
 
 
 def _bins(bins, n):

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 
 #include "joseph.hpp"
@@ -98,23 +99,23 @@ const char* pp_strerror(int code) {
 }
 
 int pp_fwd(const float* xstart, const float* xend, int64_t n, const pp_image_t* geom, const float* img, float* p,
-           void* stream) {
+           const int32_t* order, void* stream) {
     GeomK g;
     PP_TRY(make_geom(geom, g));
     PP_TRY(check_n(n));
     if (n == 0) return PP_OK;
     if (!xstart || !xend || !img || !p) return PP_EINVAL_PTR;
-    return hip_status(launch_fwd(xstart, xend, n, g, img, p, as_stream(stream)));
+    return hip_status(launch_fwd(xstart, xend, n, g, img, p, order, as_stream(stream)));
 }
 
 int pp_back(const float* xstart, const float* xend, int64_t n, const pp_image_t* geom, float* img, const float* p,
-            void* stream) {
+            const int32_t* order, void* stream) {
     GeomK g;
     PP_TRY(make_geom(geom, g));
     PP_TRY(check_n(n));
     if (n == 0) return PP_OK;
     if (!xstart || !xend || !img || !p) return PP_EINVAL_PTR;
-    return hip_status(launch_back(xstart, xend, n, g, img, p, as_stream(stream)));
+    return hip_status(launch_back(xstart, xend, n, g, img, p, order, as_stream(stream)));
 }
 
 int pp_fwd_tof_sino(const float* xstart, const float* xend, int64_t n, const pp_image_t* geom, const pp_tof_t* tof,
@@ -142,7 +143,7 @@ int pp_back_tof_sino(const float* xstart, const float* xend, int64_t n, const pp
 }
 
 int pp_fwd_tof_lm(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n, const pp_image_t* geom,
-                  const pp_tof_t* tof, const float* img, float* p, void* stream) {
+                  const pp_tof_t* tof, const float* img, float* p, const int32_t* order, void* stream) {
     GeomK g;
     TofK t;
     PP_TRY(make_geom(geom, g));
@@ -150,11 +151,11 @@ int pp_fwd_tof_lm(const float* xstart, const float* xend, const int16_t* tof_bin
     PP_TRY(check_n(n));
     if (n == 0) return PP_OK;
     if (!xstart || !xend || !tof_bin || !img || !p) return PP_EINVAL_PTR;
-    return hip_status(launch_fwd_tof_lm(xstart, xend, tof_bin, n, g, t, img, p, as_stream(stream)));
+    return hip_status(launch_fwd_tof_lm(xstart, xend, tof_bin, n, g, t, img, p, order, as_stream(stream)));
 }
 
 int pp_back_tof_lm(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n, const pp_image_t* geom,
-                   const pp_tof_t* tof, float* img, const float* p, void* stream) {
+                   const pp_tof_t* tof, float* img, const float* p, const int32_t* order, void* stream) {
     GeomK g;
     TofK t;
     PP_TRY(make_geom(geom, g));
@@ -162,7 +163,7 @@ int pp_back_tof_lm(const float* xstart, const float* xend, const int16_t* tof_bi
     PP_TRY(check_n(n));
     if (n == 0) return PP_OK;
     if (!xstart || !xend || !tof_bin || !img || !p) return PP_EINVAL_PTR;
-    return hip_status(launch_back_tof_lm(xstart, xend, tof_bin, n, g, t, img, p, as_stream(stream)));
+    return hip_status(launch_back_tof_lm(xstart, xend, tof_bin, n, g, t, img, p, order, as_stream(stream)));
 }
 
 int pp_count_samples(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n, const pp_image_t* geom,
@@ -175,6 +176,25 @@ int pp_count_samples(const float* xstart, const float* xend, const int16_t* tof_
     if (n == 0) return PP_OK;
     if (!xstart || !xend || !counts) return PP_EINVAL_PTR;
     return hip_status(launch_count(xstart, xend, tof_bin, n, g, t, counts, as_stream(stream)));
+}
+
+size_t pp_lm_presort_workspace_bytes(int64_t n) {
+    if (n <= 0 || n > INT32_MAX) return 0;
+    return presort_workspace_bytes(n);
+}
+
+int pp_lm_presort(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n, const pp_image_t* geom,
+                  const pp_tof_t* tof, int32_t* order, void* workspace, size_t workspace_bytes, void* stream) {
+    GeomK g;
+    TofK t{};
+    PP_TRY(make_geom(geom, g));
+    if (tof_bin) PP_TRY(make_tof(tof, t));
+    if (n < 0 || n > INT32_MAX) return PP_EINVAL_N;
+    if (n == 0) return PP_OK;
+    if (!xstart || !xend || !order || !workspace) return PP_EINVAL_PTR;
+    if (workspace_bytes < presort_workspace_bytes(n)) return PP_EINVAL_N;
+    return hip_status(launch_presort(xstart, xend, tof_bin, n, g, tof_bin ? t.nb : 1, order, workspace,
+                                     workspace_bytes, as_stream(stream)));
 }
 
 int64_t pp_osem_chunks(int64_t n_events, int32_t n_sub) { return osem_chunks(n_events, n_sub); }

@@ -13,6 +13,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <limits.h>
 #include <stdint.h>
 
 namespace ppmi {
@@ -41,6 +42,7 @@ struct RayK {
     int k_lo, k_hi; // planes to visit, inclusive (empty if k_lo > k_hi)
     int sp, su, sw; // element strides of axes p, u, w
     int nu, nw;     // grid size along u, w
+    int p;          // principal axis
     float ell;      // ray length per plane step, mm (incidence-angle correction)
 };
 
@@ -108,6 +110,7 @@ __device__ __forceinline__ bool ray_setup(const float* __restrict__ xs, const fl
     r.sw = g.stride[w];
     r.nu = g.n[u];
     r.nw = g.n[w];
+    r.p = p;
     // planes on the segment: t = (k - Sp) / Dp in [0, 1]
     const double ka = fmin(Sp, Sp + Dp), kb = fmax(Sp, Sp + Dp);
     int lo = 0, hi = g.n[p] - 1;
@@ -171,6 +174,49 @@ __device__ __forceinline__ void stencil_scatter(float* __restrict__ img, const R
     if (st.i1ok && st.j1ok) unsafeAtomicAdd(img + st.base + r.su + r.sw, st.fu * st.fw * c);
 }
 
+// Wave-cooperative version of stencil_scatter; every lane of the wave must
+// call it (inactive lanes with active == false).  Float atomics that hit the
+// same address within one instruction are serialised by the memory system,
+// which is exactly what nearly coincident rays of a wave produce.  Lanes are
+// therefore grouped into runs of equal stencil (same base voxel and principal
+// axis, adjacent in lane order); a segmented reduction over each run sums the
+// four weighted values into the run's first lane, and only that lane issues
+// the atomic adds.  Only the order of float additions changes.
+__device__ __forceinline__ void wave_stencil_scatter(float* __restrict__ img, bool active, const RayK& r,
+                                                     const Stencil& st, float c) {
+    const int lane = (int)__lane_id();
+    const float gu = 1.0f - st.fu, gw = 1.0f - st.fw;
+    float v00 = (active && st.i0ok && st.j0ok) ? gu * gw * c : 0.0f;
+    float v01 = (active && st.i0ok && st.j1ok) ? gu * st.fw * c : 0.0f;
+    float v10 = (active && st.i1ok && st.j0ok) ? st.fu * gw * c : 0.0f;
+    float v11 = (active && st.i1ok && st.j1ok) ? st.fu * st.fw * c : 0.0f;
+    active = active && (st.i0ok || st.i1ok) && (st.j0ok || st.j1ok);
+    const int kb = active ? st.base : (INT_MIN + lane);  // inactive lanes never match
+    const int kp = active ? r.p : -1;
+    const int pb = __shfl_up(kb, 1, 64), pp = __shfl_up(kp, 1, 64);
+    const bool head = lane == 0 || kb != pb || kp != pp;
+    const unsigned long long heads = __ballot(head);
+    const unsigned long long later = (lane == 63) ? 0ull : (heads & (~0ull << (lane + 1)));
+    const int run_end = later ? (__ffsll((long long)later) - 1) : 64;  // first lane of the next run
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const float a = __shfl_down(v00, off, 64), b = __shfl_down(v01, off, 64);
+        const float d = __shfl_down(v10, off, 64), e = __shfl_down(v11, off, 64);
+        if (lane + off < run_end) {
+            v00 += a;
+            v01 += b;
+            v10 += d;
+            v11 += e;
+        }
+    }
+    if (head && active) {
+        if (v00 != 0.0f) unsafeAtomicAdd(img + st.base, v00);
+        if (v01 != 0.0f) unsafeAtomicAdd(img + st.base + r.sw, v01);
+        if (v10 != 0.0f) unsafeAtomicAdd(img + st.base + r.su, v10);
+        if (v11 != 0.0f) unsafeAtomicAdd(img + st.base + r.su + r.sw, v11);
+    }
+}
+
 // G(x) = erf(clip(x, -trunc, trunc) / (sqrt(2) sigma)) / 2
 __device__ __forceinline__ float tof_cdf(double x, const TofK& t) {
     float xf = (float)x;
@@ -182,6 +228,19 @@ __device__ __forceinline__ float tof_cdf(double x, const TofK& t) {
 __device__ __forceinline__ float tof_weight(double s, double c, const TofK& t) {
     const double x = s - c;
     return tof_cdf(x + 0.5 * t.bw, t) - tof_cdf(x - 0.5 * t.bw, t);
+}
+
+// Wave-wide min / max (wave64; every lane of the wave must call it).
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
 }
 
 // XCD-aware block order: hardware hands consecutive workgroups to the 8 XCDs

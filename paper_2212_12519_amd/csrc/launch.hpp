@@ -12,17 +12,20 @@ struct GeomK;
 struct TofK;
 
 hipError_t launch_fwd(const float* xs, const float* xe, int64_t n, const GeomK& g, const float* img, float* p,
-                      hipStream_t s);
+                      const int32_t* order, hipStream_t s);
 hipError_t launch_back(const float* xs, const float* xe, int64_t n, const GeomK& g, float* img, const float* p,
-                       hipStream_t s);
+                       const int32_t* order, hipStream_t s);
 hipError_t launch_fwd_tof_sino(const float* xs, const float* xe, int64_t n, const GeomK& g, const TofK& t,
                                const float* img, float* p, hipStream_t s);
 hipError_t launch_back_tof_sino(const float* xs, const float* xe, int64_t n, const GeomK& g, const TofK& t,
                                 float* img, const float* p, hipStream_t s);
 hipError_t launch_fwd_tof_lm(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g,
-                             const TofK& t, const float* img, float* p, hipStream_t s);
+                             const TofK& t, const float* img, float* p, const int32_t* order, hipStream_t s);
 hipError_t launch_back_tof_lm(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g,
-                              const TofK& t, float* img, const float* p, hipStream_t s);
+                              const TofK& t, float* img, const float* p, const int32_t* order, hipStream_t s);
+size_t presort_workspace_bytes(int64_t n);
+hipError_t launch_presort(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g, int nb,
+                          int32_t* order, void* ws, size_t ws_bytes, hipStream_t s);
 
 hipError_t launch_count(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g,
                         const TofK& t, int32_t* counts, hipStream_t s);

@@ -12,11 +12,22 @@ constexpr int kBlock = 256;
 
 // ------------------------------------------------------------- non-TOF ----
 
+// Ray processed by this thread: position i of the processing order (identity,
+// or a permutation such as the one pp_lm_presort produces).  Entries outside
+// [0, n) are skipped.
+__device__ __forceinline__ int64_t ray_index(const int32_t* __restrict__ order, int64_t n) {
+    const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i >= n) return -1;
+    if (!order) return i;
+    const int64_t l = order[i];
+    return (l >= 0 && l < n) ? l : -1;
+}
+
 __global__ void __launch_bounds__(kBlock) k_fwd(const float* __restrict__ xs, const float* __restrict__ xe,
                                                 int64_t n, GeomK g, const float* __restrict__ img,
-                                                float* __restrict__ p) {
-    const int64_t l = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (l >= n) return;
+                                                float* __restrict__ p, const int32_t* __restrict__ order) {
+    const int64_t l = ray_index(order, n);
+    if (l < 0) return;
     RayK r;
     float acc = 0.0f;
     if (ray_setup(xs + 3 * l, xe + 3 * l, g, r)) {
@@ -28,15 +39,25 @@ __global__ void __launch_bounds__(kBlock) k_fwd(const float* __restrict__ xs, co
 
 __global__ void __launch_bounds__(kBlock) k_back(const float* __restrict__ xs, const float* __restrict__ xe,
                                                  int64_t n, GeomK g, float* __restrict__ img,
-                                                 const float* __restrict__ p) {
-    const int64_t l = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (l >= n) return;
-    const float pl = p[l];
-    if (pl == 0.0f) return;
+                                                 const float* __restrict__ p, const int32_t* __restrict__ order) {
+    const int64_t l = ray_index(order, n);
     RayK r;
-    if (!ray_setup(xs + 3 * l, xe + 3 * l, g, r)) return;
-    const float c = r.ell * pl;
-    for (int k = r.k_lo; k <= r.k_hi; ++k) stencil_scatter(img, r, stencil_at(r, k), c);
+    bool ok = l >= 0;
+    float c = 0.0f;
+    if (ok) {
+        const float pl = p[l];
+        ok = pl != 0.0f && ray_setup(xs + 3 * l, xe + 3 * l, g, r);
+        c = ok ? r.ell * pl : 0.0f;
+    }
+    // wave-synchronous plane order (see k_back_tof_lm)
+    const int lo = ok ? r.k_lo : (1 << 30), hi = ok ? r.k_hi : -(1 << 30);
+    const int k0 = wave_min(lo), k1 = wave_max(hi);
+    for (int k = k0; k <= k1; ++k) {
+        const bool act = k >= lo && k <= hi;
+        Stencil st{};
+        if (act) st = stencil_at(r, k);
+        wave_stencil_scatter(img, act, r, st, c);
+    }
 }
 
 // ------------------------------------------------------- TOF listmode ----
@@ -44,9 +65,9 @@ __global__ void __launch_bounds__(kBlock) k_back(const float* __restrict__ xs, c
 __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(const float* __restrict__ xs, const float* __restrict__ xe,
                                                        const int16_t* __restrict__ bins, int64_t n, GeomK g,
                                                        TofK t, const float* __restrict__ img,
-                                                       float* __restrict__ p) {
-    const int64_t l = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (l >= n) return;
+                                                       float* __restrict__ p, const int32_t* __restrict__ order) {
+    const int64_t l = ray_index(order, n);
+    if (l < 0) return;
     const int b = bins[l];
     float acc = 0.0f;
     RayK r;
@@ -63,23 +84,43 @@ __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(const float* __restrict__
     p[l] = acc;
 }
 
+// Scatter loop in wave-synchronous plane order: every lane of a wave steps
+// through the same absolute plane k (the union of the lanes' windows) and only
+// lanes whose window contains k add.  With presorted events a wave holds
+// nearly coincident rays, so at each k its atomic adds fall into one image
+// column and share cache lines -- float atomics are priced per cache-line
+// request, so this is what makes the back projection fast.
 __global__ void __launch_bounds__(kBlock) k_back_tof_lm(const float* __restrict__ xs, const float* __restrict__ xe,
                                                         const int16_t* __restrict__ bins, int64_t n, GeomK g,
                                                         TofK t, float* __restrict__ img,
-                                                        const float* __restrict__ p) {
-    const int64_t l = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (l >= n) return;
-    const int b = bins[l];
-    const float pl = p[l];
-    if (b < 0 || b >= t.nb || pl == 0.0f) return;
+                                                        const float* __restrict__ p,
+                                                        const int32_t* __restrict__ order) {
+    const int64_t l = ray_index(order, n);
     RayK r;
-    if (!ray_setup(xs + 3 * l, xe + 3 * l, g, r)) return;
-    const double c = t.c0 + b * t.bw;
-    if (!tof_window(r, c, t.win)) return;
-    const float cl = r.ell * pl;
-    for (int k = r.k_lo; k <= r.k_hi; ++k) {
-        const float w = tof_weight(fma((double)k, r.ds, r.s0), c, t);
-        if (w != 0.0f) stencil_scatter(img, r, stencil_at(r, k), w * cl);
+    bool ok = l >= 0;
+    double c = 0.0;
+    float cl = 0.0f;
+    if (ok) {
+        const int b = bins[l];
+        const float pl = p[l];
+        ok = b >= 0 && b < t.nb && pl != 0.0f && ray_setup(xs + 3 * l, xe + 3 * l, g, r);
+        if (ok) {
+            c = t.c0 + b * t.bw;
+            ok = tof_window(r, c, t.win);
+            cl = r.ell * pl;
+        }
+    }
+    const int lo = ok ? r.k_lo : (1 << 30), hi = ok ? r.k_hi : -(1 << 30);
+    const int k0 = wave_min(lo), k1 = wave_max(hi);
+    for (int k = k0; k <= k1; ++k) {
+        const bool act = k >= lo && k <= hi;
+        Stencil st{};
+        float v = 0.0f;
+        if (act) {
+            st = stencil_at(r, k);
+            v = tof_weight(fma((double)k, r.ds, r.s0), c, t) * cl;
+        }
+        wave_stencil_scatter(img, act && v != 0.0f, r, st, v);
     }
 }
 
@@ -150,27 +191,36 @@ __global__ void k_back_tof_sino(const float* __restrict__ xs, const float* __res
         lds[b * nt + ray] = in[i];
     }
     __syncthreads();
-    if (l >= n) return;
     RayK r;
-    if (!ray_setup(xs + 3 * l, xe + 3 * l, g, r)) return;
+    bool ok = l < n && ray_setup(xs + 3 * l, xe + 3 * l, g, r);
     const float* mine = lds + threadIdx.x;
-    bool any = false;
-    for (int b = 0; b < t.nb; ++b) any |= (mine[b * nt] != 0.0f);
-    if (!any) return;
-    const float ell = r.ell;
-    for (int k = r.k_lo; k <= r.k_hi; ++k) {
-        const double s = fma((double)k, r.ds, r.s0);
-        int b_lo, b_hi;
-        tof_bin_range(s, t, b_lo, b_hi);
-        const double x_hi0 = s - (t.c0 + b_lo * t.bw) + 0.5 * t.bw;
-        float g_hi = tof_cdf(x_hi0, t);
+    if (ok) {
+        bool any = false;
+        for (int b = 0; b < t.nb; ++b) any |= (mine[b * nt] != 0.0f);
+        ok = any;
+    }
+    // wave-synchronous plane loop with run-combined atomics (see k_back_tof_lm)
+    const int lo = ok ? r.k_lo : (1 << 30), hi = ok ? r.k_hi : -(1 << 30);
+    const int k0 = wave_min(lo), k1 = wave_max(hi);
+    for (int k = k0; k <= k1; ++k) {
+        const bool act = k >= lo && k <= hi;
+        Stencil st{};
         float c = 0.0f;
-        for (int b = b_lo; b <= b_hi; ++b) {
-            const float g_lo = tof_cdf(x_hi0 - (double)(b - b_lo + 1) * t.bw, t);
-            c += (g_hi - g_lo) * mine[b * nt];
-            g_hi = g_lo;
+        if (act) {
+            const double s = fma((double)k, r.ds, r.s0);
+            int b_lo, b_hi;
+            tof_bin_range(s, t, b_lo, b_hi);
+            const double x_hi0 = s - (t.c0 + b_lo * t.bw) + 0.5 * t.bw;
+            float g_hi = tof_cdf(x_hi0, t);
+            for (int b = b_lo; b <= b_hi; ++b) {
+                const float g_lo = tof_cdf(x_hi0 - (double)(b - b_lo + 1) * t.bw, t);
+                c += (g_hi - g_lo) * mine[b * nt];
+                g_hi = g_lo;
+            }
+            c *= r.ell;
+            st = stencil_at(r, k);
         }
-        if (c != 0.0f) stencil_scatter(img, r, stencil_at(r, k), ell * c);
+        wave_stencil_scatter(img, act && c != 0.0f, r, st, c);
     }
 }
 
@@ -211,26 +261,28 @@ __global__ void __launch_bounds__(kBlock) k_count(const float* __restrict__ xs, 
 static unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
 hipError_t launch_fwd(const float* xs, const float* xe, int64_t n, const GeomK& g, const float* img, float* p,
-                      hipStream_t s) {
-    hipLaunchKernelGGL(k_fwd, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, xs, xe, n, g, img, p);
+                      const int32_t* order, hipStream_t s) {
+    hipLaunchKernelGGL(k_fwd, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, xs, xe, n, g, img, p, order);
     return hipGetLastError();
 }
 
 hipError_t launch_back(const float* xs, const float* xe, int64_t n, const GeomK& g, float* img, const float* p,
-                       hipStream_t s) {
-    hipLaunchKernelGGL(k_back, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, xs, xe, n, g, img, p);
+                       const int32_t* order, hipStream_t s) {
+    hipLaunchKernelGGL(k_back, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, xs, xe, n, g, img, p, order);
     return hipGetLastError();
 }
 
 hipError_t launch_fwd_tof_lm(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g,
-                             const TofK& t, const float* img, float* p, hipStream_t s) {
-    hipLaunchKernelGGL(k_fwd_tof_lm, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, xs, xe, bins, n, g, t, img, p);
+                             const TofK& t, const float* img, float* p, const int32_t* order, hipStream_t s) {
+    hipLaunchKernelGGL(k_fwd_tof_lm, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, xs, xe, bins, n, g, t, img, p,
+                       order);
     return hipGetLastError();
 }
 
 hipError_t launch_back_tof_lm(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g,
-                              const TofK& t, float* img, const float* p, hipStream_t s) {
-    hipLaunchKernelGGL(k_back_tof_lm, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, xs, xe, bins, n, g, t, img, p);
+                              const TofK& t, float* img, const float* p, const int32_t* order, hipStream_t s) {
+    hipLaunchKernelGGL(k_back_tof_lm, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, xs, xe, bins, n, g, t, img, p,
+                       order);
     return hipGetLastError();
 }
 

@@ -8,30 +8,32 @@ from __future__ import annotations
 
 import torch
 
-from ._lib import _bins, _dev, _img, _rays, as_geom, as_tof, check, load, ptr, stream_of
+from ._lib import _bins, _dev, _img, _order, _rays, as_geom, as_tof, check, load, ptr, stream_of
 
-def pp_fwd(xstart, xend, geom, img, p):
-    """Non-TOF forward projection into p[n] (overwritten). Sec. 2.1 of the paper."""
+def pp_fwd(xstart, xend, geom, img, p, order=None):
+    """Non-TOF forward projection into p[n] (overwritten). Sec. 2.1 of the paper.
+    order: optional int32 processing order (pp_lm_presort); results stay indexed by ray."""
     g = as_geom(geom)
-    _dev(xstart, xend, img, p)
+    _dev(xstart, xend, img, p, order)
     n = _rays(xstart, xend)
     _img(img, g)
+    _order(order, n)
     if p.dtype != torch.float32 or p.numel() != n:
         raise ValueError("p must be float32 [n]")
-    gc = g.c()
-    check(load().pp_fwd(ptr(xstart), ptr(xend), n, gc, ptr(img), ptr(p), stream_of(p)))
+    check(load().pp_fwd(ptr(xstart), ptr(xend), n, g.c(), ptr(img), ptr(p), ptr(order), stream_of(p)))
     return p
 
 
-def pp_back(xstart, xend, geom, img, p):
+def pp_back(xstart, xend, geom, img, p, order=None):
     """Non-TOF back projection, img += A^T p (adjoint of pp_fwd)."""
     g = as_geom(geom)
-    _dev(xstart, xend, img, p)
+    _dev(xstart, xend, img, p, order)
     n = _rays(xstart, xend)
     _img(img, g)
+    _order(order, n)
     if p.dtype != torch.float32 or p.numel() != n:
         raise ValueError("p must be float32 [n]")
-    check(load().pp_back(ptr(xstart), ptr(xend), n, g.c(), ptr(img), ptr(p), stream_of(img)))
+    check(load().pp_back(ptr(xstart), ptr(xend), n, g.c(), ptr(img), ptr(p), ptr(order), stream_of(img)))
     return img
 
 
@@ -59,32 +61,62 @@ def pp_back_tof_sino(xstart, xend, geom, tof, img, p):
     return img
 
 
-def pp_fwd_tof_lm(xstart, xend, tof_bin, geom, tof, img, p):
+def pp_fwd_tof_lm(xstart, xend, tof_bin, geom, tof, img, p, order=None):
     """TOF listmode forward projection (event's bin only) into p[n] (overwritten)."""
     g, t = as_geom(geom), as_tof(tof)
-    _dev(xstart, xend, tof_bin, img, p)
+    _dev(xstart, xend, tof_bin, img, p, order)
     n = _rays(xstart, xend)
     _bins(tof_bin, n)
     _img(img, g)
+    _order(order, n)
     if p.dtype != torch.float32 or p.numel() != n:
         raise ValueError("p must be float32 [n]")
     check(load().pp_fwd_tof_lm(ptr(xstart), ptr(xend), ptr(tof_bin), n, g.c(), t.c(), ptr(img), ptr(p),
-                               stream_of(p)))
+                               ptr(order), stream_of(p)))
     return p
 
 
-def pp_back_tof_lm(xstart, xend, tof_bin, geom, tof, img, p):
+def pp_back_tof_lm(xstart, xend, tof_bin, geom, tof, img, p, order=None):
     """TOF listmode back projection, img += A^T p."""
     g, t = as_geom(geom), as_tof(tof)
-    _dev(xstart, xend, tof_bin, img, p)
+    _dev(xstart, xend, tof_bin, img, p, order)
     n = _rays(xstart, xend)
     _bins(tof_bin, n)
     _img(img, g)
+    _order(order, n)
     if p.dtype != torch.float32 or p.numel() != n:
         raise ValueError("p must be float32 [n]")
     check(load().pp_back_tof_lm(ptr(xstart), ptr(xend), ptr(tof_bin), n, g.c(), t.c(), ptr(img), ptr(p),
-                                stream_of(img)))
+                                ptr(order), stream_of(img)))
     return img
+
+
+def presort_workspace(n, device):
+    """A byte tensor large enough for pp_lm_presort of n events."""
+    nbytes = int(load().pp_lm_presort_workspace_bytes(int(n)))
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+
+
+def pp_lm_presort(xstart, xend, tof_bin, geom, tof, order, workspace):
+    """Processing order that groups events on neighbouring LORs (see ppmi.h)."""
+    g = as_geom(geom)
+    _dev(xstart, xend, tof_bin, order, workspace)
+    n = _rays(xstart, xend)
+    _order(order, n)
+    tc = None
+    if tof_bin is not None:
+        _bins(tof_bin, n)
+        tc = as_tof(tof).c()
+    check(load().pp_lm_presort(ptr(xstart), ptr(xend), ptr(tof_bin), n, g.c(), tc, ptr(order), ptr(workspace),
+                               workspace.numel() * workspace.element_size(), stream_of(order)))
+    return order
+
+
+def presort(xstart, xend, geom, tof_bin=None, tof=None):
+    order = torch.empty(xstart.shape[0], dtype=torch.int32, device=xstart.device)
+    if xstart.shape[0] == 0:
+        return order
+    return pp_lm_presort(xstart, xend, tof_bin, geom, tof, order, presort_workspace(xstart.shape[0], xstart.device))
 
 
 def pp_fill(dst, value):
@@ -119,16 +151,16 @@ def count_samples(xstart, xend, geom, tof_bin=None, tof=None):
 
 # ------------------------------------------------------------- conveniences
 
-def fwd(xstart, xend, geom, img):
+def fwd(xstart, xend, geom, img, order=None):
     p = torch.empty(xstart.shape[0], dtype=torch.float32, device=xstart.device)
-    return pp_fwd(xstart, xend, geom, img, p)
+    return pp_fwd(xstart, xend, geom, img, p, order)
 
 
-def back(xstart, xend, geom, p, img=None):
+def back(xstart, xend, geom, p, img=None, order=None):
     g = as_geom(geom)
     if img is None:
         img = torch.zeros(g.dim, dtype=torch.float32, device=xstart.device)
-    return pp_back(xstart, xend, g, img, p)
+    return pp_back(xstart, xend, g, img, p, order)
 
 
 def fwd_tof_sino(xstart, xend, geom, tof, img):
@@ -144,13 +176,13 @@ def back_tof_sino(xstart, xend, geom, tof, p, img=None):
     return pp_back_tof_sino(xstart, xend, g, tof, img, p)
 
 
-def fwd_tof_lm(xstart, xend, tof_bin, geom, tof, img):
+def fwd_tof_lm(xstart, xend, tof_bin, geom, tof, img, order=None):
     p = torch.empty(xstart.shape[0], dtype=torch.float32, device=xstart.device)
-    return pp_fwd_tof_lm(xstart, xend, tof_bin, geom, tof, img, p)
+    return pp_fwd_tof_lm(xstart, xend, tof_bin, geom, tof, img, p, order)
 
 
-def back_tof_lm(xstart, xend, tof_bin, geom, tof, p, img=None):
+def back_tof_lm(xstart, xend, tof_bin, geom, tof, p, img=None, order=None):
     g = as_geom(geom)
     if img is None:
         img = torch.zeros(g.dim, dtype=torch.float32, device=xstart.device)
-    return pp_back_tof_lm(xstart, xend, tof_bin, g, tof, img, p)
+    return pp_back_tof_lm(xstart, xend, tof_bin, g, tof, img, p, order)

@@ -323,3 +323,33 @@ def test_work_counter_matches_oracle(gpu, small):
     tot2, per2 = oracle.count_samples(exs.numpy(), exe.numpy(), g["origin"], g["voxsize"], g["dim"], tof=tof,
                                       bins=bins.numpy(), per_ray=True)
     assert np.array_equal(c2.cpu().numpy().astype(np.int64), per2)
+
+
+def test_presort_order(gpu, lm40):
+    """pp_lm_presort returns a permutation; projecting in that order gives bit-identical forward
+    projections (each ray's sum does not depend on the order) and the same back projection up to
+    float summation order, on the full 40M-event workload."""
+    xs, xe, bins, img = lm40
+    g = geom_of(C.GRID_CLIN)
+    G = gpu.ImageGeom(g["dim"], g["voxsize"], g["origin"])
+    tof = tof_of(C.TOF_CLIN)
+    T = gpu.TofParams(tof["bin_width"], tof["sigma"], tof["n_sigmas"], tof["n_bins"])
+    order = gpu.presort(xs, xe, G, bins, T)
+    srt, _ = torch.sort(order.long())
+    assert torch.equal(srt, torch.arange(xs.shape[0], device=xs.device))
+    p0 = gpu.fwd_tof_lm(xs, xe, bins, G, T, img)
+    p1 = gpu.fwd_tof_lm(xs, xe, bins, G, T, img, order=order)
+    assert torch.equal(p0, p1)
+    b0 = gpu.back_tof_lm(xs, xe, bins, G, T, p0)
+    b1 = gpu.back_tof_lm(xs, xe, bins, G, T, p0, order=order)
+    assert rel_l2(np64(b1), np64(b0)) <= 1e-5
+    # non-TOF projections of the same events, in presorted order
+    o2 = gpu.presort(xs, xe, G)
+    assert torch.equal(gpu.fwd(xs, xe, G, img, order=o2), gpu.fwd(xs, xe, G, img))
+    m = 200_000
+    y = torch.rand(m, device=xs.device)
+    bm = gpu.back(xs[:m].contiguous(), xe[:m].contiguous(), G, y, order=gpu.presort(xs[:m].contiguous(),
+                                                                                 xe[:m].contiguous(), G))
+    ref = oracle.back(xs[:m].cpu().numpy(), xe[:m].cpu().numpy(), g["origin"], g["voxsize"], g["dim"],
+                      y.cpu().numpy())
+    assert rel_l2(np64(bm), ref) <= BACK_TOL
