@@ -125,16 +125,24 @@ int pp_back_tof_lm(const float* xstart, const float* xend, const int16_t* tof_bi
 /* Listmode presort (Sec. 4 of the paper suggests presorting listmode events
  * to cut back-projection races): writes to `order` (int32 [n]) a permutation
  * of [0, n) that groups events on the same or neighbouring LORs -- key:
- * transaxial direction (axes 0, 1), transaxial distance from the grid centre,
- * TOF bin (when tof_bin != NULL; tof then required), axial midpoint (axis 2);
- * GPU radix sort.  Passing it as `order` to the listmode projections makes a
+ * OSEM subset (event index mod n_sub; use n_sub = 1 for none), transaxial
+ * direction (axes 0, 1), transaxial distance from the grid centre, TOF bin
+ * (when tof_bin != NULL; tof then required), axial midpoint (axis 2); GPU
+ * radix sort.  Passing it as `order` to the listmode projections makes a
  * wave's rays nearly coincident, so their gathers and atomic adds share cache
- * lines.  workspace: device memory of pp_lm_presort_workspace_bytes(n) bytes,
- * caller owned.  n <= 2^31 - 1. */
+ * lines.  With n_sub > 1 the order is subset-major (see the OSEM section).
+ * workspace: device memory of pp_lm_presort_workspace_bytes(n) bytes, caller
+ * owned.  n <= 2^31 - 1, 1 <= n_sub <= 4096. */
 size_t pp_lm_presort_workspace_bytes(int64_t n);
 int pp_lm_presort(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n,
-                  const pp_image_t* geom, const pp_tof_t* tof, int32_t* order, void* workspace,
+                  const pp_image_t* geom, const pp_tof_t* tof, int32_t n_sub, int32_t* order, void* workspace,
                   size_t workspace_bytes, void* stream);
+
+/* Reorders event arrays: out[i] = in[order[i]] (tof_bin / tof_bin_out may be
+ * NULL together).  In and out must not overlap.  Entries of order outside
+ * [0, n) copy event i unchanged. */
+int pp_gather_events(const float* xstart, const float* xend, const int16_t* tof_bin, const int32_t* order,
+                     int64_t n, float* xstart_out, float* xend_out, int16_t* tof_bin_out, void* stream);
 
 /* Work counter (for throughput accounting, not part of the method): counts[l]
  * = plane samples of ray l whose 2x2 stencil has at least one voxel inside
@@ -152,6 +160,10 @@ int pp_count_samples(const float* xstart, const float* xend, const int16_t* tof_
  *     x_v <- x_v * acc_v / (sens_v / n_sub) if sens_v > 0, else 0;  acc <- 0
  *                                                           (pp_lm_osem_update)
  * An event whose expectation a_e . x + bg is not positive contributes nothing.
+ * Event storage of a frame is SUBSET-MAJOR: subset j occupies the contiguous
+ * range [off_j, off_j + n_j), n_j = n / n_sub + (j < n mod n_sub),
+ * off_j = j (n / n_sub) + min(j, n mod n_sub), in any order inside the range
+ * (pp_lm_presort with n_sub, then pp_gather_events, produces exactly this).
  * The slot table lives in DEVICE memory and is read by the kernels at run
  * time, so one captured graph of steps serves any mix of frames: the host
  * rewrites slots between replays.  pp_lm_osem_update advances `subset`
@@ -192,6 +204,9 @@ int pp_lm_osem_accumulate(const pp_osem_slot_t* d_slots, int32_t n_slots, const 
 /* Multiplicative image update of every live slot, then acc <- 0, subset
  * advanced, steps_left decremented.  n_vox must equal the grid's voxel count. */
 int pp_lm_osem_update(pp_osem_slot_t* d_slots, int32_t n_slots, int64_t n_vox, void* stream);
+
+/* OSEM start image: x_v = 1 where sens_v > 0, else 0. */
+int pp_osem_init(float* x, const float* sens, int64_t n_vox, void* stream);
 
 /* Sets n floats at dst to value (a kernel, safe inside captured graphs). */
 int pp_fill(float* dst, int64_t n, float value, void* stream);

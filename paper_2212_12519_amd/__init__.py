@@ -6,7 +6,8 @@ include/ppmi.h); this package is its Python binding plus the autograd
 wrappers and the OSEM serving loop built on it.
 """
 from ._lib import ImageGeom, PPError, TofParams, load
-from .projectors import (back, count_samples, pp_lm_presort, presort, presort_workspace, pp_count_samples, back_tof_lm, back_tof_sino, fwd, fwd_tof_lm, fwd_tof_sino, pp_back,
+from .projectors import (back, count_samples, gather_events, pp_gather_events, pp_lm_presort, presort,
+                         presort_workspace, pp_count_samples, back_tof_lm, back_tof_sino, fwd, fwd_tof_lm, fwd_tof_sino, pp_back,
                          pp_back_tof_lm, pp_back_tof_sino, pp_fill, pp_fwd, pp_fwd_tof_lm, pp_fwd_tof_sino)
 
 __all__ = [

@@ -113,7 +113,9 @@ def load():
         "pp_back_tof_sino": [P, P, I64, G, T, P, P, P],
         "pp_fwd_tof_lm": [P, P, P, I64, G, T, P, P, P, P],
         "pp_back_tof_lm": [P, P, P, I64, G, T, P, P, P, P],
-        "pp_lm_presort": [P, P, P, I64, G, T, P, P, ctypes.c_size_t, P],
+        "pp_lm_presort": [P, P, P, I64, G, T, I32, P, P, ctypes.c_size_t, P],
+        "pp_gather_events": [P, P, P, P, I64, P, P, P, P],
+        "pp_osem_init": [P, P, I64, P],
         "pp_lm_osem_accumulate": [P, I32, G, T, P],
         "pp_lm_osem_update": [P, I32, I64, P],
         "pp_fill": [P, I64, ctypes.c_float, P],

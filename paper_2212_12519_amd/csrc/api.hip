@@ -184,17 +184,34 @@ size_t pp_lm_presort_workspace_bytes(int64_t n) {
 }
 
 int pp_lm_presort(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n, const pp_image_t* geom,
-                  const pp_tof_t* tof, int32_t* order, void* workspace, size_t workspace_bytes, void* stream) {
+                  const pp_tof_t* tof, int32_t n_sub, int32_t* order, void* workspace, size_t workspace_bytes,
+                  void* stream) {
     GeomK g;
     TofK t{};
     PP_TRY(make_geom(geom, g));
     if (tof_bin) PP_TRY(make_tof(tof, t));
-    if (n < 0 || n > INT32_MAX) return PP_EINVAL_N;
+    if (n < 0 || n > INT32_MAX || n_sub < 1 || n_sub > 4096) return PP_EINVAL_N;
     if (n == 0) return PP_OK;
     if (!xstart || !xend || !order || !workspace) return PP_EINVAL_PTR;
     if (workspace_bytes < presort_workspace_bytes(n)) return PP_EINVAL_N;
-    return hip_status(launch_presort(xstart, xend, tof_bin, n, g, tof_bin ? t.nb : 1, order, workspace,
+    return hip_status(launch_presort(xstart, xend, tof_bin, n, g, tof_bin ? t.nb : 1, n_sub, order, workspace,
                                      workspace_bytes, as_stream(stream)));
+}
+
+int pp_gather_events(const float* xstart, const float* xend, const int16_t* tof_bin, const int32_t* order, int64_t n,
+                     float* xstart_out, float* xend_out, int16_t* tof_bin_out, void* stream) {
+    if (n < 0 || n > INT32_MAX) return PP_EINVAL_N;
+    if (n == 0) return PP_OK;
+    if (!xstart || !xend || !order || !xstart_out || !xend_out || (tof_bin && !tof_bin_out)) return PP_EINVAL_PTR;
+    return hip_status(launch_gather_events(xstart, xend, tof_bin, order, n, xstart_out, xend_out, tof_bin_out,
+                                           as_stream(stream)));
+}
+
+int pp_osem_init(float* x, const float* sens, int64_t n_vox, void* stream) {
+    if (n_vox < 0 || n_vox > (int64_t(1) << 30)) return PP_EINVAL_N;
+    if (n_vox == 0) return PP_OK;
+    if (!x || !sens) return PP_EINVAL_PTR;
+    return hip_status(launch_osem_init(x, sens, n_vox, as_stream(stream)));
 }
 
 int64_t pp_osem_chunks(int64_t n_events, int32_t n_sub) { return osem_chunks(n_events, n_sub); }

@@ -25,7 +25,10 @@ hipError_t launch_back_tof_lm(const float* xs, const float* xe, const int16_t* b
                               const TofK& t, float* img, const float* p, const int32_t* order, hipStream_t s);
 size_t presort_workspace_bytes(int64_t n);
 hipError_t launch_presort(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g, int nb,
-                          int32_t* order, void* ws, size_t ws_bytes, hipStream_t s);
+                          int n_sub, int32_t* order, void* ws, size_t ws_bytes, hipStream_t s);
+hipError_t launch_gather_events(const float* xs, const float* xe, const int16_t* bins, const int32_t* order, int64_t n,
+                                float* xs_out, float* xe_out, int16_t* bins_out, hipStream_t s);
+hipError_t launch_osem_init(float* x, const float* sens, int64_t n_vox, hipStream_t s);
 
 hipError_t launch_count(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g,
                         const TofK& t, int32_t* counts, hipStream_t s);

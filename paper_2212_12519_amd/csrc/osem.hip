@@ -1,11 +1,18 @@
 // Batched listmode TOF OSEM on device-resident frames (the paper's listmode
 // OSEM of Sec. 2.6, run for many frames at once).
 //
+// Event storage of a frame is subset-major: subset j (the events whose index
+// in the frame is j mod n_sub) occupies the contiguous range
+// [off_j, off_j + n_j) with n_j = n / n_sub + (j < n mod n_sub) and
+// off_j = j * (n / n_sub) + min(j, n mod n_sub); inside a subset the events
+// may be in any order (pp_lm_presort with n_sub groups them by LOR).
+//
 // k_osem_accumulate: one persistent grid walks the work chunks of all live
-// slots (a chunk = 256 events of one slot's current subset); each thread
-// projects its event forward through the slot's image, forms 1 / (ybar) and
-// back projects it into the slot's accumulator -- forward, ratio and back
-// projection fused, the event's coordinates read once.
+// slots (a chunk = 256 consecutive events of one slot's current subset); each
+// lane projects its event forward through the slot's image, forms
+// ell / ybar and back projects it into the slot's accumulator -- forward,
+// ratio and back projection fused, the event set up once.  The scatter uses
+// the wave-synchronous plane loop with run-combined atomics.
 // k_osem_update: x <- x * acc / (sens / n_sub) (0 where sens == 0), acc <- 0.
 // k_osem_advance: next subset, one step fewer.
 #include <hip/hip_runtime.h>
@@ -30,36 +37,55 @@ __global__ void __launch_bounds__(kOsemBlock) k_osem_accumulate(const pp_osem_sl
     const pp_osem_slot_t& last = slots[n_slots - 1];
     const int64_t total = last.chunk_begin + (last.active ? slot_chunks(last.n_events, last.n_sub) : 0);
     for (int64_t c = xcd_block(blockIdx.x, gridDim.x); c < total; c += gridDim.x) {
-        // largest slot index whose first chunk is <= c
-        int lo = 0, hi = n_slots - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (slots[mid].chunk_begin <= c) lo = mid; else hi = mid - 1;
+        // largest slot index whose first chunk is <= c (block-uniform)
+        int lo_s = 0, hi_s = n_slots - 1;
+        while (lo_s < hi_s) {
+            const int mid = (lo_s + hi_s + 1) >> 1;
+            if (slots[mid].chunk_begin <= c) lo_s = mid; else hi_s = mid - 1;
         }
-        const pp_osem_slot_t& s = slots[lo];
-        if (!slot_live(s)) continue;
+        const pp_osem_slot_t& s = slots[lo_s];
+        if (!slot_live(s)) continue;  // block-uniform
+        const int64_t n = s.n_events, ns = s.n_sub, j = s.subset;
+        const int64_t base_n = n / ns, rem = n - base_n * ns;
+        const int64_t n_j = base_n + (j < rem ? 1 : 0);
+        const int64_t off_j = j * base_n + (j < rem ? j : rem);
         const int64_t q = (c - s.chunk_begin) * kOsemBlock + threadIdx.x;
-        const int64_t e = (int64_t)s.subset + q * s.n_sub;
-        if (e >= s.n_events) continue;
-        const int b = s.tof_bin[e];
-        if (b < 0 || b >= t.nb) continue;
         RayK r;
-        if (!ray_setup(s.xstart + 3 * e, s.xend + 3 * e, g, r)) continue;
-        const double centre = t.c0 + b * t.bw;
-        if (!tof_window(r, centre, t.win)) continue;
-        const float* __restrict__ x = s.x;
-        float fwd = 0.0f;
-        for (int k = r.k_lo; k <= r.k_hi; ++k) {
-            const float w = tof_weight(fma((double)k, r.ds, r.s0), centre, t);
-            fwd += w * stencil_gather(x, r, stencil_at(r, k));
+        bool ok = q < n_j;
+        const int64_t e = off_j + q;
+        double centre = 0.0;
+        if (ok) {
+            const int b = s.tof_bin[e];
+            ok = b >= 0 && b < t.nb && ray_setup(s.xstart + 3 * e, s.xend + 3 * e, g, r);
+            if (ok) {
+                centre = t.c0 + b * t.bw;
+                ok = tof_window(r, centre, t.win);
+            }
         }
-        const float ybar = r.ell * fwd + s.bg;
-        if (!(ybar > 0.0f)) continue;
-        const float cl = r.ell / ybar;
+        float cl = 0.0f;
+        if (ok) {
+            const float* __restrict__ x = s.x;
+            float fwd = 0.0f;
+            for (int k = r.k_lo; k <= r.k_hi; ++k) {
+                const float w = tof_weight(fma((double)k, r.ds, r.s0), centre, t);
+                fwd += w * stencil_gather(x, r, stencil_at(r, k));
+            }
+            const float ybar = r.ell * fwd + s.bg;
+            ok = ybar > 0.0f;
+            cl = ok ? r.ell / ybar : 0.0f;
+        }
+        const int lo = ok ? r.k_lo : (1 << 30), hi = ok ? r.k_hi : -(1 << 30);
+        const int k0 = wave_min(lo), k1 = wave_max(hi);
         float* __restrict__ acc = s.acc;
-        for (int k = r.k_lo; k <= r.k_hi; ++k) {
-            const float w = tof_weight(fma((double)k, r.ds, r.s0), centre, t);
-            if (w != 0.0f) stencil_scatter(acc, r, stencil_at(r, k), w * cl);
+        for (int k = k0; k <= k1; ++k) {
+            const bool act = k >= lo && k <= hi;
+            Stencil st{};
+            float v = 0.0f;
+            if (act) {
+                st = stencil_at(r, k);
+                v = tof_weight(fma((double)k, r.ds, r.s0), centre, t) * cl;
+            }
+            wave_stencil_scatter(acc, act && v != 0.0f, r, st, v);
         }
     }
 }
@@ -89,6 +115,12 @@ __global__ void k_osem_advance(pp_osem_slot_t* slots, int n_slots) {
     }
 }
 
+__global__ void k_osem_init(float* __restrict__ x, const float* __restrict__ sens, int64_t n_vox) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_vox; i += stride)
+        x[i] = sens[i] > 0.0f ? 1.0f : 0.0f;
+}
+
 __global__ void k_fill(float* __restrict__ dst, int64_t n, float value) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = value;
@@ -110,10 +142,18 @@ hipError_t launch_osem_update(pp_osem_slot_t* slots, int n_slots, int64_t n_vox,
     return hipGetLastError();
 }
 
-hipError_t launch_fill(float* dst, int64_t n, float value, hipStream_t s) {
+static unsigned fill_blocks(int64_t n) {
     int64_t blocks = (n + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, s, dst, n, value);
+    return (unsigned)(blocks > 8192 ? 8192 : blocks);
+}
+
+hipError_t launch_osem_init(float* x, const float* sens, int64_t n_vox, hipStream_t s) {
+    hipLaunchKernelGGL(k_osem_init, dim3(fill_blocks(n_vox)), dim3(256), 0, s, x, sens, n_vox);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(float* dst, int64_t n, float value, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill, dim3(fill_blocks(n)), dim3(256), 0, s, dst, n, value);
     return hipGetLastError();
 }
 

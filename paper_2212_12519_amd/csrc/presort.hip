@@ -8,7 +8,8 @@
 // races in the back projection; the order changes nothing but the summation
 // order of floats.
 //
-// Key (32 bits, most significant first):
+// Key (64 bits, most significant first):
+//   32 bits  OSEM subset of the event (index mod n_sub; 0 when n_sub == 1)
 //   10 bits  transaxial direction angle of the LOR in [0, pi)   (axes 0, 1)
 //   10 bits  signed transaxial distance of the LOR from the grid centre
 //    5 bits  TOF bin (scaled to 32 levels)
@@ -31,14 +32,15 @@ struct KeyGeom {
 
 __global__ void __launch_bounds__(256) k_lm_keys(const float* __restrict__ xs, const float* __restrict__ xe,
                                                  const int16_t* __restrict__ bins, int64_t n, KeyGeom kg, int nb,
-                                                 uint32_t* __restrict__ keys, int32_t* __restrict__ idx) {
+                                                 int n_sub, uint64_t* __restrict__ keys, int32_t* __restrict__ idx) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     idx[i] = (int32_t)i;
+    const uint64_t sub = (uint64_t)(i % n_sub) << 32;
     const float sx = xs[3 * i], sy = xs[3 * i + 1], sz = xs[3 * i + 2];
     const float ex = xe[3 * i], ey = xe[3 * i + 1], ez = xe[3 * i + 2];
     if (!(isfinite(sx) && isfinite(sy) && isfinite(sz) && isfinite(ex) && isfinite(ey) && isfinite(ez))) {
-        keys[i] = 0xffffffffu;
+        keys[i] = sub | 0xffffffffull;
         return;
     }
     const float pi = 3.14159265358979f;
@@ -57,32 +59,38 @@ __global__ void __launch_bounds__(256) k_lm_keys(const float* __restrict__ xs, c
         if (b >= 0 && b < nb) qt = (uint32_t)((b * 32) / nb);
     }
     const float fz = fminf(fmaxf((0.5f * (sz + ez) - kg.z0) * kg.inv_zext * 128.0f, 0.0f), 127.0f);
-    keys[i] = (qphi << 22) | (qrho << 12) | (qt << 7) | (uint32_t)fz;
+    keys[i] = sub | (uint64_t)((qphi << 22) | (qrho << 12) | (qt << 7) | (uint32_t)fz);
 }
 
 static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
+static int key_bits(int n_sub) {
+    int b = 32;
+    while (n_sub > 1 && (1 << (b - 32)) < n_sub) ++b;
+    return b;
+}
+
 static size_t sort_temp_bytes(int64_t n) {
     size_t bytes = 0;
-    hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint32_t*)nullptr, (uint32_t*)nullptr,
-                                       (const int32_t*)nullptr, (int32_t*)nullptr, (int)n, 0, 32, (hipStream_t)0);
+    hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                                       (const int32_t*)nullptr, (int32_t*)nullptr, (int)n, 0, 64, (hipStream_t)0);
     return bytes;
 }
 
 size_t presort_workspace_bytes(int64_t n) {
     if (n <= 0) return 0;
-    return 3 * align256((size_t)n * 4) + align256(sort_temp_bytes(n));
+    return 2 * align256((size_t)n * 8) + align256((size_t)n * 4) + align256(sort_temp_bytes(n));
 }
 
 hipError_t launch_presort(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g, int nb,
-                          int32_t* order, void* ws, size_t ws_bytes, hipStream_t s) {
-    const size_t a = align256((size_t)n * 4);
+                          int n_sub, int32_t* order, void* ws, size_t ws_bytes, hipStream_t s) {
+    const size_t a8 = align256((size_t)n * 8), a4 = align256((size_t)n * 4);
     char* base = static_cast<char*>(ws);
-    uint32_t* keys = reinterpret_cast<uint32_t*>(base);
-    uint32_t* keys_sorted = reinterpret_cast<uint32_t*>(base + a);
-    int32_t* idx = reinterpret_cast<int32_t*>(base + 2 * a);
-    void* temp = base + 3 * a;
-    size_t temp_bytes = ws_bytes - 3 * a;
+    uint64_t* keys = reinterpret_cast<uint64_t*>(base);
+    uint64_t* keys_sorted = reinterpret_cast<uint64_t*>(base + a8);
+    int32_t* idx = reinterpret_cast<int32_t*>(base + 2 * a8);
+    void* temp = base + 2 * a8 + a4;
+    size_t temp_bytes = ws_bytes - (2 * a8 + a4);
     KeyGeom kg;
     const double ext0 = g.n[0] * g.h[0], ext1 = g.n[1] * g.h[1];
     kg.cx = (float)(g.o[0] + 0.5 * (g.n[0] - 1) * g.h[0]);
@@ -90,11 +98,37 @@ hipError_t launch_presort(const float* xs, const float* xe, const int16_t* bins,
     kg.inv_rmax = (float)(1.0 / (0.5 * sqrt(ext0 * ext0 + ext1 * ext1) + 1e-3));
     kg.z0 = (float)(g.o[2] - 0.5 * g.h[2]);
     kg.inv_zext = (float)(1.0 / (g.n[2] * g.h[2]));
-    hipLaunchKernelGGL(k_lm_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, xs, xe, bins, n, kg, nb, keys,
-                       idx);
+    hipLaunchKernelGGL(k_lm_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, xs, xe, bins, n, kg, nb, n_sub,
+                       keys, idx);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, keys_sorted, idx, order, (int)n, 0, 32, s);
+    return hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, keys_sorted, idx, order, (int)n, 0,
+                                              key_bits(n_sub), s);
+}
+
+// out[i] = in[order[i]] for the three event arrays (bins optional)
+__global__ void __launch_bounds__(256) k_gather_events(const float* __restrict__ xs, const float* __restrict__ xe,
+                                                       const int16_t* __restrict__ bins,
+                                                       const int32_t* __restrict__ order, int64_t n,
+                                                       float* __restrict__ xs_out, float* __restrict__ xe_out,
+                                                       int16_t* __restrict__ bins_out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    int64_t j = order[i];
+    if (j < 0 || j >= n) j = i;  // not a permutation entry: keep the event in place
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        xs_out[3 * i + a] = xs[3 * j + a];
+        xe_out[3 * i + a] = xe[3 * j + a];
+    }
+    if (bins) bins_out[i] = bins[j];
+}
+
+hipError_t launch_gather_events(const float* xs, const float* xe, const int16_t* bins, const int32_t* order, int64_t n,
+                                float* xs_out, float* xe_out, int16_t* bins_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_events, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, xs, xe, bins, order, n,
+                       xs_out, xe_out, bins_out);
+    return hipGetLastError();
 }
 
 }  // namespace ppmi

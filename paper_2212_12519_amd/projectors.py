@@ -97,8 +97,8 @@ def presort_workspace(n, device):
     return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
 
 
-def pp_lm_presort(xstart, xend, tof_bin, geom, tof, order, workspace):
-    """Processing order that groups events on neighbouring LORs (see ppmi.h)."""
+def pp_lm_presort(xstart, xend, tof_bin, geom, tof, order, workspace, n_sub=1):
+    """Processing order that groups events on neighbouring LORs (subset-major if n_sub > 1)."""
     g = as_geom(geom)
     _dev(xstart, xend, tof_bin, order, workspace)
     n = _rays(xstart, xend)
@@ -107,16 +107,38 @@ def pp_lm_presort(xstart, xend, tof_bin, geom, tof, order, workspace):
     if tof_bin is not None:
         _bins(tof_bin, n)
         tc = as_tof(tof).c()
-    check(load().pp_lm_presort(ptr(xstart), ptr(xend), ptr(tof_bin), n, g.c(), tc, ptr(order), ptr(workspace),
-                               workspace.numel() * workspace.element_size(), stream_of(order)))
+    check(load().pp_lm_presort(ptr(xstart), ptr(xend), ptr(tof_bin), n, g.c(), tc, int(n_sub), ptr(order),
+                               ptr(workspace), workspace.numel() * workspace.element_size(), stream_of(order)))
     return order
 
 
-def presort(xstart, xend, geom, tof_bin=None, tof=None):
+def presort(xstart, xend, geom, tof_bin=None, tof=None, n_sub=1):
     order = torch.empty(xstart.shape[0], dtype=torch.int32, device=xstart.device)
     if xstart.shape[0] == 0:
         return order
-    return pp_lm_presort(xstart, xend, tof_bin, geom, tof, order, presort_workspace(xstart.shape[0], xstart.device))
+    return pp_lm_presort(xstart, xend, tof_bin, geom, tof, order, presort_workspace(xstart.shape[0], xstart.device),
+                         n_sub)
+
+
+def pp_gather_events(xstart, xend, tof_bin, order, xstart_out, xend_out, tof_bin_out):
+    """out[i] = in[order[i]] for the event arrays (library kernel)."""
+    _dev(xstart, xend, tof_bin, order, xstart_out, xend_out, tof_bin_out)
+    n = _rays(xstart, xend)
+    _rays(xstart_out, xend_out)
+    _order(order, n)
+    if xstart_out.shape[0] != n or (tof_bin is not None and (tof_bin_out is None or tof_bin_out.numel() != n)):
+        raise ValueError("output arrays must match the input event count")
+    check(load().pp_gather_events(ptr(xstart), ptr(xend), ptr(tof_bin), ptr(order), n, ptr(xstart_out),
+                                  ptr(xend_out), ptr(tof_bin_out), stream_of(order)))
+
+
+def gather_events(xstart, xend, tof_bin, order):
+    xs = torch.empty_like(xstart)
+    xe = torch.empty_like(xend)
+    tb = torch.empty_like(tof_bin) if tof_bin is not None else None
+    if xstart.shape[0]:
+        pp_gather_events(xstart, xend, tof_bin, order, xs, xe, tb)
+    return xs, xe, tb
 
 
 def pp_fill(dst, value):

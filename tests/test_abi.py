@@ -74,9 +74,13 @@ def test_error_codes(lib):
     ws = lib.pp_lm_presort_workspace_bytes(1000)
     assert ws >= 3 * 4000
     assert lib.pp_lm_presort_workspace_bytes(0) == 0
-    assert lib.pp_lm_presort(DUMMY, DUMMY, None, 1000, g, None, DUMMY, DUMMY, ws - 1, None) == PP_EINVAL_N
-    assert lib.pp_lm_presort(DUMMY, DUMMY, None, 1000, g, None, None, DUMMY, ws, None) == PP_EINVAL_PTR
-    assert lib.pp_lm_presort(DUMMY, DUMMY, None, -3, g, None, DUMMY, DUMMY, ws, None) == PP_EINVAL_N
+    assert lib.pp_lm_presort(DUMMY, DUMMY, None, 1000, g, None, 1, DUMMY, DUMMY, ws - 1, None) == PP_EINVAL_N
+    assert lib.pp_lm_presort(DUMMY, DUMMY, None, 1000, g, None, 1, None, DUMMY, ws, None) == PP_EINVAL_PTR
+    assert lib.pp_lm_presort(DUMMY, DUMMY, None, -3, g, None, 1, DUMMY, DUMMY, ws, None) == PP_EINVAL_N
+    assert lib.pp_lm_presort(DUMMY, DUMMY, None, 1000, g, None, 0, DUMMY, DUMMY, ws, None) == PP_EINVAL_N
+    assert lib.pp_gather_events(DUMMY, DUMMY, DUMMY, DUMMY, 10, DUMMY, DUMMY, None, None) == PP_EINVAL_PTR
+    assert lib.pp_gather_events(None, None, None, None, 0, None, None, None, None) == PP_OK
+    assert lib.pp_osem_init(None, None, 10, None) == PP_EINVAL_PTR
     for c in range(6):
         assert lib.pp_strerror(c)
 
