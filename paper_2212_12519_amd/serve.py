@@ -1,0 +1,279 @@
+"""Continuous-batching server for short-frame listmode TOF OSEM reconstructions.
+
+Motivation from the paper: data-driven motion correction reconstructs many very
+short frames (Sec. 1), and OSEM should keep every operation on the GPU
+(Sec. 2.6, Sec. 4).  Requests (a frame's events, an image grid, iterations x
+subsets) arrive over time.  The server
+
+* admits queued requests FIFO whenever a slot of their grid's table is free
+  and the frame fits the HBM budget (events in subset-major presorted order,
+  image, accumulator);
+* advances every admitted frame by one OSEM subset update per step, all
+  frames of a grid in one fused launch pair -- frames at different
+  iterations / subsets coexist, new frames join between steps, finished
+  frames leave (continuous batching at subset granularity);
+* replays a HIP graph captured once per grid (the slot table is read from
+  device memory, so the same graph serves every mix);
+* records arrival, admission and completion times for p50 / p99 latency.
+
+``run_sequential`` is the baseline: the same trace served one frame at a
+time, FIFO, with plain projector calls (pp_fwd_tof_lm, a torch ratio,
+pp_back_tof_lm, a torch image update) per subset.
+"""
+from __future__ import annotations
+
+import math
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from ._lib import as_geom, as_tof, load
+from . import osem as O
+from .projectors import back_tof_lm, fwd_tof_lm
+
+
+@dataclass
+class OsemRequest:
+    rid: int
+    xstart: torch.Tensor
+    xend: torch.Tensor
+    tof_bin: torch.Tensor
+    grid: object  # ImageGeom
+    arrival: float  # seconds after the start of the trace
+    n_iter: int = 3
+    n_sub: int = 8
+    bg: float = 0.1
+
+
+@dataclass
+class OsemResult:
+    rid: int
+    image: torch.Tensor
+    arrival: float
+    admitted: float
+    finished: float
+
+    @property
+    def latency(self):
+        return self.finished - self.arrival
+
+
+def frame_footprint(n_events, n_vox):
+    """HBM bytes a frame holds while admitted: presorted event copy (26 B/event), x and acc."""
+    return 26 * int(n_events) + 2 * 4 * int(n_vox)
+
+
+@dataclass
+class _Live:
+    req: OsemRequest
+    slot: int
+    tensors: tuple
+    x: torch.Tensor
+    admitted: float
+    nbytes: int
+
+
+@dataclass
+class _GridState:
+    geom: object
+    sens: torch.Tensor
+    table: O.SlotTable
+    free: list
+    live: dict = field(default_factory=dict)
+    graph: object = None
+    dirty: bool = False
+
+
+class OsemServer:
+    def __init__(self, tof, sens_by_grid, max_slots=64, hbm_budget=32e9, steps_per_tick=1, use_graph=True,
+                 device="cuda"):
+        self.tof = as_tof(tof)
+        self.device = torch.device(device)
+        self.budget = float(hbm_budget)
+        self.steps = int(steps_per_tick)
+        self.use_graph = use_graph
+        self.grids = {}
+        for geom, sens in sens_by_grid:
+            g = as_geom(geom)
+            self.grids[g] = _GridState(g, sens, O.SlotTable(max_slots, self.device), list(range(max_slots)))
+        self.in_use = 0
+        self.rejected = []
+        load()
+
+    def _admit(self, req, now):
+        st = self.grids[as_geom(req.grid)]
+        if not st.free:
+            return False
+        nbytes = frame_footprint(req.xstart.shape[0], st.geom.n_vox)
+        if nbytes > self.budget:
+            self.rejected.append(req.rid)  # can never fit: refuse instead of blocking the queue
+            return True
+        if self.in_use + nbytes > self.budget:
+            return False
+        slot = st.free.pop(0)
+        xs, xe, tb = O.prepare_frame(req.xstart, req.xend, req.tof_bin, st.geom, self.tof, req.n_sub)
+        x = O.init_image(st.sens)
+        acc = torch.zeros_like(st.sens)
+        st.table.set(slot, xs, xe, tb, x, acc, st.sens, req.n_sub, req.n_iter * req.n_sub, req.bg)
+        st.live[slot] = _Live(req, slot, (xs, xe, tb, acc), x, now, nbytes)
+        st.dirty = True
+        self.in_use += nbytes
+        return True
+
+    def _step(self, st):
+        if st.dirty:
+            st.table.upload()
+            st.dirty = False
+        if self.use_graph:
+            if st.graph is None:
+                st.graph = O.capture_steps(st.table, st.geom, self.tof, self.steps)
+            st.graph.replay()
+        else:
+            O.osem_steps(st.table, st.geom, self.tof, self.steps)
+        st.table.advance_host(self.steps)
+
+    def run(self, trace, clock=time.perf_counter):
+        """Serve a trace of OsemRequests (arrival times relative to the start); returns OsemResults."""
+        pending = deque(sorted(trace, key=lambda r: r.arrival))
+        queue = deque()
+        results = []
+        t0 = clock()
+        done_ev = torch.cuda.Event()
+        while pending or queue or any(st.live for st in self.grids.values()):
+            now = clock() - t0
+            while pending and pending[0].arrival <= now:
+                queue.append(pending.popleft())
+            while queue and self._admit(queue[0], now):
+                queue.popleft()
+            live = [st for st in self.grids.values() if st.live]
+            if not live:
+                if pending:
+                    time.sleep(max(0.0, pending[0].arrival - (clock() - t0)))
+                continue
+            for st in live:
+                self._step(st)
+            done_ev.record()
+            done_ev.synchronize()
+            now = clock() - t0
+            for st in live:
+                for slot in [s for s, lv in st.live.items() if st.table.host[s].steps_left <= 0]:
+                    lv = st.live.pop(slot)
+                    st.table.clear(slot)
+                    st.free.append(slot)
+                    st.dirty = True
+                    self.in_use -= lv.nbytes
+                    results.append(OsemResult(lv.req.rid, lv.x, lv.req.arrival, lv.admitted, now))
+        return results
+
+
+def run_sequential(trace, tof, sens_by_grid, clock=time.perf_counter):
+    """Baseline: the same trace, one frame at a time (FIFO), plain projector calls per subset."""
+    tof = as_tof(tof)
+    sens = {as_geom(g): s for g, s in sens_by_grid}
+    results = []
+    t0 = clock()
+    for req in sorted(trace, key=lambda r: r.arrival):
+        now = clock() - t0
+        if req.arrival > now:
+            time.sleep(req.arrival - now)
+        start = clock() - t0
+        g = as_geom(req.grid)
+        sv = sens[g]
+        xs, xe, tb = O.prepare_frame(req.xstart, req.xend, req.tof_bin, g, tof, req.n_sub)
+        n, ns = xs.shape[0], req.n_sub
+        base, rem = n // ns, n % ns
+        x = O.init_image(sv)
+        acc = torch.zeros_like(sv)
+        pos = sv > 0
+        for _ in range(req.n_iter):
+            for j in range(ns):
+                a = j * base + min(j, rem)
+                b = a + base + (1 if j < rem else 0)
+                ybar = fwd_tof_lm(xs[a:b], xe[a:b], tb[a:b], g, tof, x) + req.bg
+                ratio = torch.where(ybar > 0, 1.0 / ybar, torch.zeros_like(ybar))
+                acc.zero_()
+                back_tof_lm(xs[a:b], xe[a:b], tb[a:b], g, tof, ratio, img=acc)
+                x = torch.where(pos, x * acc / (sv / ns), torch.zeros_like(x))
+        torch.cuda.current_stream().synchronize()
+        results.append(OsemResult(req.rid, x, req.arrival, start, clock() - t0))
+    return results
+
+
+def latency_stats(results, t_first=None):
+    lat = np.array([r.latency for r in results])
+    if not len(lat):
+        return {}
+    t_first = min(r.arrival for r in results) if t_first is None else t_first
+    span = max(r.finished for r in results) - t_first
+    return {"n": len(lat), "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+            "mean_s": float(lat.mean()), "frames_per_s": len(lat) / span if span > 0 else math.inf,
+            "makespan_s": span}
+
+
+def make_trace(pool, grids, n_requests, seed, events_range, rate_hz, n_iter=3, n_sub=8, bg=0.1):
+    """Poisson arrivals; log-uniform event counts; each frame a random contiguous slice of the
+    event pool; grids drawn uniformly from `grids`."""
+    xs, xe, tb = pool
+    rng = np.random.default_rng(seed)
+    n_pool = xs.shape[0]
+    t, out = 0.0, []
+    lo, hi = math.log(events_range[0]), math.log(events_range[1])
+    for rid in range(n_requests):
+        t += rng.exponential(1.0 / rate_hz)
+        n = int(min(n_pool, round(math.exp(rng.uniform(lo, hi)))))
+        o = int(rng.integers(0, n_pool - n + 1))
+        g = grids[int(rng.integers(0, len(grids)))]
+        out.append(OsemRequest(rid, xs[o:o + n], xe[o:o + n], tb[o:o + n], g, t, n_iter, n_sub, bg))
+    return out
+
+
+def bench_leg(args, log):
+    """Serving measurement for bench.py: 256 Poisson-arriving TOF LM-OSEM frames (3 it x 8 subsets,
+    0.5M-20M events log-uniform, 128x128x64 or 215x215x71 grid), continuous batching vs sequential
+    plain calls on the same trace.  Returns a dict for the benchmark's JSON line."""
+    from synth import configs as C
+    from synth import generate_tof_lm_events
+    import paper_2212_12519_amd as pp
+
+    dev = torch.device("cuda")
+    t = C.TOF_CLIN
+    T = pp.TofParams(t.bin_width, t.sigma, t.n_sigmas, t.n_bins)
+    src = C.phantom_clin(device=dev)
+    pool = generate_tof_lm_events(C.SCANNER_CLIN, C.SINO_CLIN.n_rad, C.SINO_CLIN.max_rd, C.GRID_CLIN, src,
+                                  C.N_EVENTS_LM, seed=C.SEED_SERVE, tof_bin_width=t.bin_width, tof_sigma=t.sigma,
+                                  n_tof_bins=t.n_bins, device=dev)
+    lxs, lxe = C.SINO_CLIN.lors(device=dev, radial_chunk=25)
+    grids = [pp.ImageGeom(g.dim, g.voxsize, g.origin) for g in C.SERVE_GRIDS]
+    sens = [(g, O.sensitivity(lxs, lxe, g)) for g in grids]
+    del lxs, lxe
+    torch.cuda.empty_cache()
+    n_req = int(getattr(args, "serve_requests", None) or C.N_REQUESTS)
+    # calibrate the sequential service rate on a short burst, then load the server at 1.25x that rate
+    cal = make_trace(pool, grids, 6, C.SEED_SERVE + 1, C.SERVE_EVENTS_RANGE, 1e9)
+    run_sequential(cal[:1], T, sens)  # warm-up (graphs, allocator)
+    t0 = time.perf_counter()
+    run_sequential(cal, T, sens)
+    service = (time.perf_counter() - t0) / len(cal)
+    rate = 1.25 / service
+    trace = make_trace(pool, grids, n_req, C.SEED_SERVE, C.SERVE_EVENTS_RANGE, rate)
+    log(f"serving: {n_req} requests, sequential service ~{service * 1e3:.0f} ms/frame, arrival rate {rate:.2f}/s")
+    server = OsemServer(T, sens, max_slots=64, hbm_budget=32e9, steps_per_tick=1, use_graph=True)
+    server.run(make_trace(pool, grids, 4, C.SEED_SERVE + 2, (500_000, 600_000), 1e9))  # warm-up and capture
+    res_b = server.run(trace)
+    sb = latency_stats(res_b, 0.0)
+    log(f"serving batched: p50 {sb['p50_s']:.3f} s p99 {sb['p99_s']:.3f} s, {sb['frames_per_s']:.2f} frames/s")
+    res_s = run_sequential(trace, T, sens)
+    ss = latency_stats(res_s, 0.0)
+    log(f"serving sequential: p50 {ss['p50_s']:.3f} s p99 {ss['p99_s']:.3f} s, {ss['frames_per_s']:.2f} frames/s")
+    # equal accuracy: the same frames reconstructed both ways
+    by_id = {r.rid: r.image for r in res_s}
+    diffs = [float(torch.linalg.vector_norm(r.image - by_id[r.rid]) / torch.linalg.vector_norm(by_id[r.rid]))
+             for r in res_b[:16]]
+    return {"requests": n_req, "arrival_rate_hz": rate, "iterations": 3, "subsets": 8,
+            "batched": sb, "sequential_plain": ss,
+            "speedup_frames_per_s": sb["frames_per_s"] / ss["frames_per_s"],
+            "max_rel_l2_batched_vs_plain": max(diffs) if diffs else None,
+            "hbm_budget_gb": 32.0, "rejected": len(server.rejected)}

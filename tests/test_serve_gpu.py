@@ -1,0 +1,83 @@
+"""Serving loop: every frame's image is the same alone and in the continuous-batching mix
+(<= 1e-4), admission respects the HBM budget (a frame larger than the budget is refused,
+the others wait their turn), graph replay and eager stepping agree, and the sequential
+plain-call baseline reconstructs the same images."""
+import numpy as np
+import pytest
+import torch
+
+from helpers import rel_l2
+from synth import configs as C
+from synth import generate_tof_lm_events
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def setup(gpu):
+    from paper_2212_12519_amd import osem
+
+    dev = torch.device("cuda")
+    t = C.TOF_CLIN
+    T = gpu.TofParams(t.bin_width, t.sigma, t.n_sigmas, t.n_bins)
+    src = C.phantom_clin(device=dev)
+    pool = generate_tof_lm_events(C.SCANNER_CLIN, C.SINO_CLIN.n_rad, C.SINO_CLIN.max_rd, C.GRID_CLIN, src,
+                                  4_000_000, seed=71, tof_bin_width=t.bin_width, tof_sigma=t.sigma,
+                                  n_tof_bins=t.n_bins, device=dev)
+    lxs, lxe = C.SINO_CLIN.lors(views=torch.arange(0, 380, 5), device=dev, radial_chunk=50)
+    grids = [gpu.ImageGeom(g.dim, g.voxsize, g.origin) for g in C.SERVE_GRIDS]
+    sens = [(g, osem.sensitivity(lxs, lxe, g)) for g in grids]
+    return pool, grids, sens, T
+
+
+def _alone(req, sens, T):
+    from paper_2212_12519_amd import osem
+
+    s = dict(sens)[req.grid]
+    return osem.lm_osem(req.xstart, req.xend, req.tof_bin, req.grid, T, s, req.n_iter, req.n_sub, req.bg)
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_results_equal_alone(gpu, setup, use_graph):
+    from paper_2212_12519_amd import serve
+
+    pool, grids, sens, T = setup
+    trace = serve.make_trace(pool, grids, 10, seed=72, events_range=(50_000, 800_000), rate_hz=40.0)
+    server = serve.OsemServer(T, sens, max_slots=4, hbm_budget=8e9, use_graph=use_graph)
+    res = server.run(trace)
+    assert sorted(r.rid for r in res) == list(range(10))
+    by_id = {r.rid: r for r in res}
+    for req in trace:
+        r = by_id[req.rid]
+        assert r.finished >= r.admitted >= req.arrival - 1e-6
+        ref = _alone(req, sens, T)
+        assert rel_l2(r.image.cpu().numpy(), ref.cpu().numpy()) <= 1e-4, req.rid
+
+
+def test_budget_admission(gpu, setup):
+    """With a budget that fits one frame at a time, frames are served one by one (no overlap of
+    their admitted intervals) and a frame larger than the budget is refused."""
+    from paper_2212_12519_amd import serve
+
+    pool, grids, sens, T = setup
+    trace = serve.make_trace(pool, grids[:1], 4, seed=73, events_range=(100_000, 120_000), rate_hz=1000.0)
+    nv = grids[0].n_vox
+    budget = serve.frame_footprint(125_000, nv)
+    big = serve.OsemRequest(99, pool[0][:3_000_000], pool[1][:3_000_000], pool[2][:3_000_000], grids[0], 0.0)
+    server = serve.OsemServer(T, sens, max_slots=4, hbm_budget=budget, use_graph=True)
+    res = sorted(server.run(trace + [big]), key=lambda r: r.admitted)
+    assert server.rejected == [99]
+    assert len(res) == 4
+    for a, b in zip(res, res[1:]):
+        assert b.admitted >= a.finished - 1e-6
+
+
+def test_sequential_baseline_same_images(gpu, setup):
+    from paper_2212_12519_amd import serve
+
+    pool, grids, sens, T = setup
+    trace = serve.make_trace(pool, grids, 3, seed=74, events_range=(200_000, 400_000), rate_hz=100.0)
+    seq = {r.rid: r.image for r in serve.run_sequential(trace, T, sens)}
+    for req in trace:
+        ref = _alone(req, sens, T)
+        assert rel_l2(seq[req.rid].cpu().numpy(), ref.cpu().numpy()) <= 1e-4
