@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
     ap.add_argument("--only", default=None, help="profiling helper: lm | sino | serve")
+    ap.add_argument("--serve-requests", type=int, default=None, help="requests in the serving leg (default 256)")
     return ap.parse_args()
 
 
@@ -224,12 +225,12 @@ def main():
         print(json.dumps(extra))
         return
     if args.only in (None, "serve") and not args.no_serve:
-        try:
-            from paper_2212_12519_amd import serve  # noqa: F401
-        except ImportError:
-            serve = None
-        if serve is not None:
-            extra["osem_serving"] = serve.bench_leg(args, log)
+        from paper_2212_12519_amd import serve
+
+        extra["osem_serving"] = serve.bench_leg(args, log)
+    if args.only == "serve":
+        print(json.dumps(extra))
+        return
     cpu = None
     if not args.no_cpu and lm_inputs is not None:
         cpu = cpu_leg(args, lm_inputs, C)
