@@ -31,6 +31,25 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 
 
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter profile, or None when the
+    kernel sources changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "tof_lm_40M_traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in rec.get("sources", []):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != rec.get("source_sha256"):
+        return None
+    k = rec.get("kernels", {}).get("ppmi::k_" + kernel.replace("pp_", ""))
+    return k["traffic_bytes"] if k else None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -217,7 +236,13 @@ def main():
     if args.only in (None, "lm"):
         lm, lm_inputs = lm_leg(args, pp, C, dev)
     if args.only == "lm":
-        print(json.dumps({"lm": lm}))
+        # a plain device copy of known size (1 GiB read + 1 GiB written), so hardware byte
+        # counters collected on this run can be scaled to bytes
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"lm": lm, "calibration_copy_bytes": src.numel() * 4}))
         return
     if args.only in (None, "sino") and not args.no_sino:
         extra["sinogram"] = sino_leg(args, pp, C, dev)
@@ -244,7 +269,7 @@ def main():
                                "phantom 215x215x71 @ 1.65x1.65x2.0 mm, 29 TOF bins x 28 mm, FWHM 58.5 mm, 3 sigma",
                    "n_events": lm["n_events"], "image": list(C.GRID_CLIN.dim), "tof_bins": C.TOF_CLIN.n_bins},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": lm["dominant"],
+                     "frac": ach / HBM_PEAK_GBS, "traffic": profiled_traffic(lm["dominant"]), "kernel": lm["dominant"],
                      "alg_bytes_per_launch": lm["alg_bytes_per_launch"]},
         "cpu_baseline": cpu,
         "lm": {k: lm[k] for k in ("t_presort_ms", "t_fwd_ms", "t_back_ms", "unsorted_t_fwd_ms", "unsorted_t_back_ms",
