@@ -56,7 +56,8 @@ def _load():
     lib.orc_back_tof_lm.argtypes = geo + tof + [P, P, P]
     lib.orc_count_samples.argtypes = geo + tof + [P, P]
     lib.orc_count_samples.restype = I64
-    lib.orc_lm_osem.argtypes = [P, P, P, I64, P, P, P] + tof + [P, ctypes.c_double, I32, I32, P]
+    lib.orc_lm_osem.argtypes = [P, P, P, I64, P, P, P] + tof + [P, ctypes.c_double, I32, I32, P, P]
+    lib.orc_gauss3d.argtypes = [P, P, P, P, P]
     lib.orc_max_threads.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -182,8 +183,31 @@ def count_samples(xstart, xend, origin, voxsize, dim, tof=None, bins=None, per_r
     return (int(tot), pr) if per_ray else int(tot)
 
 
-def lm_osem(xstart, xend, bins, origin, voxsize, dim, tof, sens, bg, n_iter, n_sub, x0):
-    """Listmode TOF OSEM; returns the float64 image after n_iter x n_sub updates."""
+def _fwhm3(fwhm):
+    f = np.ascontiguousarray(np.broadcast_to(np.asarray(fwhm, dtype=np.float64), (3,)))
+    if not np.all(np.isfinite(f)) or np.any(f < 0):
+        raise ValueError("fwhm must be finite and >= 0")
+    return f
+
+
+def gauss3d(img, voxsize, fwhm):
+    """Resolution model: the image blurred by a 3D Gaussian of FWHM `fwhm` mm (scalar or per axis),
+    sampled on the voxel grid, truncated at 4 sigma, zero outside the grid (float64 result)."""
+    lib = _load()
+    x = np.ascontiguousarray(np.asarray(img, dtype=np.float64))
+    if x.ndim != 3:
+        raise ValueError("img must be 3-D")
+    h = np.ascontiguousarray(np.asarray(voxsize, dtype=np.float32).reshape(3))
+    d = np.ascontiguousarray(np.asarray(x.shape, dtype=np.int32))
+    f = _fwhm3(fwhm)
+    out = np.empty_like(x)
+    lib.orc_gauss3d(_ptr(x), _ptr(out), _ptr(d), _ptr(h), _ptr(f))
+    return out
+
+
+def lm_osem(xstart, xend, bins, origin, voxsize, dim, tof, sens, bg, n_iter, n_sub, x0, fwhm=None):
+    """Listmode TOF OSEM; returns the float64 image after n_iter x n_sub updates.  With `fwhm`
+    (mm, scalar or per axis) the system model includes the Gaussian resolution model."""
     lib = _load()
     xs, xe = _f32(xstart, 3), _f32(xend, 3)
     o, h, d = _geom(origin, voxsize, dim)
@@ -191,6 +215,8 @@ def lm_osem(xstart, xend, bins, origin, voxsize, dim, tof, sens, bg, n_iter, n_s
     b = _bins(bins, xs.shape[0])
     s = np.ascontiguousarray(np.asarray(sens, dtype=np.float64).reshape(tuple(d)))
     x = np.array(np.asarray(x0, dtype=np.float64).reshape(tuple(d)), copy=True, order="C")
+    f = None if fwhm is None else _fwhm3(fwhm)
     lib.orc_lm_osem(_ptr(xs), _ptr(xe), _ptr(b), xs.shape[0], _ptr(o), _ptr(h), _ptr(d), *ta, _ptr(s),
-                    ctypes.c_double(bg), ctypes.c_int32(n_iter), ctypes.c_int32(n_sub), _ptr(x))
+                    ctypes.c_double(bg), ctypes.c_int32(n_iter), ctypes.c_int32(n_sub), _ptr(x),
+                    None if f is None else _ptr(f))
     return x

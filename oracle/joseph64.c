@@ -364,24 +364,85 @@ int64_t orc_count_samples(const float* xs, const float* xe, int64_t n, const flo
     return total;
 }
 
+/* Image-based resolution model (the Gaussian blur the paper's listmode OSEM
+ * reconstructions include, Sec. 2.6): a shift-invariant 3D Gaussian of the
+ * given FWHM per axis (mm), applied as a discrete convolution on the voxel
+ * grid.  Readings: sigma_a = FWHM_a / (2 sqrt(2 ln 2)) / h_a in voxels; the
+ * kernel of axis a is exp(-i^2 / (2 sigma_a^2)) for |i| <= r_a =
+ * floor(4 sigma_a + 1/2), normalised to sum 1 (FWHM_a == 0: identity); the
+ * 3D kernel is the product of the three; voxels outside the grid read as 0.
+ * With these readings the operator is symmetric, so it is its own adjoint.
+ * Evaluated as one 1D convolution per axis (the product kernel factorises). */
+static int gauss_taps(double fwhm, float h, double* w, int max_r) {
+    if (!(fwhm > 0.0)) {
+        w[0] = 1.0;
+        return 0;
+    }
+    double sig = fwhm / (2.0 * sqrt(2.0 * log(2.0))) / (double)h;
+    int r = (int)floor(4.0 * sig + 0.5);
+    if (r > max_r) abort();
+    double sum = 0.0;
+    for (int i = -r; i <= r; ++i) sum += (w[i + r] = exp(-(double)i * i / (2.0 * sig * sig)));
+    for (int i = -r; i <= r; ++i) w[i + r] /= sum;
+    return r;
+}
+
+void orc_gauss3d(const double* src, double* dst, const int32_t* dim, const float* vs, const double* fwhm) {
+    enum { MAXR = 64 };
+    int64_t n0 = dim[0], n1 = dim[1], n2 = dim[2], nv = n0 * n1 * n2;
+    double* a = (double*)malloc((size_t)nv * sizeof(double));
+    double* b = (double*)malloc((size_t)nv * sizeof(double));
+    if (!a || !b) abort();
+    memcpy(a, src, (size_t)nv * sizeof(double));
+    const int64_t stride[3] = {n1 * n2, n2, 1};
+    for (int ax = 0; ax < 3; ++ax) {
+        double w[2 * MAXR + 1];
+        int r = gauss_taps(fwhm[ax], vs[ax], w, MAXR);
+        int64_t len = dim[ax];
+#pragma omp parallel for schedule(static)
+        for (int64_t v = 0; v < nv; ++v) {
+            int64_t pos = (v / stride[ax]) % len;  /* index along this axis */
+            double acc = 0.0;
+            for (int i = -r; i <= r; ++i) {
+                int64_t q = pos + i;
+                if (q < 0 || q >= len) continue;
+                acc += w[i + r] * a[v + (int64_t)i * stride[ax]];
+            }
+            b[v] = acc;
+        }
+        double* t = a;
+        a = b;
+        b = t;
+    }
+    memcpy(dst, a, (size_t)nv * sizeof(double));
+    free(a);
+    free(b);
+}
+
 /* Listmode OSEM with TOF (ordered subsets EM, the paper's Sec. 2.6 iteration):
  * for it in [0, n_iter), subset j in [0, n_sub):
- *     acc = sum over events e with e % n_sub == j of a_e / (a_e . x + bg)
- *     x_v <- x_v * acc_v / (sens_v / n_sub)   if sens_v > 0, else 0.
- * x holds the initial image on entry and the result on return. */
+ *     acc = sum over events e with e % n_sub == j of a_e / (a_e . x' + bg)
+ *     x_v <- x_v * acc'_v / (sens_v / n_sub)   if sens_v > 0, else 0,
+ * where without a resolution model (fwhm == NULL) x' = x and acc' = acc, and
+ * with one x' = G x and acc' = G acc (G = orc_gauss3d with that FWHM: the
+ * system model is the projector after the blur, its adjoint the blur after
+ * the back projection; sens must then be G applied to the back projection of
+ * ones).  x holds the initial image on entry and the result on return. */
 void orc_lm_osem(const float* xs, const float* xe, const int16_t* bins, int64_t n, const float* origin,
                  const float* vs, const int32_t* dim, float bin_width, float sigma, float n_sigmas,
                  float center_offset, int32_t n_bins, const double* sens, double bg, int32_t n_iter,
-                 int32_t n_sub, double* x) {
+                 int32_t n_sub, double* x, const double* fwhm) {
     grid64 g = mkgrid(origin, vs, dim);
     tof64 tf = mktof(bin_width, sigma, n_sigmas, center_offset, n_bins);
     int64_t nv = nvox(&g);
     int nt = nthreads();
     double* priv = (double*)malloc((size_t)nt * (size_t)nv * sizeof(double));
     double* acc = (double*)malloc((size_t)nv * sizeof(double));
-    if (!priv || !acc) abort();
+    double* xf = fwhm ? (double*)malloc((size_t)nv * sizeof(double)) : x;
+    if (!priv || !acc || !xf) abort();
     for (int it = 0; it < n_iter; ++it) {
         for (int j = 0; j < n_sub; ++j) {
+            if (fwhm) orc_gauss3d(x, xf, dim, vs, fwhm);
             memset(priv, 0, (size_t)nt * (size_t)nv * sizeof(double));
             int64_t n_j = (n > j) ? (n - j + n_sub - 1) / n_sub : 0;
 #pragma omp parallel
@@ -391,7 +452,7 @@ void orc_lm_osem(const float* xs, const float* xe, const int16_t* bins, int64_t 
                 for (int64_t q = 0; q < n_j; ++q) {
                     int64_t e = (int64_t)j + q * n_sub;
                     double ybar;
-                    ray_forward(xs + 3 * e, xe + 3 * e, &g, &tf, 2, bins[e], x, &ybar);
+                    ray_forward(xs + 3 * e, xe + 3 * e, &g, &tf, 2, bins[e], xf, &ybar);
                     ybar += bg;
                     if (!(ybar > 0.0)) continue;
                     double r = 1.0 / ybar;
@@ -404,6 +465,7 @@ void orc_lm_osem(const float* xs, const float* xe, const int16_t* bins, int64_t 
                 for (int th = 0; th < nt; ++th) s += priv[(size_t)th * (size_t)nv + (size_t)v];
                 acc[v] = s;
             }
+            if (fwhm) orc_gauss3d(acc, acc, dim, vs, fwhm);
 #pragma omp parallel for schedule(static)
             for (int64_t v = 0; v < nv; ++v)
                 x[v] = (sens[v] > 0.0) ? x[v] * acc[v] / (sens[v] / (double)n_sub) : 0.0;
@@ -411,4 +473,5 @@ void orc_lm_osem(const float* xs, const float* xe, const int16_t* bins, int64_t 
     }
     free(priv);
     free(acc);
+    if (fwhm) free(xf);
 }

@@ -14,6 +14,8 @@ Gauss-Legendre quadrature of the truncated Gaussian density over the TOF bin
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 _GL_X, _GL_W = np.polynomial.legendre.leggauss(48)
@@ -89,3 +91,25 @@ def system_matrix(xstart, xend, origin, voxsize, dim, tof=None, mode="nontof", b
                 cb = (b - 0.5 * (int(tof["n_bins"]) - 1)) * tof["bin_width"] + tof.get("center_offset", 0.0)
                 A[l, v] = ell * wgt * tof_weight_quadrature(spos, cb, tof["bin_width"], tof["sigma"], tof["n_sigmas"])
     return A
+
+
+def gauss_matrix(dim, voxsize, fwhm):
+    """Dense resolution-model matrix G[v, u] for a tiny grid, written without separability: the
+    isotropic Gaussian exp(-|x_v - x_u|^2 / (2 sigma^2)) of the 3-D displacement in mm, kept
+    where every axis offset is within that axis' truncation radius floor(4 sigma / h_a + 1/2)
+    voxels, divided by its sum over that box (so that G 1 = 1 away from the edges).  Voxels
+    outside the grid simply do not exist (zero padding)."""
+    dim = tuple(int(d) for d in dim)
+    h = np.asarray(voxsize, dtype=np.float32).astype(np.float64)
+    f = np.broadcast_to(np.asarray(fwhm, dtype=np.float64), (3,))
+    assert np.all(f == f[0]) and f[0] > 0, "isotropic kernel only"
+    sigma = f[0] / math.sqrt(8.0 * math.log(2.0))
+    r = np.floor(4.0 * sigma / h + 0.5).astype(int)
+    # normalisation over the truncation box
+    offs = np.stack(np.meshgrid(*[np.arange(-r[a], r[a] + 1) for a in range(3)], indexing="ij"), -1)
+    norm = np.exp(-np.sum((offs * h) ** 2, axis=-1) / (2.0 * sigma**2)).sum()
+    idx = np.stack(np.meshgrid(*[np.arange(d) for d in dim], indexing="ij"), -1).reshape(-1, 3)
+    delta = idx[:, None, :] - idx[None, :, :]
+    inside = np.all(np.abs(delta) <= r, axis=-1)
+    g = np.exp(-np.sum((delta * h) ** 2, axis=-1) / (2.0 * sigma**2)) / norm
+    return np.where(inside, g, 0.0)
