@@ -31,23 +31,78 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 
 
-def profiled_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter profile, or None when the
-    kernel sources changed since the counters were taken."""
+def kernel_sources_sha():
+    """sha256 over every HIP source of the library (sorted by name)."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "tof_lm_40M_traffic.json")
+    d = os.path.join(ROOT, "paper_2212_12519_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "tof_lm_40M_traffic.json")
+# the device kernel each timed entry point of the listmode step launches
+KERNEL_OF = {"pp_lm_presort": "ppmi::k_lm_keys", "pp_fwd_tof_lm": "ppmi::k_fwd_tof_lm",
+             "pp_back_tof_lm": "ppmi::k_back_runs<ppmi::ModeTofLm>"}
+
+
+def profiled_traffic(entry):
+    """HBM bytes per launch of the kernel behind `entry` from the committed counter profile, or
+    None when the kernel sources changed since the counters were taken."""
     try:
-        rec = json.load(open(path))
+        rec = json.load(open(TRAFFIC_JSON))
     except (OSError, ValueError):
         return None
-    h = hashlib.sha256()
-    for f in rec.get("sources", []):
-        h.update(open(os.path.join(ROOT, f), "rb").read())
-    if h.hexdigest() != rec.get("source_sha256"):
+    if kernel_sources_sha() != rec.get("source_sha256"):
         return None
-    k = rec.get("kernels", {}).get("ppmi::k_" + kernel.replace("pp_", ""))
+    k = rec.get("kernels", {}).get(KERNEL_OF.get(entry, ""))
     return k["traffic_bytes"] if k else None
+
+
+def kernel_short_name(name):
+    """'void ns::k<T>(args...)' -> 'ns::k<T>'."""
+    name = name.strip()
+    if name.startswith("void "):
+        name = name[5:]
+    return name.split("(", 1)[0]
+
+
+def write_traffic(fetch_csv, write_csv, copy_bytes=1 << 30):
+    """Turn two rocprofv3 counter-collection CSVs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) of
+    `bench.py --only lm` into the traffic record: per kernel of the step the mean KiB per
+    launch, scaled to bytes by what the same counters read for the run's 1 GiB device copy."""
+    import csv
+
+    def per_kernel(path, counter):
+        acc = {}
+        for row in csv.DictReader(open(path)):
+            if row["Counter_Name"] != counter:
+                continue
+            acc.setdefault(kernel_short_name(row["Kernel_Name"]), []).append(float(row["Counter_Value"]))
+        return acc
+
+    fe, wr = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    copy = [k for k in fe if "copyBuffer" in k]
+    if not copy:
+        raise SystemExit("no device copy kernel in the counter file")
+    cf, cw = max(max(fe[k]) for k in copy), max(max(wr[k]) for k in copy)
+    fs, ws = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
+    kernels = {}
+    for k in KERNEL_OF.values():
+        if k in fe and k in wr:
+            f, w = sum(fe[k]) / len(fe[k]), sum(wr[k]) / len(wr[k])
+            kernels[k] = {"fetch_kib": f, "write_kib": w, "launches": len(fe[k]),
+                          "traffic_bytes": 1024.0 * (f * fs + w * ws)}
+    rec = {"kernels": kernels, "copy_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
+           "fetch_scale": fs, "write_scale": ws, "source_sha256": kernel_sources_sha(),
+           "sources": "paper_2212_12519_amd/csrc/*.hip, *.hpp"}
+    with open(TRAFFIC_JSON, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec, indent=1))
 
 
 def log(msg):
@@ -66,6 +121,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
     ap.add_argument("--only", default=None, help="profiling helper: lm | sino | serve")
     ap.add_argument("--serve-requests", type=int, default=None, help="requests in the serving leg (default 256)")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
+                    help="no GPU work: write the traffic record from two rocprofv3 counter CSVs of --only lm")
     return ap.parse_args()
 
 
@@ -218,6 +275,9 @@ def sino_leg(args, pp, C, dev):
 
 def main():
     args = parse()
+    if args.write_traffic:
+        write_traffic(*args.write_traffic)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path.",
               file=sys.stderr)
@@ -269,7 +329,8 @@ def main():
                                "phantom 215x215x71 @ 1.65x1.65x2.0 mm, 29 TOF bins x 28 mm, FWHM 58.5 mm, 3 sigma",
                    "n_events": lm["n_events"], "image": list(C.GRID_CLIN.dim), "tof_bins": C.TOF_CLIN.n_bins},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS, "traffic": profiled_traffic(lm["dominant"]), "kernel": lm["dominant"],
+                     "frac": ach / HBM_PEAK_GBS, "traffic": profiled_traffic(lm["dominant"]), "entry": lm["dominant"],
+                     "kernel": KERNEL_OF[lm["dominant"]],
                      "alg_bytes_per_launch": lm["alg_bytes_per_launch"]},
         "cpu_baseline": cpu,
         "lm": {k: lm[k] for k in ("t_presort_ms", "t_fwd_ms", "t_back_ms", "unsorted_t_fwd_ms", "unsorted_t_back_ms",

@@ -191,7 +191,7 @@ typedef struct pp_osem_slot {
     int32_t reserved;
 } pp_osem_slot_t;
 
-/* Work chunks a slot needs per step (events of the largest subset / 256,
+/* Work chunks a slot needs per step (events of the largest subset / 1024,
  * rounded up).  The host sets chunk_begin of slot s to the sum over slots
  * r < s of pp_osem_chunks(n_events_r, n_sub_r) (0 for inactive slots). */
 int64_t pp_osem_chunks(int64_t n_events, int32_t n_sub);

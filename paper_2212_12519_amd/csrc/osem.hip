@@ -8,32 +8,63 @@
 // may be in any order (pp_lm_presort with n_sub groups them by LOR).
 //
 // k_osem_accumulate: one persistent grid walks the work chunks of all live
-// slots (a chunk = 256 consecutive events of one slot's current subset); each
+// slots (a chunk = 1024 consecutive events of one slot's current subset); each
 // lane projects its event forward through the slot's image, forms
 // ell / ybar and back projects it into the slot's accumulator -- forward,
-// ratio and back projection fused, the event set up once.  The scatter uses
-// the wave-synchronous plane loop with run-combined atomics.
+// ratio and back projection fused, the event set up once.  The scatter is the
+// run/sheet back projection of sheet.hpp (LDS sheets for runs of events on one
+// transaxial line, run-combined atomics for the rest).
 // k_osem_update: x <- x * acc / (sens / n_sub) (0 where sens == 0), acc <- 0.
 // k_osem_advance: next subset, one step fewer.
 #include <hip/hip_runtime.h>
 
 #include "joseph.hpp"
 #include "launch.hpp"
+#include "sheet.hpp"
 
 namespace ppmi {
 
 constexpr int kOsemBlock = 256;
+constexpr int kOsemGroups = 4;
+constexpr int64_t kOsemChunk = (int64_t)kSheetBlock * kOsemGroups;  // events of one work chunk
 
 __device__ __forceinline__ bool slot_live(const pp_osem_slot_t& s) { return s.active && s.steps_left > 0; }
 
 __host__ __device__ inline int64_t slot_chunks(int64_t n_events, int32_t n_sub) {
     if (n_events <= 0 || n_sub <= 0) return 0;
     const int64_t per_subset = (n_events + n_sub - 1) / n_sub;  // largest subset
-    return (per_subset + kOsemBlock - 1) / kOsemBlock;
+    return (per_subset + kOsemChunk - 1) / kOsemChunk;
 }
 
-__global__ void __launch_bounds__(kOsemBlock) k_osem_accumulate(const pp_osem_slot_t* __restrict__ slots,
-                                                                int n_slots, GeomK g, TofK t) {
+// Per event: forward project through the frame's current image (setup), then scatter
+// ell / ybar times the TOF weight (sample) -- the run/sheet back projection of sheet.hpp.
+struct ModeOsem {
+    const float* __restrict__ x;
+    const int16_t* __restrict__ bins;
+    float bg;
+    TofK t;
+    __device__ bool setup(int64_t l, const float* xs, const float* xe, const GeomK& g, RayK& r, double& cen,
+                          float& cv) const {
+        const int b = bins[l];
+        cen = t.c0 + b * t.bw;
+        if (b < 0 || b >= t.nb || !ray_setup(xs + 3 * l, xe + 3 * l, g, r)) return false;
+        if (!tof_window(r, cen, t.win)) return false;
+        float fwd = 0.0f;
+        for (int k = r.k_lo; k <= r.k_hi; ++k) {
+            const float w = tof_weight(fma((double)k, r.ds, r.s0), cen, t);
+            fwd += w * stencil_gather(x, r, stencil_at(r, k));
+        }
+        const float ybar = r.ell * fwd + bg;
+        if (!(ybar > 0.0f)) return false;
+        cv = r.ell / ybar;
+        return true;
+    }
+    __device__ float sample(double s, double cen, float cv) const { return tof_weight(s, cen, t) * cv; }
+};
+
+__global__ void __launch_bounds__(kSheetBlock) k_osem_accumulate(const pp_osem_slot_t* __restrict__ slots,
+                                                                 int n_slots, GeomK g, TofK t, int nw_lds) {
+    extern __shared__ double smem[];
     const pp_osem_slot_t& last = slots[n_slots - 1];
     const int64_t total = last.chunk_begin + (last.active ? slot_chunks(last.n_events, last.n_sub) : 0);
     for (int64_t c = xcd_block(blockIdx.x, gridDim.x); c < total; c += gridDim.x) {
@@ -49,44 +80,11 @@ __global__ void __launch_bounds__(kOsemBlock) k_osem_accumulate(const pp_osem_sl
         const int64_t base_n = n / ns, rem = n - base_n * ns;
         const int64_t n_j = base_n + (j < rem ? 1 : 0);
         const int64_t off_j = j * base_n + (j < rem ? j : rem);
-        const int64_t q = (c - s.chunk_begin) * kOsemBlock + threadIdx.x;
-        RayK r;
-        bool ok = q < n_j;
-        const int64_t e = off_j + q;
-        double centre = 0.0;
-        if (ok) {
-            const int b = s.tof_bin[e];
-            ok = b >= 0 && b < t.nb && ray_setup(s.xstart + 3 * e, s.xend + 3 * e, g, r);
-            if (ok) {
-                centre = t.c0 + b * t.bw;
-                ok = tof_window(r, centre, t.win);
-            }
-        }
-        float cl = 0.0f;
-        if (ok) {
-            const float* __restrict__ x = s.x;
-            float fwd = 0.0f;
-            for (int k = r.k_lo; k <= r.k_hi; ++k) {
-                const float w = tof_weight(fma((double)k, r.ds, r.s0), centre, t);
-                fwd += w * stencil_gather(x, r, stencil_at(r, k));
-            }
-            const float ybar = r.ell * fwd + s.bg;
-            ok = ybar > 0.0f;
-            cl = ok ? r.ell / ybar : 0.0f;
-        }
-        const int lo = ok ? r.k_lo : (1 << 30), hi = ok ? r.k_hi : -(1 << 30);
-        const int k0 = wave_min(lo), k1 = wave_max(hi);
-        float* __restrict__ acc = s.acc;
-        for (int k = k0; k <= k1; ++k) {
-            const bool act = k >= lo && k <= hi;
-            Stencil st{};
-            float v = 0.0f;
-            if (act) {
-                st = stencil_at(r, k);
-                v = tof_weight(fma((double)k, r.ds, r.s0), centre, t) * cl;
-            }
-            wave_stencil_scatter(acc, act && v != 0.0f, r, st, v);
-        }
+        const int64_t q0 = (c - s.chunk_begin) * kOsemChunk;
+        if (q0 >= n_j) continue;
+        ModeOsem m{s.x, s.tof_bin + off_j, s.bg, t};
+        back_runs_chunk(m, s.xstart + 3 * off_j, s.xend + 3 * off_j, n_j, g, s.acc, nullptr, nw_lds, kOsemGroups,
+                        q0, smem);
     }
 }
 
@@ -130,7 +128,12 @@ int64_t osem_chunks(int64_t n_events, int32_t n_sub) { return slot_chunks(n_even
 
 hipError_t launch_osem_accumulate(const pp_osem_slot_t* slots, int n_slots, const GeomK& g, const TofK& t,
                                   int n_blocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_osem_accumulate, dim3(n_blocks), dim3(kOsemBlock), 0, s, slots, n_slots, g, t);
+    const int nw = (g.n[2] <= kSheetMaxW) ? g.n[2] : 0;
+    const size_t lds = SheetLayout::bytes(nw);
+    hipError_t e = hipFuncSetAttribute((const void*)k_osem_accumulate, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_osem_accumulate, dim3(n_blocks), dim3(kSheetBlock), lds, s, slots, n_slots, g, t, nw);
     return hipGetLastError();
 }
 

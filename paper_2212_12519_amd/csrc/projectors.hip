@@ -5,6 +5,7 @@
 
 #include "joseph.hpp"
 #include "launch.hpp"
+#include "sheet.hpp"
 
 namespace ppmi {
 
@@ -37,29 +38,6 @@ __global__ void __launch_bounds__(kBlock) k_fwd(const float* __restrict__ xs, co
     p[l] = acc;
 }
 
-__global__ void __launch_bounds__(kBlock) k_back(const float* __restrict__ xs, const float* __restrict__ xe,
-                                                 int64_t n, GeomK g, float* __restrict__ img,
-                                                 const float* __restrict__ p, const int32_t* __restrict__ order) {
-    const int64_t l = ray_index(order, n);
-    RayK r;
-    bool ok = l >= 0;
-    float c = 0.0f;
-    if (ok) {
-        const float pl = p[l];
-        ok = pl != 0.0f && ray_setup(xs + 3 * l, xe + 3 * l, g, r);
-        c = ok ? r.ell * pl : 0.0f;
-    }
-    // wave-synchronous plane order (see k_back_tof_lm)
-    const int lo = ok ? r.k_lo : (1 << 30), hi = ok ? r.k_hi : -(1 << 30);
-    const int k0 = wave_min(lo), k1 = wave_max(hi);
-    for (int k = k0; k <= k1; ++k) {
-        const bool act = k >= lo && k <= hi;
-        Stencil st{};
-        if (act) st = stencil_at(r, k);
-        wave_stencil_scatter(img, act, r, st, c);
-    }
-}
-
 // ------------------------------------------------------- TOF listmode ----
 
 __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(const float* __restrict__ xs, const float* __restrict__ xe,
@@ -84,46 +62,6 @@ __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(const float* __restrict__
     p[l] = acc;
 }
 
-// Scatter loop in wave-synchronous plane order: every lane of a wave steps
-// through the same absolute plane k (the union of the lanes' windows) and only
-// lanes whose window contains k add.  With presorted events a wave holds
-// nearly coincident rays, so at each k its atomic adds fall into one image
-// column and share cache lines -- float atomics are priced per cache-line
-// request, so this is what makes the back projection fast.
-__global__ void __launch_bounds__(kBlock) k_back_tof_lm(const float* __restrict__ xs, const float* __restrict__ xe,
-                                                        const int16_t* __restrict__ bins, int64_t n, GeomK g,
-                                                        TofK t, float* __restrict__ img,
-                                                        const float* __restrict__ p,
-                                                        const int32_t* __restrict__ order) {
-    const int64_t l = ray_index(order, n);
-    RayK r;
-    bool ok = l >= 0;
-    double c = 0.0;
-    float cl = 0.0f;
-    if (ok) {
-        const int b = bins[l];
-        const float pl = p[l];
-        ok = b >= 0 && b < t.nb && pl != 0.0f && ray_setup(xs + 3 * l, xe + 3 * l, g, r);
-        if (ok) {
-            c = t.c0 + b * t.bw;
-            ok = tof_window(r, c, t.win);
-            cl = r.ell * pl;
-        }
-    }
-    const int lo = ok ? r.k_lo : (1 << 30), hi = ok ? r.k_hi : -(1 << 30);
-    const int k0 = wave_min(lo), k1 = wave_max(hi);
-    for (int k = k0; k <= k1; ++k) {
-        const bool act = k >= lo && k <= hi;
-        Stencil st{};
-        float v = 0.0f;
-        if (act) {
-            st = stencil_at(r, k);
-            v = tof_weight(fma((double)k, r.ds, r.s0), c, t) * cl;
-        }
-        wave_stencil_scatter(img, act && v != 0.0f, r, st, v);
-    }
-}
-
 // ------------------------------------------------------- TOF sinogram ----
 //
 // Each thread keeps its n_bins accumulators in LDS (column per thread, so a
@@ -132,13 +70,6 @@ __global__ void __launch_bounds__(kBlock) k_back_tof_lm(const float* __restrict_
 // edge, so a window of m bins costs m + 1 erf evaluations.  The block's
 // [rays][bins] output tile is contiguous in memory and is written with
 // coalesced stores at the end.
-
-__device__ __forceinline__ void tof_bin_range(double s, const TofK& t, int& b_lo, int& b_hi) {
-    const double lo = floor((s - t.win - t.c0) / t.bw);
-    const double hi = ceil((s + t.win - t.c0) / t.bw);
-    b_lo = (int)fmax(lo, 0.0);
-    b_hi = (int)fmin(hi, (double)(t.nb - 1));
-}
 
 __global__ void k_fwd_tof_sino(const float* __restrict__ xs, const float* __restrict__ xe, int64_t n, GeomK g,
                                TofK t, const float* __restrict__ img, float* __restrict__ p) {
@@ -266,10 +197,25 @@ hipError_t launch_fwd(const float* xs, const float* xe, int64_t n, const GeomK& 
     return hipGetLastError();
 }
 
+// Back projections of ray lists go through the run/sheet kernel (sheet.hpp).
+template <class Mode>
+static hipError_t launch_runs(const Mode& m, const float* xs, const float* xe, int64_t n, const GeomK& g, float* img,
+                              const int32_t* order, hipStream_t s) {
+    const int nw = (g.n[2] <= kSheetMaxW) ? g.n[2] : 0;
+    const size_t lds = SheetLayout::bytes(nw);
+    hipError_t e = hipFuncSetAttribute((const void*)k_back_runs<Mode>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    const int64_t groups = kSheetGroups;
+    hipLaunchKernelGGL(k_back_runs<Mode>, dim3(grid_for(n, kSheetBlock * groups)), dim3(kSheetBlock), lds, s, m, xs,
+                       xe, n, g, img, order, nw, (int)groups);
+    return hipGetLastError();
+}
+
 hipError_t launch_back(const float* xs, const float* xe, int64_t n, const GeomK& g, float* img, const float* p,
                        const int32_t* order, hipStream_t s) {
-    hipLaunchKernelGGL(k_back, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, xs, xe, n, g, img, p, order);
-    return hipGetLastError();
+    ModeNonTof m{p};
+    return launch_runs(m, xs, xe, n, g, img, order, s);
 }
 
 hipError_t launch_fwd_tof_lm(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g,
@@ -281,9 +227,8 @@ hipError_t launch_fwd_tof_lm(const float* xs, const float* xe, const int16_t* bi
 
 hipError_t launch_back_tof_lm(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g,
                               const TofK& t, float* img, const float* p, const int32_t* order, hipStream_t s) {
-    hipLaunchKernelGGL(k_back_tof_lm, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, xs, xe, bins, n, g, t, img, p,
-                       order);
-    return hipGetLastError();
+    ModeTofLm m{p, bins, t};
+    return launch_runs(m, xs, xe, n, g, img, order, s);
 }
 
 static int sino_block(int nb) { return nb <= 64 ? 256 : 64; }  // LDS tile <= 64 KiB

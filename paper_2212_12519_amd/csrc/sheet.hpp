@@ -1,0 +1,416 @@
+// Run/sheet back projection for ordered ray lists (presorted listmode events,
+// radial-view-plane sinograms).
+//
+// Float atomic adds on this GPU are priced per cache-line request at the
+// memory side, so the direct scatter (4 atomics per plane sample) is bound by
+// request count.  In an ordered ray list, consecutive rays very often lie on
+// the same transaxial line: same principal axis p (0 or 1) and identical
+// in-plane coordinate U(k) = U0 + k dU at every plane k -- they differ only in
+// their axial coordinate W(k) and in their value.  All contributions of such a
+// run then fall into a "sheet" of the image: at plane k the two columns
+// (k, i0(k), :) and (k, i0(k) + 1, :) along the fastest axis (2).
+//
+// A workgroup takes 256 consecutive rays of the processing order and splits
+// them into runs (bitwise-equal p, U0, dU).  For every run of >= kRunMin rays
+// each thread becomes a plane k: it walks the run's rays and accumulates the
+// W-interpolated values into its own LDS column (thread-private addresses: no
+// atomics, no bank conflicts), then the waves flush the sheet with
+// contiguous, duplicate-free atomics -- one memory request per ~16 values
+// instead of one per value.  The u-weights (1 - fu, fu) are shared by the
+// run and applied at the flush.  Rays in short runs (or with p == 2, or grids
+// whose axis 2 exceeds the LDS column) take the direct wave-synchronous,
+// run-combined scatter.  The arithmetic per (ray, plane) sample is the same
+// as in the direct path; only the order of float additions differs.
+#pragma once
+
+#include "joseph.hpp"
+
+namespace ppmi {
+
+constexpr int kSheetBlock = 256;
+constexpr int kRunMin = 8;
+constexpr int kSheetMaxW = 128;  // largest axis-2 size with an LDS sheet
+constexpr int kSheetGroups = 8;  // groups of 256 rays per workgroup (a sheet persists across them)
+
+// LDS layout of k_back_runs (bytes): per-ray arrays, then the column buffer.
+struct SheetLayout {
+    static constexpr int kDoubles = 7;  // W0 dW s0 ds cen U0 dU
+    static constexpr int kInts = 9;     // lo hi pax start cnt klo khi list(+count) value
+    static size_t ray_bytes() { return (size_t)kSheetBlock * (kDoubles * 8 + kInts * 4) + 32; }
+    static size_t col_floats(int nw) { return (size_t)nw * (kSheetBlock + 1); }
+    static size_t bytes(int nw) { return ray_bytes() + col_floats(nw) * 4; }
+};
+
+// Per-ray value hooks:
+//   setup(l, r, cen, cv): prepare ray l (false = no contribution); cen = TOF bin centre (or 0),
+//                          cv = ell * p (the constant factor of every sample)
+//   sample(k, r-params): the value scattered at plane k
+struct ModeNonTof {
+    const float* __restrict__ p;
+    __device__ bool setup(int64_t l, const float* xs, const float* xe, const GeomK& g, RayK& r, double& cen,
+                          float& cv) const {
+        const float pl = p[l];
+        cen = 0.0;
+        if (pl == 0.0f || !ray_setup(xs + 3 * l, xe + 3 * l, g, r)) return false;
+        cv = r.ell * pl;
+        return true;
+    }
+    __device__ float sample(double /*s*/, double /*cen*/, float cv) const { return cv; }
+};
+
+struct ModeTofLm {
+    const float* __restrict__ p;
+    const int16_t* __restrict__ bins;
+    TofK t;
+    __device__ bool setup(int64_t l, const float* xs, const float* xe, const GeomK& g, RayK& r, double& cen,
+                          float& cv) const {
+        const int b = bins[l];
+        const float pl = p[l];
+        cen = t.c0 + b * t.bw;
+        if (b < 0 || b >= t.nb || pl == 0.0f || !ray_setup(xs + 3 * l, xe + 3 * l, g, r)) return false;
+        if (!tof_window(r, cen, t.win)) return false;
+        cv = r.ell * pl;
+        return true;
+    }
+    __device__ float sample(double s, double cen, float cv) const { return tof_weight(s, cen, t) * cv; }
+};
+
+// Broadcast lane `src` (wave-uniform) of a double to the whole wave through scalar registers.
+__device__ __forceinline__ double bcast(double v, int src) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// col[j][k] += a, col[j + 1][k] += b for the in-range entries (thread-private column k)
+__device__ __forceinline__ void col_add(float* col, int j, int k, float a, float b, int nw) {
+    constexpr int B = kSheetBlock;
+    if ((unsigned)j < (unsigned)nw && a != 0.0f) col[j * (B + 1) + k] += a;
+    if ((unsigned)(j + 1) < (unsigned)nw && b != 0.0f) col[(j + 1) * (B + 1) + k] += b;
+}
+
+// TOF sinogram: the sample value is ell * sum over the bins of the TOF window of w_b(s) p[l][b]
+// (neighbouring bins share their erf edge).  The ray index rides in the `cen` slot (exact in a
+// double for any ray count below 2^53); cv = ell.
+__device__ __forceinline__ void tof_bin_range(double s, const TofK& t, int& b_lo, int& b_hi) {
+    const double lo = floor((s - t.win - t.c0) / t.bw);
+    const double hi = ceil((s + t.win - t.c0) / t.bw);
+    b_lo = (int)fmax(lo, 0.0);
+    b_hi = (int)fmin(hi, (double)(t.nb - 1));
+}
+
+struct ModeTofSino {
+    const float* __restrict__ p;
+    TofK t;
+    __device__ bool setup(int64_t l, const float* xs, const float* xe, const GeomK& g, RayK& r, double& cen,
+                          float& cv) const {
+        cen = (double)l;
+        const float* pr = p + l * t.nb;
+        bool any = false;
+        for (int b = 0; b < t.nb; ++b) any |= (pr[b] != 0.0f);
+        if (!any || !ray_setup(xs + 3 * l, xe + 3 * l, g, r)) return false;
+        cv = r.ell;
+        return true;
+    }
+    __device__ float sample(double s, double cen, float cv) const {
+        const float* pr = p + (int64_t)cen * t.nb;
+        int b_lo, b_hi;
+        tof_bin_range(s, t, b_lo, b_hi);
+        const double x_hi0 = s - (t.c0 + b_lo * t.bw) + 0.5 * t.bw;
+        float g_hi = tof_cdf(x_hi0, t);
+        float c = 0.0f;
+        for (int b = b_lo; b <= b_hi; ++b) {
+            const float g_lo = tof_cdf(x_hi0 - (double)(b - b_lo + 1) * t.bw, t);
+            c += (g_hi - g_lo) * pr[b];
+            g_hi = g_lo;
+        }
+        return c * cv;
+    }
+};
+
+// Flush the sheet (planes kmin..kmax of line (p, U0, dU)) with contiguous atomics and clear it.
+__device__ __forceinline__ void sheet_flush(float* __restrict__ img, float* col, const GeomK& g, int p, double U0,
+                                            double dU, int kmin, int kmax, int nw) {
+    constexpr int B = kSheetBlock;
+    const int lane = (int)__lane_id();
+    const int wave = threadIdx.x >> 6;
+    const int su = (p == 0) ? g.stride[1] : g.stride[0];
+    const int sp = g.stride[p];
+    const int nu = (p == 0) ? g.n[1] : g.n[0];
+    for (int k = kmin + wave; k <= kmax; k += B / 64) {
+        const double U = fma((double)k, dU, U0);
+        const double fi = floor(U);
+        const int i0 = (int)fi;
+        const float fu = (float)(U - fi);
+        const bool ok0 = (unsigned)i0 < (unsigned)nu, ok1 = (unsigned)(i0 + 1) < (unsigned)nu;
+        const int base = k * sp + i0 * su;
+        for (int j = lane; j < nw; j += 64) {
+            float* cp = col + j * (B + 1) + k;
+            const float v = *cp;
+            if (v != 0.0f) {
+                *cp = 0.0f;
+                if (ok0) unsafeAtomicAdd(img + base + j, (1.0f - fu) * v);
+                if (ok1) unsafeAtomicAdd(img + base + su + j, fu * v);
+            }
+        }
+    }
+}
+
+// One workgroup walks `groups` consecutive groups of 256 rays of the processing
+// order.  The sheet of the current line persists across groups (thread t holds
+// the column of absolute plane t, so lines need n_p <= 256); it is flushed when a
+// run of another line starts, and at the end.
+template <class Mode>
+__device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, const float* __restrict__ xe, int64_t n,
+                                const GeomK& g, float* __restrict__ img, const int32_t* __restrict__ order,
+                                int nw_lds, int groups, int64_t chunk0, double* smem) {
+    constexpr int B = kSheetBlock;
+    double* W0 = smem;
+    double* dW = W0 + B;
+    double* s0 = dW + B;
+    double* ds = s0 + B;
+    double* cen = ds + B;
+    double* U0 = cen + B;
+    double* dU = U0 + B;
+    float* cvs = reinterpret_cast<float*>(dU + B);
+    int* lo = reinterpret_cast<int*>(cvs + B);
+    int* hi = lo + B;
+    int* pax = hi + B;
+    int* start = pax + B;
+    int* cnt = start + B;
+    int* klo = cnt + B;
+    int* khi = klo + B;
+    int* list = khi + B;  // sheet-run heads; count at list[B]; per-wave counts at list[B + 4 ..]
+    float* col = reinterpret_cast<float*>(list + B + 8);  // [nw][B + 1]
+
+    const int tid = threadIdx.x;
+    const int lane = (int)__lane_id();
+    const int wave = tid >> 6;
+    const int nw = g.n[2];
+    const bool sheets = nw_lds > 0 && nw <= nw_lds;
+    if (sheets)
+        for (int q = tid; q < nw * (B + 1); q += B) col[q] = 0.0f;
+    // current sheet (block-uniform copies in registers, updated after barriers)
+    bool sh_on = false;
+    int sh_p = -1, sh_kmin = 0, sh_kmax = -1;
+    double sh_U0 = 0.0, sh_dU = 0.0;
+    for (int grp = 0; grp < groups; ++grp) {
+        const int64_t i = chunk0 + (int64_t)grp * B + tid;
+        if (chunk0 + (int64_t)grp * B >= n) break;  // block-uniform
+        int64_t l = -1;
+        if (i < n) {
+            l = order ? (int64_t)order[i] : i;
+            if (l < 0 || l >= n) l = -1;
+        }
+        RayK r;
+        double c = 0.0;
+        float cv = 0.0f;
+        const bool ok = l >= 0 && m.setup(l, xs, xe, g, r, c, cv);
+        // compact the valid rays to the front of the group (stable order), so that rays
+        // without a contribution do not break runs
+        const unsigned long long vb = __ballot(ok);
+        __syncthreads();  // previous group's LDS readers are done
+        if (lane == 0) list[B + 4 + wave] = __popcll(vb);
+        __syncthreads();
+        int voff = 0, nvalid = 0;
+        for (int w = 0; w < B / 64; ++w) {
+            const int c_w = list[B + 4 + w];
+            voff += (w < wave) ? c_w : 0;
+            nvalid += c_w;
+        }
+        const int cp = ok ? voff + __popcll(vb & ((1ull << lane) - 1ull)) : -1;
+        if (ok) {
+            W0[cp] = r.W0;
+            dW[cp] = r.dW;
+            s0[cp] = r.s0;
+            ds[cp] = r.ds;
+            cen[cp] = c;
+            U0[cp] = r.U0;
+            dU[cp] = r.dU;
+            cvs[cp] = cv;
+            lo[cp] = r.k_lo;
+            hi[cp] = r.k_hi;
+            pax[cp] = r.p;
+        }
+        __syncthreads();
+        // runs over the compacted entries (thread t examines entry t): maximal stretches with
+        // bitwise-equal (p, U0, dU)
+        const bool e_ok = tid < nvalid;
+        const bool same =
+            e_ok && tid > 0 && pax[tid - 1] == pax[tid] && U0[tid - 1] == U0[tid] && dU[tid - 1] == dU[tid];
+        int st = (e_ok && !same) ? tid : -1;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int o = __shfl_up(st, off, 64);
+            if (lane >= off) st = max(st, o);
+        }
+        // carry across waves: latest head position of each earlier wave; boundary masks for lengths
+        const bool bnd = !(e_ok && same);  // a run head, or an entry past the valid ones
+        const unsigned long long bmask = __ballot(bnd);
+        if (lane == 63) start[wave] = st;
+        if (lane == 0) {
+            klo[2 * wave] = (int)(bmask & 0xffffffffull);
+            klo[2 * wave + 1] = (int)(bmask >> 32);
+        }
+        __syncthreads();
+        int carry = -1;
+        for (int w = 0; w < wave; ++w) carry = max(carry, start[w]);
+        // run length of a head: distance to the next boundary after it
+        int len = 0;
+        if (e_ok && !same) {
+            int w = wave;
+            unsigned long long mk = (lane == 63) ? 0ull : (bmask & (~0ull << (lane + 1)));
+            int nxt = B;
+            while (true) {
+                if (mk) {
+                    nxt = w * 64 + __ffsll((long long)mk) - 1;
+                    break;
+                }
+                if (++w >= B / 64) break;
+                mk = ((unsigned long long)(unsigned)klo[2 * w + 1] << 32) | (unsigned)klo[2 * w];
+            }
+            len = nxt - tid;
+        }
+        __syncthreads();
+        if (e_ok && same && st < 0) st = carry;
+        if (!e_ok) st = -1;
+        start[tid] = st;
+        cnt[tid] = len;
+        __syncthreads();
+        // a run goes to the sheet if it is long, or if it continues the current sheet's line
+        auto sheet_run = [&](int h) {
+            if (!sheets || cnt[h] == 0 || pax[h] == 2 || g.n[pax[h]] > B) return false;
+            if (cnt[h] >= kRunMin) return true;
+            return sh_on && pax[h] == sh_p && U0[h] == sh_U0 && dU[h] == sh_dU;
+        };
+        const bool in_sheet = ok && sheet_run(start[cp]);
+        // parallel compaction of the sheet-run heads (in order): ballot + prefix popcount
+        {
+            const bool f = sheet_run(tid);
+            const unsigned long long bal = __ballot(f);
+            if (lane == 0) list[B + 4 + wave] = __popcll(bal);
+            __syncthreads();
+            int off = 0, total = 0;
+            for (int w = 0; w < B / 64; ++w) {
+                const int c_w = list[B + 4 + w];
+                off += (w < wave) ? c_w : 0;
+                total += c_w;
+            }
+            if (f) list[off + __popcll(bal & ((1ull << lane) - 1ull))] = tid;
+            if (tid == 0) list[B] = total;
+        }
+        // direct path for the other rays: wave-synchronous, run-combined atomics
+        {
+            const bool d = ok && !in_sheet;
+            const int dlo = d ? r.k_lo : (1 << 30), dhi = d ? r.k_hi : -(1 << 30);
+            const int k0 = wave_min(dlo), k1 = wave_max(dhi);
+            for (int k = k0; k <= k1; ++k) {
+                const bool act = k >= dlo && k <= dhi;
+                Stencil stn{};
+                float v = 0.0f;
+                if (act) {
+                    stn = stencil_at(r, k);
+                    v = m.sample(fma((double)k, r.ds, r.s0), c, cv);
+                }
+                wave_stencil_scatter(img, act && v != 0.0f, r, stn, v);
+            }
+        }
+        __syncthreads();
+        const int n_long = list[B];
+        for (int li = 0; li < n_long; ++li) {
+            const int h = list[li];
+            const bool same_line = sh_on && pax[h] == sh_p && U0[h] == sh_U0 && dU[h] == sh_dU;
+            if (sh_on && !same_line) {
+                sheet_flush(img, col, g, sh_p, sh_U0, sh_dU, sh_kmin, sh_kmax, nw);
+                __syncthreads();
+                sh_on = false;
+            }
+            if (!sh_on) {
+                sh_on = true;
+                sh_p = pax[h];
+                sh_U0 = U0[h];
+                sh_dU = dU[h];
+                sh_kmin = 0;
+                sh_kmax = g.n[sh_p] - 1;
+            }
+            // thread tid accumulates the column of absolute plane k = tid.  Each wave loads 64 of
+            // the run's rays with one vector LDS read and broadcasts them lane by lane (readlane);
+            // four rays are evaluated branch-free per step so their dependency chains interleave,
+            // and the current pair of z entries stays in registers until z changes.
+            const int k = tid;
+            const int len = cnt[h];
+            const bool kin = k <= sh_kmax;
+            int jc = -2;
+            float accA = 0.0f, accB = 0.0f;
+            for (int b0 = h; b0 < h + len; b0 += 64) {
+                const int nb = min(64, h + len - b0);
+                const int q = b0 + min(lane, nb - 1);
+                const double qW0 = W0[q], qdW = dW[q], qs0 = s0[q], qds = ds[q], qcen = cen[q];
+                const int qcv = __float_as_int(cvs[q]);
+                const int qlo = lo[q], qhi = hi[q];
+                // rays whose plane window meets this wave's 64 planes (wave-uniform bit mask)
+                const int kw0 = wave * 64, kw1 = min(kw0 + 63, sh_kmax);
+                unsigned long long todo = __ballot(lane < nb && qlo <= kw1 && qhi >= kw0);
+                while (todo) {
+                    int ru[4], nu_ = 0;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        if (todo) {
+                            ru[u] = __ffsll((long long)todo) - 1;
+                            todo &= todo - 1ull;
+                            ++nu_;
+                        } else {
+                            ru[u] = ru[0];
+                        }
+                    }
+                    int j0v[4];
+                    float fwv[4], vv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int rlo = __builtin_amdgcn_readlane(qlo, ru[u]);
+                        const int rhi = __builtin_amdgcn_readlane(qhi, ru[u]);
+                        const bool act = kin && u < nu_ && k >= rlo && k <= rhi;
+                        const double W = fma((double)k, bcast(qdW, ru[u]), bcast(qW0, ru[u]));
+                        const double fj = floor(W);
+                        j0v[u] = (int)fj;
+                        fwv[u] = (float)(W - fj);
+                        const float v = m.sample(fma((double)k, bcast(qds, ru[u]), bcast(qs0, ru[u])),
+                                                 bcast(qcen, ru[u]),
+                                                 __int_as_float(__builtin_amdgcn_readlane(qcv, ru[u])));
+                        vv[u] = act ? v : 0.0f;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        if (vv[u] != 0.0f) {
+                            if (j0v[u] != jc) {
+                                col_add(col, jc, k, accA, accB, nw);
+                                jc = j0v[u];
+                                accA = 0.0f;
+                                accB = 0.0f;
+                            }
+                            accA += (1.0f - fwv[u]) * vv[u];
+                            accB += fwv[u] * vv[u];
+                        }
+                    }
+                }
+            }
+            col_add(col, jc, k, accA, accB, nw);
+            __syncthreads();
+        }
+    }
+    if (sh_on) sheet_flush(img, col, g, sh_p, sh_U0, sh_dU, sh_kmin, sh_kmax, nw);
+    __syncthreads();  // the LDS may be reused by the caller
+}
+
+template <class Mode>
+__global__ void __launch_bounds__(kSheetBlock) k_back_runs(Mode m, const float* __restrict__ xs,
+                                                          const float* __restrict__ xe, int64_t n, GeomK g,
+                                                          float* __restrict__ img, const int32_t* __restrict__ order,
+                                                          int nw_lds, int groups) {
+    extern __shared__ double smem[];
+    const int64_t chunk0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * groups * kSheetBlock;
+    back_runs_chunk(m, xs, xe, n, g, img, order, nw_lds, groups, chunk0, smem);
+}
+
+}  // namespace ppmi

@@ -88,9 +88,9 @@ def test_error_codes(lib):
 def test_osem_chunks(lib):
     assert lib.pp_osem_chunks(0, 8) == 0
     assert lib.pp_osem_chunks(1, 8) == 1
-    assert lib.pp_osem_chunks(8 * 256, 8) == 1
-    assert lib.pp_osem_chunks(8 * 256 + 1, 8) == 2
-    assert lib.pp_osem_chunks(20_000_000, 8) == (2_500_000 + 255) // 256
+    assert lib.pp_osem_chunks(8 * 1024, 8) == 1
+    assert lib.pp_osem_chunks(8 * 1024 + 1, 8) == 2
+    assert lib.pp_osem_chunks(20_000_000, 8) == (2_500_000 + 1023) // 1024
 
 
 def test_python_binding_rejects_cpu_tensors():
