@@ -31,16 +31,19 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 
 
+# the sources the listmode step's kernels and their launch configuration are built from
+STEP_SOURCES = ("api.hip", "joseph.hpp", "launch.hpp", "presort.hip", "projectors.hip", "sheet.hpp")
+
+
 def kernel_sources_sha():
-    """sha256 over every HIP source of the library (sorted by name)."""
+    """sha256 over the sources of the listmode step's kernels."""
     import hashlib
 
     d = os.path.join(ROOT, "paper_2212_12519_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(f.encode())
-            h.update(open(os.path.join(d, f), "rb").read())
+    for f in STEP_SOURCES:
+        h.update(f.encode())
+        h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()
 
 
@@ -99,7 +102,7 @@ def write_traffic(fetch_csv, write_csv, copy_bytes=1 << 30):
                           "traffic_bytes": 1024.0 * (f * fs + w * ws)}
     rec = {"kernels": kernels, "copy_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
            "fetch_scale": fs, "write_scale": ws, "source_sha256": kernel_sources_sha(),
-           "sources": "paper_2212_12519_amd/csrc/*.hip, *.hpp"}
+           "sources": ["paper_2212_12519_amd/csrc/" + f for f in STEP_SOURCES]}
     with open(TRAFFIC_JSON, "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec, indent=1))
@@ -121,6 +124,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
     ap.add_argument("--only", default=None, help="profiling helper: lm | sino | serve")
     ap.add_argument("--serve-requests", type=int, default=None, help="requests in the serving leg (default 256)")
+    ap.add_argument("--no-res", action="store_true", help="serving leg without the resolution model")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
                     help="no GPU work: write the traffic record from two rocprofv3 counter CSVs of --only lm")
     return ap.parse_args()
@@ -223,7 +227,7 @@ def cpu_leg(args, lm_inputs, C):
         oracle.back_tof_lm(a, b, g.origin, g.voxsize, g.dim, tof, c, pv)
         return time.perf_counter() - t0
 
-    n0 = 100_000
+    n0 = 500_000
     t_cal = run(n0)
     n = int(min(xs.shape[0], max(n0, n0 * args.cpu_seconds / max(t_cal, 1e-6))))
     dt = run(n)

@@ -61,15 +61,16 @@
 extern "C" {
 #endif
 
-#define PP_ABI_VERSION 1
+#define PP_ABI_VERSION 2
 
 enum pp_status {
     PP_OK = 0,
     PP_EINVAL_PTR = 1,  /* a required pointer is NULL */
-    PP_EINVAL_GEOM = 2, /* dim <= 0, voxel count >= 2^31, voxsize <= 0 or non-finite, origin non-finite */
+    PP_EINVAL_GEOM = 2, /* dim <= 0, voxel count > 2^30, voxsize <= 0 or non-finite, origin non-finite */
     PP_EINVAL_TOF = 3,  /* n_bins not in [1, 256], bin_width/sigma/n_sigmas <= 0 or non-finite */
     PP_EINVAL_N = 4,    /* negative count, or a count/slot argument out of range */
-    PP_EHIP = 5         /* the HIP runtime rejected a launch */
+    PP_EHIP = 5,        /* the HIP runtime rejected a launch */
+    PP_EINVAL_RES = 6   /* resolution model: FWHM negative or non-finite, or wider than 31 voxels of radius */
 };
 
 typedef struct pp_image {
@@ -156,10 +157,16 @@ int pp_count_samples(const float* xstart, const float* xend, const int16_t* tof_
  * Batched listmode TOF OSEM (the paper's listmode OSEM of Sec. 2.6, run for
  * many short frames at once).  One "step" of a frame is one ordered-subset
  * update with subset j = {events e : e mod n_sub == j}:
- *     acc  = sum_{e in subset j} a_e / (a_e . x + bg)      (pp_lm_osem_accumulate)
- *     x_v <- x_v * acc_v / (sens_v / n_sub) if sens_v > 0, else 0;  acc <- 0
+ *     acc  = sum_{e in subset j} a_e / (a_e . x' + bg)     (pp_lm_osem_accumulate)
+ *     x_v <- x_v * acc'_v / (sens_v / n_sub) if sens_v > 0, else 0;  acc <- 0
  *                                                           (pp_lm_osem_update)
- * An event whose expectation a_e . x + bg is not positive contributes nothing.
+ * An event whose expectation a_e . x' + bg is not positive contributes nothing.
+ * Without the resolution model (x_fwd == NULL) x' = x and acc' = acc.  With it
+ * (x_fwd and tmp set) the system model is the projector after the Gaussian
+ * blur G of pp_gauss3d (the paper's OSEM includes such an image-based model):
+ * x' = x_fwd = G x, acc' = G acc, and sens must be G applied to the back
+ * projection of ones; before the first step x_fwd must hold G x
+ * (pp_gauss3d(x, x_fwd, tmp, ...)).  pp_lm_osem_update keeps x_fwd = G x.
  * Event storage of a frame is SUBSET-MAJOR: subset j occupies the contiguous
  * range [off_j, off_j + n_j), n_j = n / n_sub + (j < n mod n_sub),
  * off_j = j (n / n_sub) + min(j, n mod n_sub), in any order inside the range
@@ -189,6 +196,9 @@ typedef struct pp_osem_slot {
     int32_t steps_left;      /* steps still to run; 0 = finished */
     int32_t active;          /* 0 = empty slot */
     int32_t reserved;
+    float* x_fwd;            /* [n_vox] G x for the resolution model, or NULL (no model) */
+    float* tmp;              /* [n_vox] scratch of the resolution model; required when x_fwd is set
+                              * (a slot with x_fwd but no tmp is skipped by every call) */
 } pp_osem_slot_t;
 
 /* Work chunks a slot needs per step (events of the largest subset / 1024,
@@ -202,11 +212,26 @@ int pp_lm_osem_accumulate(const pp_osem_slot_t* d_slots, int32_t n_slots, const 
                           const pp_tof_t* tof, void* stream);
 
 /* Multiplicative image update of every live slot, then acc <- 0, subset
- * advanced, steps_left decremented.  n_vox must equal the grid's voxel count. */
-int pp_lm_osem_update(pp_osem_slot_t* d_slots, int32_t n_slots, int64_t n_vox, void* stream);
+ * advanced, steps_left decremented.  geom: the slots' common image grid.
+ * res_fwhm: host array of 3 FWHM values in mm (per image axis) of the
+ * resolution model, applied to the slots that have x_fwd set; NULL = FWHM 0
+ * (G = identity).  Errors: PP_EINVAL_RES as for pp_gauss3d. */
+int pp_lm_osem_update(pp_osem_slot_t* d_slots, int32_t n_slots, const pp_image_t* geom, const float* res_fwhm,
+                      void* stream);
 
 /* OSEM start image: x_v = 1 where sens_v > 0, else 0. */
 int pp_osem_init(float* x, const float* sens, int64_t n_vox, void* stream);
+
+/* Image-based resolution model (the paper's listmode OSEM uses a 3D Gaussian
+ * of 4.5 mm FWHM, Sec. 2.6): dst = G src, G the discrete Gaussian blur with,
+ * along image axis a, taps exp(-i^2 / (2 s_a^2)) for |i| <= floor(4 s_a + 1/2),
+ * normalised to sum 1, where s_a = fwhm[a] / (2 sqrt(2 ln 2)) / voxsize[a]
+ * voxels (fwhm[a] == 0: no blur along a); voxels outside the grid count as 0.
+ * G is symmetric (its own adjoint).  src, dst, tmp: DEVICE float arrays of
+ * the grid's voxel count, pairwise non-overlapping (tmp is overwritten).
+ * fwhm: host array of 3 values in mm.  Errors: PP_EINVAL_PTR (NULL or
+ * overlapping arrays), PP_EINVAL_GEOM, PP_EINVAL_RES. */
+int pp_gauss3d(const float* src, float* dst, float* tmp, const pp_image_t* geom, const float* fwhm, void* stream);
 
 /* Sets n floats at dst to value (a kernel, safe inside captured graphs). */
 int pp_fill(float* dst, int64_t n, float value, void* stream);

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libppmi.so")
 _lib = None
 
-PP_OK, PP_EINVAL_PTR, PP_EINVAL_GEOM, PP_EINVAL_TOF, PP_EINVAL_N, PP_EHIP = range(6)
+PP_OK, PP_EINVAL_PTR, PP_EINVAL_GEOM, PP_EINVAL_TOF, PP_EINVAL_N, PP_EHIP, PP_EINVAL_RES = range(7)
 
 
 class PPError(RuntimeError):
@@ -40,10 +40,11 @@ class COsemSlot(ctypes.Structure):
                 ("x", ctypes.c_void_p), ("acc", ctypes.c_void_p), ("sens", ctypes.c_void_p),
                 ("n_events", ctypes.c_int64), ("chunk_begin", ctypes.c_int64), ("bg", ctypes.c_float),
                 ("n_sub", ctypes.c_int32), ("subset", ctypes.c_int32), ("steps_left", ctypes.c_int32),
-                ("active", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("active", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("x_fwd", ctypes.c_void_p), ("tmp", ctypes.c_void_p)]
 
 
-assert ctypes.sizeof(COsemSlot) == 88, ctypes.sizeof(COsemSlot)
+assert ctypes.sizeof(COsemSlot) == 104, ctypes.sizeof(COsemSlot)
 
 
 @dataclass(frozen=True)
@@ -117,7 +118,8 @@ def load():
         "pp_gather_events": [P, P, P, P, I64, P, P, P, P],
         "pp_osem_init": [P, P, I64, P],
         "pp_lm_osem_accumulate": [P, I32, G, T, P],
-        "pp_lm_osem_update": [P, I32, I64, P],
+        "pp_lm_osem_update": [P, I32, G, P, P],
+        "pp_gauss3d": [P, P, P, G, P, P],
         "pp_fill": [P, I64, ctypes.c_float, P],
         "pp_count_samples": [P, P, P, I64, G, T, P, P],
     }

@@ -60,6 +60,35 @@ int make_tof(const pp_tof_t* ti, TofK& t) {
     return PP_OK;
 }
 
+// Resolution-model taps (definition in ppmi.h at pp_gauss3d); fwhm == NULL: no blur.
+int make_gauss(const float* fwhm, const GeomK& g, GaussK& k) {
+    for (int a = 0; a < 3; ++a) {
+        const double f = fwhm ? (double)fwhm[a] : 0.0;
+        if (!std::isfinite(f) || f < 0.0) return PP_EINVAL_RES;
+        for (int i = 0; i < 2 * kGaussMaxR + 1; ++i) k.w[a][i] = 0.0f;
+        if (f == 0.0) {
+            k.r[a] = 0;
+            k.w[a][0] = 1.0f;
+            continue;
+        }
+        const double sig = f / (2.0 * std::sqrt(2.0 * std::log(2.0))) / g.h[a];
+        const double rr = std::floor(4.0 * sig + 0.5);
+        if (!(rr <= kGaussMaxR)) return PP_EINVAL_RES;
+        const int r = (int)rr;
+        double w[2 * kGaussMaxR + 1], sum = 0.0;
+        for (int i = -r; i <= r; ++i) sum += (w[i + r] = std::exp(-(double)i * i / (2.0 * sig * sig)));
+        for (int i = 0; i <= 2 * r; ++i) k.w[a][i] = (float)(w[i] / sum);
+        k.r[a] = r;
+    }
+    return PP_OK;
+}
+
+bool overlap(const void* a, const void* b, int64_t bytes) {
+    const char* p = static_cast<const char*>(a);
+    const char* q = static_cast<const char*>(b);
+    return p < q + bytes && q < p + bytes;
+}
+
 // grid limit: 2^31 - 1 workgroups of >= 64 threads
 constexpr int64_t kMaxRays = ((int64_t(1) << 31) - 1) * 64;
 
@@ -94,6 +123,7 @@ const char* pp_strerror(int code) {
         case PP_EINVAL_TOF: return "invalid TOF parameters (n_bins not in [1,256], or width/sigma/n_sigmas <= 0)";
         case PP_EINVAL_N: return "count or slot argument out of range";
         case PP_EHIP: return g_hip_msg[0] ? g_hip_msg : "HIP launch error";
+        case PP_EINVAL_RES: return "invalid resolution model (FWHM < 0 or non-finite, or radius > 31 voxels)";
         default: return "unknown status code";
     }
 }
@@ -228,15 +258,39 @@ int pp_lm_osem_accumulate(const pp_osem_slot_t* d_slots, int32_t n_slots, const 
     return hip_status(launch_osem_accumulate(d_slots, n_slots, g, t, device_cus() * 2, as_stream(stream)));
 }
 
-int pp_lm_osem_update(pp_osem_slot_t* d_slots, int32_t n_slots, int64_t n_vox, void* stream) {
-    if (n_slots < 0 || n_slots > (1 << 20) || n_vox <= 0 || n_vox > (int64_t(1) << 30)) return PP_EINVAL_N;
+int pp_lm_osem_update(pp_osem_slot_t* d_slots, int32_t n_slots, const pp_image_t* geom, const float* res_fwhm,
+                      void* stream) {
+    GeomK g;
+    GaussK k;
+    PP_TRY(make_geom(geom, g));
+    PP_TRY(make_gauss(res_fwhm, g, k));
+    if (n_slots < 0 || n_slots > (1 << 20)) return PP_EINVAL_N;
     if (n_slots == 0) return PP_OK;
     if (!d_slots) return PP_EINVAL_PTR;
+    const int64_t n_vox = (int64_t)g.n[0] * g.n[1] * g.n[2];
     const int64_t total = (int64_t)n_slots * n_vox;
     int64_t blocks = (total + 255) / 256;
-    const int64_t cap = (int64_t)device_cus() * 16;
+    const int cus = device_cus();
+    const int64_t cap = (int64_t)cus * 16;
     if (blocks > cap) blocks = cap;
-    return hip_status(launch_osem_update(d_slots, n_slots, n_vox, (int)blocks, as_stream(stream)));
+    hipStream_t s = as_stream(stream);
+    // slots without the model: plain update; slots with it: the blur passes with the fused update;
+    // then every updated slot advances
+    hipError_t e = launch_osem_update(d_slots, n_slots, n_vox, (int)blocks, s);
+    if (e == hipSuccess) e = launch_osem_res_update(d_slots, n_slots, g, k, cus, s);
+    if (e == hipSuccess) e = launch_osem_advance(d_slots, n_slots, s);
+    return hip_status(e);
+}
+
+int pp_gauss3d(const float* src, float* dst, float* tmp, const pp_image_t* geom, const float* fwhm, void* stream) {
+    GeomK g;
+    GaussK k;
+    PP_TRY(make_geom(geom, g));
+    if (!src || !dst || !tmp || !fwhm) return PP_EINVAL_PTR;
+    PP_TRY(make_gauss(fwhm, g, k));
+    const int64_t bytes = (int64_t)g.n[0] * g.n[1] * g.n[2] * (int64_t)sizeof(float);
+    if (overlap(src, dst, bytes) || overlap(src, tmp, bytes) || overlap(dst, tmp, bytes)) return PP_EINVAL_PTR;
+    return hip_status(launch_gauss3d(src, dst, tmp, g, k, device_cus(), as_stream(stream)));
 }
 
 int pp_fill(float* dst, int64_t n, float value, void* stream) {

@@ -34,6 +34,13 @@ struct TofK {
     int nb;               // bins
 };
 
+// Resolution-model blur taps per axis: w[a][i + r[a]] for |i| <= r[a].
+constexpr int kGaussMaxR = 31;
+struct GaussK {
+    int r[3];
+    float w[3][2 * kGaussMaxR + 1];
+};
+
 // A ray prepared for plane stepping along its principal axis p.
 struct RayK {
     double U0, dU;  // in-plane voxel coordinate along axis u at plane k: U0 + k dU

@@ -14,7 +14,8 @@
 // ratio and back projection fused, the event set up once.  The scatter is the
 // run/sheet back projection of sheet.hpp (LDS sheets for runs of events on one
 // transaxial line, run-combined atomics for the rest).
-// k_osem_update: x <- x * acc / (sens / n_sub) (0 where sens == 0), acc <- 0.
+// k_osem_update: x <- x * acc / (sens / n_sub) (0 where sens == 0), acc <- 0, for
+// the slots without the resolution model (blur.hip updates the others).
 // k_osem_advance: next subset, one step fewer.
 #include <hip/hip_runtime.h>
 
@@ -28,7 +29,10 @@ constexpr int kOsemBlock = 256;
 constexpr int kOsemGroups = 4;
 constexpr int64_t kOsemChunk = (int64_t)kSheetBlock * kOsemGroups;  // events of one work chunk
 
-__device__ __forceinline__ bool slot_live(const pp_osem_slot_t& s) { return s.active && s.steps_left > 0; }
+// live: active with steps to run, and (without the resolution model, or with its scratch image)
+__device__ __forceinline__ bool slot_live(const pp_osem_slot_t& s) {
+    return s.active && s.steps_left > 0 && (s.x_fwd == nullptr || s.tmp != nullptr);
+}
 
 __host__ __device__ inline int64_t slot_chunks(int64_t n_events, int32_t n_sub) {
     if (n_events <= 0 || n_sub <= 0) return 0;
@@ -82,7 +86,7 @@ __global__ void __launch_bounds__(kSheetBlock) k_osem_accumulate(const pp_osem_s
         const int64_t off_j = j * base_n + (j < rem ? j : rem);
         const int64_t q0 = (c - s.chunk_begin) * kOsemChunk;
         if (q0 >= n_j) continue;
-        ModeOsem m{s.x, s.tof_bin + off_j, s.bg, t};
+        ModeOsem m{s.x_fwd ? s.x_fwd : s.x, s.tof_bin + off_j, s.bg, t};
         back_runs_chunk(m, s.xstart + 3 * off_j, s.xend + 3 * off_j, n_j, g, s.acc, nullptr, nw_lds, kOsemGroups,
                         q0, smem);
     }
@@ -96,7 +100,7 @@ __global__ void __launch_bounds__(kOsemBlock) k_osem_update(const pp_osem_slot_t
         const int si = (int)(i / n_vox);
         const int64_t v = i - (int64_t)si * n_vox;
         const pp_osem_slot_t& s = slots[si];
-        if (!slot_live(s)) continue;
+        if (!slot_live(s) || s.x_fwd != nullptr) continue;  // resolution-model slots: blur.hip
         const float sv = s.sens[v];
         const float a = s.acc[v];
         s.x[v] = (sv > 0.0f) ? s.x[v] * a / (sv / (float)s.n_sub) : 0.0f;
@@ -139,8 +143,10 @@ hipError_t launch_osem_accumulate(const pp_osem_slot_t* slots, int n_slots, cons
 
 hipError_t launch_osem_update(pp_osem_slot_t* slots, int n_slots, int64_t n_vox, int n_blocks, hipStream_t s) {
     hipLaunchKernelGGL(k_osem_update, dim3(n_blocks), dim3(kOsemBlock), 0, s, slots, n_slots, n_vox);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_osem_advance(pp_osem_slot_t* slots, int n_slots, hipStream_t s) {
     hipLaunchKernelGGL(k_osem_advance, dim3(1), dim3(256), 0, s, slots, n_slots);
     return hipGetLastError();
 }

@@ -10,6 +10,9 @@ Reading of the method used throughout (same as the FP64 oracle): subset j
 holds the events with index e mod n_sub == j in the frame's own event order;
 x0 = 1 where the sensitivity is positive, else 0; each subset update is
 x <- x * A_j^T (1 / (A_j x + bg)) / (sens / n_sub), zero where sens == 0.
+With the image-based resolution model (the paper's reconstructions use a 3D
+Gaussian of 4.5 mm FWHM, Sec. 2.6) the system model is A G: the forward
+projects G x, the back projection is followed by G, and sens = G A^T 1.
 """
 from __future__ import annotations
 
@@ -18,9 +21,10 @@ import ctypes
 import torch
 
 from ._lib import COsemSlot, as_geom, as_tof, check, load, ptr, stream_of
-from .projectors import back, gather_events, presort
+from .projectors import back, fwhm3, gather_events, pp_gauss3d, presort
 
 SLOT_BYTES = ctypes.sizeof(COsemSlot)
+RES_FWHM_MM = 4.5  # the paper's resolution model
 
 
 def prepare_frame(xstart, xend, tof_bin, geom, tof, n_sub):
@@ -29,8 +33,9 @@ def prepare_frame(xstart, xend, tof_bin, geom, tof, n_sub):
     return gather_events(xstart, xend, tof_bin, order)
 
 
-def sensitivity(lor_start, lor_end, geom, chunk=1 << 26):
-    """Non-TOF back projection of ones over a LOR set (the scanner's sinogram LORs)."""
+def sensitivity(lor_start, lor_end, geom, chunk=1 << 26, res_fwhm=None):
+    """Non-TOF back projection of ones over a LOR set (the scanner's sinogram LORs), followed by
+    the resolution model when `res_fwhm` is given."""
     g = as_geom(geom)
     dev = lor_start.device
     sens = torch.zeros(g.dim, dtype=torch.float32, device=dev)
@@ -38,6 +43,10 @@ def sensitivity(lor_start, lor_end, geom, chunk=1 << 26):
         b = min(lor_start.shape[0], a + chunk)
         ones = torch.ones(b - a, dtype=torch.float32, device=dev)
         back(lor_start[a:b], lor_end[a:b], g, ones, img=sens)
+    if res_fwhm is not None:
+        out, tmp = torch.empty_like(sens), torch.empty_like(sens)
+        pp_gauss3d(sens, out, tmp, g, res_fwhm)
+        sens = out
     return sens
 
 
@@ -51,10 +60,16 @@ class SlotTable:
         self.dev = torch.zeros(self.capacity * SLOT_BYTES, dtype=torch.uint8, device=device)
         self._copied = None
 
-    def set(self, i, xs, xe, tb, x, acc, sens, n_sub, steps, bg):
+    def set(self, i, xs, xe, tb, x, acc, sens, n_sub, steps, bg, x_fwd=None, tmp=None):
+        """Slot i <- a frame.  x_fwd and tmp (both or neither): the resolution model's G x (set
+        before the first step) and its scratch image."""
+        if (x_fwd is None) != (tmp is None):
+            raise ValueError("x_fwd and tmp go together")
         s = self.host[i]
         s.xstart, s.xend, s.tof_bin = xs.data_ptr(), xe.data_ptr(), tb.data_ptr()
         s.x, s.acc, s.sens = x.data_ptr(), acc.data_ptr(), sens.data_ptr()
+        s.x_fwd = None if x_fwd is None else x_fwd.data_ptr()
+        s.tmp = None if tmp is None else tmp.data_ptr()
         s.n_events = xs.shape[0]
         s.bg = float(bg)
         s.n_sub = int(n_sub)
@@ -89,24 +104,26 @@ class SlotTable:
                     s.steps_left -= 1
 
 
-def osem_steps(table: SlotTable, geom, tof, n_steps=1):
-    """Enqueue n_steps subset updates for every live slot of the table (current stream)."""
+def osem_steps(table: SlotTable, geom, tof, n_steps=1, res_fwhm=None):
+    """Enqueue n_steps subset updates for every live slot of the table (current stream);
+    res_fwhm (mm) is the resolution model of the slots that have x_fwd set."""
     g, t = as_geom(geom), as_tof(tof)
     lib = load()
     gc, tc = g.c(), t.c()
+    fw = None if res_fwhm is None else fwhm3(res_fwhm)
     st = stream_of(table.dev)
     for _ in range(n_steps):
         check(lib.pp_lm_osem_accumulate(ptr(table.dev), table.capacity, gc, tc, st))
-        check(lib.pp_lm_osem_update(ptr(table.dev), table.capacity, g.n_vox, st))
+        check(lib.pp_lm_osem_update(ptr(table.dev), table.capacity, gc, fw, st))
 
 
-def capture_steps(table: SlotTable, geom, tof, n_steps=1):
+def capture_steps(table: SlotTable, geom, tof, n_steps=1, res_fwhm=None):
     """A HIP graph of n_steps subset updates over the table (replay serves any slot mix)."""
     graph = torch.cuda.CUDAGraph()
     cap = torch.cuda.Stream(device=table.dev.device)
     cap.wait_stream(torch.cuda.current_stream(table.dev.device))
     with torch.cuda.graph(graph, stream=cap):
-        osem_steps(table, geom, tof, n_steps)
+        osem_steps(table, geom, tof, n_steps, res_fwhm)
     torch.cuda.current_stream(table.dev.device).wait_stream(cap)
     return graph
 
@@ -117,16 +134,28 @@ def init_image(sens):
     return x
 
 
-def lm_osem(xstart, xend, tof_bin, geom, tof, sens, n_iter, n_sub, bg=0.1, x0=None):
-    """Listmode TOF OSEM of one frame (events in the frame's own order) on the fused kernels."""
+def res_buffers(x, geom, res_fwhm):
+    """(x_fwd = G x, tmp) for a frame that uses the resolution model."""
+    x_fwd, tmp = torch.empty_like(x), torch.empty_like(x)
+    pp_gauss3d(x, x_fwd, tmp, geom, res_fwhm)
+    return x_fwd, tmp
+
+
+def lm_osem(xstart, xend, tof_bin, geom, tof, sens, n_iter, n_sub, bg=0.1, x0=None, res_fwhm=None):
+    """Listmode TOF OSEM of one frame (events in the frame's own order) on the fused kernels;
+    with `res_fwhm` (mm) the system model includes the Gaussian resolution model (then `sens`
+    must include it too, see `sensitivity`)."""
     g = as_geom(geom)
     xs, xe, tb = prepare_frame(xstart, xend, tof_bin, g, tof, n_sub)
     x = init_image(sens) if x0 is None else x0.clone()
     acc = torch.zeros_like(sens)
+    x_fwd = tmp = None
+    if res_fwhm is not None:
+        x_fwd, tmp = res_buffers(x, g, res_fwhm)
     table = SlotTable(1, xstart.device)
-    table.set(0, xs, xe, tb, x, acc, sens, n_sub, n_iter * n_sub, bg)
+    table.set(0, xs, xe, tb, x, acc, sens, n_sub, n_iter * n_sub, bg, x_fwd, tmp)
     table.upload()
-    osem_steps(table, g, tof, n_iter * n_sub)
+    osem_steps(table, g, tof, n_iter * n_sub, res_fwhm)
     torch.cuda.current_stream(x.device).synchronize()
     del xs, xe, tb
     return x

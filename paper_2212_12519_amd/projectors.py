@@ -6,6 +6,8 @@ allocate the output with torch and call the ``pp_*`` function.
 """
 from __future__ import annotations
 
+import ctypes
+
 import torch
 
 from ._lib import _bins, _dev, _img, _order, _rays, as_geom, as_tof, check, load, ptr, stream_of
@@ -148,6 +150,32 @@ def pp_fill(dst, value):
         raise TypeError("float32 only")
     check(load().pp_fill(ptr(dst), dst.numel(), float(value), stream_of(dst)))
     return dst
+
+
+def fwhm3(fwhm):
+    """A resolution-model FWHM (mm, scalar or per axis) as the C float[3] the library takes."""
+    if isinstance(fwhm, (int, float)):
+        fwhm = (fwhm, fwhm, fwhm)
+    f = [float(v) for v in fwhm]
+    if len(f) != 3:
+        raise ValueError("fwhm: a scalar or 3 values")
+    return (ctypes.c_float * 3)(*f)
+
+
+def pp_gauss3d(src, dst, tmp, geom, fwhm):
+    """dst = G src, the Gaussian resolution model of FWHM `fwhm` mm; tmp is overwritten."""
+    g = as_geom(geom)
+    _dev(src, dst, tmp)
+    for a in (src, dst, tmp):
+        _img(a, g)
+    check(load().pp_gauss3d(ptr(src), ptr(dst), ptr(tmp), g.c(), fwhm3(fwhm), stream_of(dst)))
+    return dst
+
+
+def gauss3d(img, geom, fwhm):
+    """The image blurred by the resolution model (a new tensor)."""
+    dst, tmp = torch.empty_like(img), torch.empty_like(img)
+    return pp_gauss3d(img, dst, tmp, geom, fwhm)
 
 
 def pp_count_samples(xstart, xend, tof_bin, geom, tof, counts):

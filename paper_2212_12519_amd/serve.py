@@ -14,11 +14,15 @@ subsets) arrive over time.  The server
   frames leave (continuous batching at subset granularity);
 * replays a HIP graph captured once per grid (the slot table is read from
   device memory, so the same graph serves every mix);
+* optionally includes the image-based Gaussian resolution model in the
+  system model (the paper's OSEM does, Sec. 2.6): blur passes per step inside
+  the same graph;
 * records arrival, admission and completion times for p50 / p99 latency.
 
 ``run_sequential`` is the baseline: the same trace served one frame at a
 time, FIFO, with plain projector calls (pp_fwd_tof_lm, a torch ratio,
-pp_back_tof_lm, a torch image update) per subset.
+pp_back_tof_lm, a torch image update; pp_gauss3d around them with the
+resolution model) per subset.
 """
 from __future__ import annotations
 
@@ -32,7 +36,7 @@ import torch
 
 from ._lib import as_geom, as_tof, load
 from . import osem as O
-from .projectors import back_tof_lm, fwd_tof_lm
+from .projectors import back_tof_lm, fwd_tof_lm, gauss3d
 
 
 @dataclass
@@ -61,9 +65,10 @@ class OsemResult:
         return self.finished - self.arrival
 
 
-def frame_footprint(n_events, n_vox):
-    """HBM bytes a frame holds while admitted: presorted event copy (26 B/event), x and acc."""
-    return 26 * int(n_events) + 2 * 4 * int(n_vox)
+def frame_footprint(n_events, n_vox, res=False):
+    """HBM bytes a frame holds while admitted: presorted event copy (26 B/event), x and acc
+    (plus x_fwd and the scratch image with the resolution model)."""
+    return 26 * int(n_events) + (4 if res else 2) * 4 * int(n_vox)
 
 
 @dataclass
@@ -89,8 +94,11 @@ class _GridState:
 
 class OsemServer:
     def __init__(self, tof, sens_by_grid, max_slots=64, hbm_budget=32e9, steps_per_tick=1, use_graph=True,
-                 device="cuda"):
+                 device="cuda", res_fwhm=None):
+        """sens_by_grid: [(geom, sensitivity image)], the sensitivity including the resolution
+        model when res_fwhm (mm) is given."""
         self.tof = as_tof(tof)
+        self.res_fwhm = res_fwhm
         self.device = torch.device(device)
         self.budget = float(hbm_budget)
         self.steps = int(steps_per_tick)
@@ -107,7 +115,7 @@ class OsemServer:
         st = self.grids[as_geom(req.grid)]
         if not st.free:
             return False
-        nbytes = frame_footprint(req.xstart.shape[0], st.geom.n_vox)
+        nbytes = frame_footprint(req.xstart.shape[0], st.geom.n_vox, self.res_fwhm is not None)
         if nbytes > self.budget:
             self.rejected.append(req.rid)  # can never fit: refuse instead of blocking the queue
             return True
@@ -117,8 +125,11 @@ class OsemServer:
         xs, xe, tb = O.prepare_frame(req.xstart, req.xend, req.tof_bin, st.geom, self.tof, req.n_sub)
         x = O.init_image(st.sens)
         acc = torch.zeros_like(st.sens)
-        st.table.set(slot, xs, xe, tb, x, acc, st.sens, req.n_sub, req.n_iter * req.n_sub, req.bg)
-        st.live[slot] = _Live(req, slot, (xs, xe, tb, acc), x, now, nbytes)
+        xf = tmp = None
+        if self.res_fwhm is not None:
+            xf, tmp = O.res_buffers(x, st.geom, self.res_fwhm)
+        st.table.set(slot, xs, xe, tb, x, acc, st.sens, req.n_sub, req.n_iter * req.n_sub, req.bg, xf, tmp)
+        st.live[slot] = _Live(req, slot, (xs, xe, tb, acc, xf, tmp), x, now, nbytes)
         st.dirty = True
         self.in_use += nbytes
         return True
@@ -129,10 +140,10 @@ class OsemServer:
             st.dirty = False
         if self.use_graph:
             if st.graph is None:
-                st.graph = O.capture_steps(st.table, st.geom, self.tof, self.steps)
+                st.graph = O.capture_steps(st.table, st.geom, self.tof, self.steps, self.res_fwhm)
             st.graph.replay()
         else:
-            O.osem_steps(st.table, st.geom, self.tof, self.steps)
+            O.osem_steps(st.table, st.geom, self.tof, self.steps, self.res_fwhm)
         st.table.advance_host(self.steps)
 
     def run(self, trace, clock=time.perf_counter):
@@ -169,11 +180,12 @@ class OsemServer:
         return results
 
 
-def run_sequential(trace, tof, sens_by_grid, presorted=True, clock=time.perf_counter):
+def run_sequential(trace, tof, sens_by_grid, presorted=True, clock=time.perf_counter, res_fwhm=None):
     """Baseline: the same trace, one frame at a time (FIFO), plain projector calls per subset
-    (pp_fwd_tof_lm, torch ratio, pp_back_tof_lm, torch image update).  presorted=True first puts
-    the frame's events in subset-major presorted order (pp_lm_presort + pp_gather_events);
-    presorted=False uses the events as given, each subset copied out of the strided view."""
+    (pp_fwd_tof_lm, torch ratio, pp_back_tof_lm, torch image update; with res_fwhm a pp_gauss3d
+    before the forward and after the back projection).  presorted=True first puts the frame's
+    events in subset-major presorted order (pp_lm_presort + pp_gather_events); presorted=False
+    uses the events as given, each subset copied out of the strided view."""
     tof = as_tof(tof)
     sens = {as_geom(g): s for g, s in sens_by_grid}
     results = []
@@ -203,11 +215,13 @@ def run_sequential(trace, tof, sens_by_grid, presorted=True, clock=time.perf_cou
         pos = sv > 0
         for _ in range(req.n_iter):
             for sx, se, sb in subsets:
-                ybar = fwd_tof_lm(sx, se, sb, g, tof, x) + req.bg
+                xf = x if res_fwhm is None else gauss3d(x, g, res_fwhm)
+                ybar = fwd_tof_lm(sx, se, sb, g, tof, xf) + req.bg
                 ratio = torch.where(ybar > 0, 1.0 / ybar, torch.zeros_like(ybar))
                 acc.zero_()
                 back_tof_lm(sx, se, sb, g, tof, ratio, img=acc)
-                x = torch.where(pos, x * acc / (sv / ns), torch.zeros_like(x))
+                ab = acc if res_fwhm is None else gauss3d(acc, g, res_fwhm)
+                x = torch.where(pos, x * ab / (sv / ns), torch.zeros_like(x))
         torch.cuda.current_stream().synchronize()
         results.append(OsemResult(req.rid, x, req.arrival, start, clock() - t0))
     return results
@@ -263,17 +277,19 @@ def bench_leg(args, log):
                                   n_tof_bins=t.n_bins, device=dev)
     lxs, lxe = C.SINO_CLIN.lors(device=dev, radial_chunk=25)
     grids = [pp.ImageGeom(g.dim, g.voxsize, g.origin) for g in C.SERVE_GRIDS]
-    sens = [(g, O.sensitivity(lxs, lxe, g)) for g in grids]
+    res = None if getattr(args, "no_res", False) else O.RES_FWHM_MM
+    sens = [(g, O.sensitivity(lxs, lxe, g, res_fwhm=res)) for g in grids]
     del lxs, lxe
     torch.cuda.empty_cache()
     n_req = int(getattr(args, "serve_requests", None) or C.N_REQUESTS)
-    server = OsemServer(T, sens, max_slots=SERVE_SLOTS, hbm_budget=32e9, steps_per_tick=1, use_graph=True)
+    server = OsemServer(T, sens, max_slots=SERVE_SLOTS, hbm_budget=32e9, steps_per_tick=1, use_graph=True,
+                        res_fwhm=res)
     server.run(make_trace(pool, grids, 4, C.SEED_SERVE + 2, (500_000, 600_000), 1e9))  # warm-up and capture
     # calibrate the sequential (presorted) service time on a burst from the same distribution
     cal = make_trace(pool, grids, 16, C.SEED_SERVE + 1, C.SERVE_EVENTS_RANGE, 1e9)
-    run_sequential(cal[:2], T, sens)
+    run_sequential(cal[:2], T, sens, res_fwhm=res)
     t0 = time.perf_counter()
-    run_sequential(cal, T, sens)
+    run_sequential(cal, T, sens, res_fwhm=res)
     service = (time.perf_counter() - t0) / len(cal)
     # overload: Poisson arrivals at 3x the sequential service rate, so frames/s measures capacity
     rate = 3.0 / service
@@ -282,12 +298,12 @@ def bench_leg(args, log):
     res_b = server.run(trace)
     sb = latency_stats(res_b, 0.0)
     log(f"serving batched: p50 {sb['p50_s']:.3f} s p99 {sb['p99_s']:.3f} s, {sb['frames_per_s']:.2f} frames/s")
-    res_s = run_sequential(trace, T, sens)
+    res_s = run_sequential(trace, T, sens, res_fwhm=res)
     ss = latency_stats(res_s, 0.0)
     log(f"serving sequential presorted: p50 {ss['p50_s']:.3f} s p99 {ss['p99_s']:.3f} s, "
         f"{ss['frames_per_s']:.2f} frames/s")
     n_u = min(n_req, 64)
-    res_u = run_sequential(trace[:n_u], T, sens, presorted=False)
+    res_u = run_sequential(trace[:n_u], T, sens, presorted=False, res_fwhm=res)
     su = latency_stats(res_u, 0.0)
     log(f"serving sequential as-given (first {n_u}): p50 {su['p50_s']:.3f} s p99 {su['p99_s']:.3f} s, "
         f"{su['frames_per_s']:.2f} frames/s")
@@ -296,7 +312,7 @@ def bench_leg(args, log):
     diffs = [float(torch.linalg.vector_norm(r.image - by_id[r.rid]) / torch.linalg.vector_norm(by_id[r.rid]))
              for r in res_b[:16]]
     return {"requests": n_req, "arrival_rate_hz": rate, "offered_load_vs_sequential": 3.0, "iterations": 3,
-            "subsets": 8, "batched": sb, "sequential_plain_presorted": ss,
+            "subsets": 8, "resolution_model_fwhm_mm": res, "batched": sb, "sequential_plain_presorted": ss,
             "sequential_plain_as_given": dict(su, note=f"first {n_u} requests of the same trace"),
             "batched_first_requests": sb_u,
             "speedup_frames_per_s_vs_plain_presorted": sb["frames_per_s"] / ss["frames_per_s"],

@@ -29,7 +29,7 @@ def test_exports_every_declared_symbol(lib):
     assert len(names) >= 12, names
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.pp_abi_version() == 1
+    assert lib.pp_abi_version() == 2
 
 
 def _geom(dim=(4, 4, 4), vs=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0)):
@@ -45,10 +45,13 @@ def _tof(bw=1.0, sig=1.0, ns=3.0, nb=5):
 
 
 DUMMY = ctypes.c_void_p(16)  # never dereferenced: validation fails before any launch
+DUMMY2 = ctypes.c_void_p(1 << 20)
+DUMMY3 = ctypes.c_void_p(1 << 21)
 
 
 def test_error_codes(lib):
-    from paper_2212_12519_amd._lib import PP_EINVAL_GEOM, PP_EINVAL_N, PP_EINVAL_PTR, PP_EINVAL_TOF, PP_OK
+    from paper_2212_12519_amd._lib import (PP_EINVAL_GEOM, PP_EINVAL_N, PP_EINVAL_PTR, PP_EINVAL_RES, PP_EINVAL_TOF,
+                                           PP_OK)
 
     g = _geom()
     assert lib.pp_fwd(None, None, 0, g, None, None, None, None) == PP_OK  # n == 0: no-op
@@ -67,8 +70,24 @@ def test_error_codes(lib):
     assert lib.pp_fwd_tof_lm(DUMMY, DUMMY, DUMMY, 5, g, None, DUMMY, DUMMY, None, None) == PP_EINVAL_PTR
     assert lib.pp_lm_osem_accumulate(DUMMY, -1, g, _tof(), None) == PP_EINVAL_N
     assert lib.pp_lm_osem_accumulate(DUMMY, 0, g, _tof(), None) == PP_OK
-    assert lib.pp_lm_osem_update(DUMMY, 3, 0, None) == PP_EINVAL_N
-    assert lib.pp_lm_osem_update(None, 3, 64, None) == PP_EINVAL_PTR
+    assert lib.pp_lm_osem_update(DUMMY, -1, g, None, None) == PP_EINVAL_N
+    assert lib.pp_lm_osem_update(None, 3, g, None, None) == PP_EINVAL_PTR
+    assert lib.pp_lm_osem_update(DUMMY, 3, None, None, None) == PP_EINVAL_PTR
+    assert lib.pp_lm_osem_update(DUMMY, 3, _geom(dim=(0, 4, 4)), None, None) == PP_EINVAL_GEOM
+    f3 = ctypes.c_float * 3
+    for bad in (f3(-1.0, 4.5, 4.5), f3(float("nan"), 4.5, 4.5), f3(4.5, float("inf"), 4.5), f3(4.5, 4.5, 1e4)):
+        assert lib.pp_lm_osem_update(DUMMY, 3, g, bad, None) == PP_EINVAL_RES
+        assert lib.pp_gauss3d(DUMMY, DUMMY2, DUMMY3, g, bad, None) == PP_EINVAL_RES
+    # resolution model: pointers, aliasing, widths at the radius limit (31 voxels)
+    ok = f3(4.5, 4.5, 4.5)
+    assert lib.pp_gauss3d(None, DUMMY2, DUMMY3, g, ok, None) == PP_EINVAL_PTR
+    assert lib.pp_gauss3d(DUMMY, DUMMY2, DUMMY3, g, None, None) == PP_EINVAL_PTR
+    assert lib.pp_gauss3d(DUMMY, DUMMY, DUMMY3, g, ok, None) == PP_EINVAL_PTR  # dst aliases src
+    assert lib.pp_gauss3d(DUMMY, DUMMY2, ctypes.c_void_p((1 << 20) + 4), g, ok, None) == PP_EINVAL_PTR  # tmp overlaps dst
+    sig_max = 31.49 / 4.0  # radius floor(4 s + 1/2) = 31 voxels at 1 mm
+    assert lib.pp_gauss3d(DUMMY, DUMMY2, DUMMY3, _geom(dim=(0, 4, 4)), ok, None) == PP_EINVAL_GEOM
+    assert lib.pp_lm_osem_update(DUMMY, 0, g, f3(*(3 * [sig_max * 2.3548])), None) == PP_OK
+    assert lib.pp_lm_osem_update(DUMMY, 0, g, f3(*(3 * [32.0 / 4.0 * 2.3549])), None) == PP_EINVAL_RES
     assert lib.pp_fill(None, 10, ctypes.c_float(0.0), None) == PP_EINVAL_PTR
     assert lib.pp_fill(None, -1, ctypes.c_float(0.0), None) == PP_EINVAL_N
     ws = lib.pp_lm_presort_workspace_bytes(1000)
