@@ -54,6 +54,7 @@ int make_tof(const pp_tof_t* ti, TofK& t) {
     t.bw = bw;
     t.c0 = -0.5 * (double)(ti->n_bins - 1) * bw + (double)ti->center_offset;
     t.trunc = (float)(ns * sig);
+    t.hbw = (float)(0.5 * bw);
     t.win = ns * sig + 0.5 * bw;
     t.inv_sqrt2_sig = (float)(1.0 / (std::sqrt(2.0) * sig));
     t.nb = ti->n_bins;

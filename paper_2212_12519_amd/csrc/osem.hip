@@ -43,19 +43,18 @@ __host__ __device__ inline int64_t slot_chunks(int64_t n_events, int32_t n_sub) 
 // Per event: forward project through the frame's current image (setup), then scatter
 // ell / ybar times the TOF weight (sample) -- the run/sheet back projection of sheet.hpp.
 struct ModeOsem {
+    static constexpr bool kColAtomic = true;
     const float* __restrict__ x;
     const int16_t* __restrict__ bins;
     float bg;
     TofK t;
-    __device__ bool setup(int64_t l, const float* xs, const float* xe, const GeomK& g, RayK& r, double& cen,
-                          float& cv) const {
+    __device__ bool setup(int64_t l, const float* xs, const float* xe, const GeomK& g, RayK& r, float& cv) const {
         const int b = bins[l];
-        cen = t.c0 + b * t.bw;
         if (b < 0 || b >= t.nb || !ray_setup(xs + 3 * l, xe + 3 * l, g, r)) return false;
-        if (!tof_window(r, cen, t.win)) return false;
+        if (!tof_window_rel(r, t.c0 + b * t.bw, t.win)) return false;
         float fwd = 0.0f;
         for (int k = r.k_lo; k <= r.k_hi; ++k) {
-            const float w = tof_weight(fma((double)k, r.ds, r.s0), cen, t);
+            const float w = tof_weight(fma((double)k, r.ds, r.s0), t);
             fwd += w * stencil_gather(x, r, stencil_at(r, k));
         }
         const float ybar = r.ell * fwd + bg;
@@ -63,7 +62,7 @@ struct ModeOsem {
         cv = r.ell / ybar;
         return true;
     }
-    __device__ float sample(double s, double cen, float cv) const { return tof_weight(s, cen, t) * cv; }
+    __device__ float sample(double x, float cv) const { return tof_weight(x, t) * cv; }
 };
 
 __global__ void __launch_bounds__(kSheetBlock) k_osem_accumulate(const pp_osem_slot_t* __restrict__ slots,

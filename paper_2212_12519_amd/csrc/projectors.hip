@@ -50,10 +50,9 @@ __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(const float* __restrict__
     float acc = 0.0f;
     RayK r;
     if (b >= 0 && b < t.nb && ray_setup(xs + 3 * l, xe + 3 * l, g, r)) {
-        const double c = t.c0 + b * t.bw;
-        if (tof_window(r, c, t.win)) {
+        if (tof_window_rel(r, t.c0 + b * t.bw, t.win)) {
             for (int k = r.k_lo; k <= r.k_hi; ++k) {
-                const float w = tof_weight(fma((double)k, r.ds, r.s0), c, t);
+                const float w = tof_weight(fma((double)k, r.ds, r.s0), t);
                 acc += w * stencil_gather(img, r, stencil_at(r, k));
             }
             acc *= r.ell;

@@ -31,48 +31,48 @@ constexpr int kSheetBlock = 256;
 constexpr int kRunMin = 8;
 constexpr int kSheetMaxW = 128;  // largest axis-2 size with an LDS sheet
 constexpr int kSheetGroups = 8;  // groups of 256 rays per workgroup (a sheet persists across them)
+constexpr int kSheetUnroll = 1;  // rays evaluated together in the sheet loop
 
 // LDS layout of k_back_runs (bytes): per-ray arrays, then the column buffer.
 struct SheetLayout {
-    static constexpr int kDoubles = 7;  // W0 dW s0 ds cen U0 dU
-    static constexpr int kInts = 9;     // lo hi pax start cnt klo khi list(+count) value
-    static size_t ray_bytes() { return (size_t)kSheetBlock * (kDoubles * 8 + kInts * 4) + 32; }
+    static constexpr int kDoubles = 6;  // W0 dW s0 ds U0 dU
+    static constexpr int kWords = 6;    // cv, lohi, pax, start, cnt, list; plus 16 words of masks/counts
+    static size_t ray_bytes() { return (size_t)kSheetBlock * (kDoubles * 8 + kWords * 4) + 16 * 4; }
     static size_t col_floats(int nw) { return (size_t)nw * (kSheetBlock + 1); }
     static size_t bytes(int nw) { return ray_bytes() + col_floats(nw) * 4; }
 };
 
 // Per-ray value hooks:
-//   setup(l, r, cen, cv): prepare ray l (false = no contribution); cen = TOF bin centre (or 0),
-//                          cv = ell * p (the constant factor of every sample)
-//   sample(k, r-params): the value scattered at plane k
+//   setup(l, r, cv): prepare ray l (false = no contribution); cv = ell * p (the constant
+//                    factor of every sample); for TOF, r.s0 is made relative to the bin centre
+//   sample(x, cv):   the value scattered at the plane sample with TOF coordinate
+//                    x = fma(k, r.ds, r.s0)
 struct ModeNonTof {
+    static constexpr bool kColAtomic = false;
     const float* __restrict__ p;
-    __device__ bool setup(int64_t l, const float* xs, const float* xe, const GeomK& g, RayK& r, double& cen,
-                          float& cv) const {
+    __device__ bool setup(int64_t l, const float* xs, const float* xe, const GeomK& g, RayK& r, float& cv) const {
         const float pl = p[l];
-        cen = 0.0;
         if (pl == 0.0f || !ray_setup(xs + 3 * l, xe + 3 * l, g, r)) return false;
         cv = r.ell * pl;
         return true;
     }
-    __device__ float sample(double /*s*/, double /*cen*/, float cv) const { return cv; }
+    __device__ float sample(double /*x*/, float cv) const { return cv; }
 };
 
 struct ModeTofLm {
+    static constexpr bool kColAtomic = true;
     const float* __restrict__ p;
     const int16_t* __restrict__ bins;
     TofK t;
-    __device__ bool setup(int64_t l, const float* xs, const float* xe, const GeomK& g, RayK& r, double& cen,
-                          float& cv) const {
+    __device__ bool setup(int64_t l, const float* xs, const float* xe, const GeomK& g, RayK& r, float& cv) const {
         const int b = bins[l];
         const float pl = p[l];
-        cen = t.c0 + b * t.bw;
         if (b < 0 || b >= t.nb || pl == 0.0f || !ray_setup(xs + 3 * l, xe + 3 * l, g, r)) return false;
-        if (!tof_window(r, cen, t.win)) return false;
+        if (!tof_window_rel(r, t.c0 + b * t.bw, t.win)) return false;
         cv = r.ell * pl;
         return true;
     }
-    __device__ float sample(double s, double cen, float cv) const { return tof_weight(s, cen, t) * cv; }
+    __device__ float sample(double x, float cv) const { return tof_weight(x, t) * cv; }
 };
 
 // Broadcast lane `src` (wave-uniform) of a double to the whole wave through scalar registers.
@@ -83,51 +83,26 @@ __device__ __forceinline__ double bcast(double v, int src) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// col[j][k] += a, col[j + 1][k] += b for the in-range entries (thread-private column k)
+// col[j][k] += a, col[j + 1][k] += b for the in-range entries (thread-private column k).
+// Atomic: LDS adds without return (no wait for the old value; pays where z changes
+// seldom along the processing order, listmode); else a read-modify-write (cheaper where z
+// changes at almost every ray, radial-view-plane sinograms).
+template <bool Atomic>
 __device__ __forceinline__ void col_add(float* col, int j, int k, float a, float b, int nw) {
     constexpr int B = kSheetBlock;
-    if ((unsigned)j < (unsigned)nw && a != 0.0f) col[j * (B + 1) + k] += a;
-    if ((unsigned)(j + 1) < (unsigned)nw && b != 0.0f) col[(j + 1) * (B + 1) + k] += b;
-}
-
-// TOF sinogram: the sample value is ell * sum over the bins of the TOF window of w_b(s) p[l][b]
-// (neighbouring bins share their erf edge).  The ray index rides in the `cen` slot (exact in a
-// double for any ray count below 2^53); cv = ell.
-__device__ __forceinline__ void tof_bin_range(double s, const TofK& t, int& b_lo, int& b_hi) {
-    const double lo = floor((s - t.win - t.c0) / t.bw);
-    const double hi = ceil((s + t.win - t.c0) / t.bw);
-    b_lo = (int)fmax(lo, 0.0);
-    b_hi = (int)fmin(hi, (double)(t.nb - 1));
-}
-
-struct ModeTofSino {
-    const float* __restrict__ p;
-    TofK t;
-    __device__ bool setup(int64_t l, const float* xs, const float* xe, const GeomK& g, RayK& r, double& cen,
-                          float& cv) const {
-        cen = (double)l;
-        const float* pr = p + l * t.nb;
-        bool any = false;
-        for (int b = 0; b < t.nb; ++b) any |= (pr[b] != 0.0f);
-        if (!any || !ray_setup(xs + 3 * l, xe + 3 * l, g, r)) return false;
-        cv = r.ell;
-        return true;
+    if ((unsigned)j < (unsigned)nw && a != 0.0f) {
+        if (Atomic)
+            __hip_atomic_fetch_add(col + j * (B + 1) + k, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        else
+            col[j * (B + 1) + k] += a;
     }
-    __device__ float sample(double s, double cen, float cv) const {
-        const float* pr = p + (int64_t)cen * t.nb;
-        int b_lo, b_hi;
-        tof_bin_range(s, t, b_lo, b_hi);
-        const double x_hi0 = s - (t.c0 + b_lo * t.bw) + 0.5 * t.bw;
-        float g_hi = tof_cdf(x_hi0, t);
-        float c = 0.0f;
-        for (int b = b_lo; b <= b_hi; ++b) {
-            const float g_lo = tof_cdf(x_hi0 - (double)(b - b_lo + 1) * t.bw, t);
-            c += (g_hi - g_lo) * pr[b];
-            g_hi = g_lo;
-        }
-        return c * cv;
+    if ((unsigned)(j + 1) < (unsigned)nw && b != 0.0f) {
+        if (Atomic)
+            __hip_atomic_fetch_add(col + (j + 1) * (B + 1) + k, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        else
+            col[(j + 1) * (B + 1) + k] += b;
     }
-};
+}
 
 // Flush the sheet (planes kmin..kmax of line (p, U0, dU)) with contiguous atomics and clear it.
 __device__ __forceinline__ void sheet_flush(float* __restrict__ img, float* col, const GeomK& g, int p, double U0,
@@ -170,18 +145,15 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
     double* dW = W0 + B;
     double* s0 = dW + B;
     double* ds = s0 + B;
-    double* cen = ds + B;
-    double* U0 = cen + B;
+    double* U0 = ds + B;
     double* dU = U0 + B;
     float* cvs = reinterpret_cast<float*>(dU + B);
-    int* lo = reinterpret_cast<int*>(cvs + B);
-    int* hi = lo + B;
-    int* pax = hi + B;
+    int* lohi = reinterpret_cast<int*>(cvs + B);  // k_lo | k_hi << 16 (sheet rays: planes < 256)
+    int* pax = lohi + B;
     int* start = pax + B;
     int* cnt = start + B;
-    int* klo = cnt + B;
-    int* khi = klo + B;
-    int* list = khi + B;  // sheet-run heads; count at list[B]; per-wave counts at list[B + 4 ..]
+    int* masks = cnt + B;  // 8 words: run-boundary ballots of the 4 waves
+    int* list = masks + 8;  // sheet-run heads; count at list[B]; per-wave counts at list[B + 4 ..]
     float* col = reinterpret_cast<float*>(list + B + 8);  // [nw][B + 1]
 
     const int tid = threadIdx.x;
@@ -204,9 +176,8 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
             if (l < 0 || l >= n) l = -1;
         }
         RayK r;
-        double c = 0.0;
         float cv = 0.0f;
-        const bool ok = l >= 0 && m.setup(l, xs, xe, g, r, c, cv);
+        const bool ok = l >= 0 && m.setup(l, xs, xe, g, r, cv);
         // compact the valid rays to the front of the group (stable order), so that rays
         // without a contribution do not break runs
         const unsigned long long vb = __ballot(ok);
@@ -225,12 +196,10 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
             dW[cp] = r.dW;
             s0[cp] = r.s0;
             ds[cp] = r.ds;
-            cen[cp] = c;
             U0[cp] = r.U0;
             dU[cp] = r.dU;
             cvs[cp] = cv;
-            lo[cp] = r.k_lo;
-            hi[cp] = r.k_hi;
+            lohi[cp] = (r.k_lo & 0xffff) | (r.k_hi << 16);
             pax[cp] = r.p;
         }
         __syncthreads();
@@ -250,8 +219,8 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
         const unsigned long long bmask = __ballot(bnd);
         if (lane == 63) start[wave] = st;
         if (lane == 0) {
-            klo[2 * wave] = (int)(bmask & 0xffffffffull);
-            klo[2 * wave + 1] = (int)(bmask >> 32);
+            masks[2 * wave] = (int)(bmask & 0xffffffffull);
+            masks[2 * wave + 1] = (int)(bmask >> 32);
         }
         __syncthreads();
         int carry = -1;
@@ -268,7 +237,7 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
                     break;
                 }
                 if (++w >= B / 64) break;
-                mk = ((unsigned long long)(unsigned)klo[2 * w + 1] << 32) | (unsigned)klo[2 * w];
+                mk = ((unsigned long long)(unsigned)masks[2 * w + 1] << 32) | (unsigned)masks[2 * w];
             }
             len = nxt - tid;
         }
@@ -311,7 +280,7 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
                 float v = 0.0f;
                 if (act) {
                     stn = stencil_at(r, k);
-                    v = m.sample(fma((double)k, r.ds, r.s0), c, cv);
+                    v = m.sample(fma((double)k, r.ds, r.s0), cv);
                 }
                 wave_stencil_scatter(img, act && v != 0.0f, r, stn, v);
             }
@@ -346,16 +315,17 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
             for (int b0 = h; b0 < h + len; b0 += 64) {
                 const int nb = min(64, h + len - b0);
                 const int q = b0 + min(lane, nb - 1);
-                const double qW0 = W0[q], qdW = dW[q], qs0 = s0[q], qds = ds[q], qcen = cen[q];
+                const double qW0 = W0[q], qdW = dW[q], qs0 = s0[q], qds = ds[q];
                 const int qcv = __float_as_int(cvs[q]);
-                const int qlo = lo[q], qhi = hi[q];
+                const int qlh = lohi[q];
                 // rays whose plane window meets this wave's 64 planes (wave-uniform bit mask)
                 const int kw0 = wave * 64, kw1 = min(kw0 + 63, sh_kmax);
-                unsigned long long todo = __ballot(lane < nb && qlo <= kw1 && qhi >= kw0);
+                unsigned long long todo =
+                    __ballot(lane < nb && (qlh & 0xffff) <= kw1 && (qlh >> 16) >= kw0);
                 while (todo) {
-                    int ru[4], nu_ = 0;
+                    int ru[kSheetUnroll], nu_ = 0;
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
+                    for (int u = 0; u < kSheetUnroll; ++u) {
                         if (todo) {
                             ru[u] = __ffsll((long long)todo) - 1;
                             todo &= todo - 1ull;
@@ -364,38 +334,49 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
                             ru[u] = ru[0];
                         }
                     }
-                    int j0v[4];
-                    float fwv[4], vv[4];
+                    // evaluate all rays of the batch first (straight-line code, no branches)
+                    int j0v[kSheetUnroll];
+                    float fwv[kSheetUnroll], vv[kSheetUnroll];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int rlo = __builtin_amdgcn_readlane(qlo, ru[u]);
-                        const int rhi = __builtin_amdgcn_readlane(qhi, ru[u]);
-                        const bool act = kin && u < nu_ && k >= rlo && k <= rhi;
+                    for (int u = 0; u < kSheetUnroll; ++u) {
+                        const int rlh = __builtin_amdgcn_readlane(qlh, ru[u]);
+                        const bool act = kin && u < nu_ && k >= (rlh & 0xffff) && k <= (rlh >> 16);
                         const double W = fma((double)k, bcast(qdW, ru[u]), bcast(qW0, ru[u]));
                         const double fj = floor(W);
                         j0v[u] = (int)fj;
                         fwv[u] = (float)(W - fj);
                         const float v = m.sample(fma((double)k, bcast(qds, ru[u]), bcast(qs0, ru[u])),
-                                                 bcast(qcen, ru[u]),
                                                  __int_as_float(__builtin_amdgcn_readlane(qcv, ru[u])));
                         vv[u] = act ? v : 0.0f;
                     }
+                    // then accumulate: the pair of z entries stays in registers until z changes.
+                    // The common case (no contributing ray of the batch leaves entry jc) is tested
+                    // on all rays at once, so the evaluations above stay in one basic block.
+                    bool same = true;
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        if (vv[u] != 0.0f) {
-                            if (j0v[u] != jc) {
-                                col_add(col, jc, k, accA, accB, nw);
+                    for (int u = 0; u < kSheetUnroll; ++u) same &= (vv[u] == 0.0f) | (j0v[u] == jc);
+                    if (same) {
+#pragma unroll
+                        for (int u = 0; u < kSheetUnroll; ++u) {
+                            accA = fmaf(1.0f - fwv[u], vv[u], accA);
+                            accB = fmaf(fwv[u], vv[u], accB);
+                        }
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < kSheetUnroll; ++u) {
+                            if (vv[u] != 0.0f && j0v[u] != jc) {
+                                col_add<Mode::kColAtomic>(col, jc, k, accA, accB, nw);
                                 jc = j0v[u];
                                 accA = 0.0f;
                                 accB = 0.0f;
                             }
-                            accA += (1.0f - fwv[u]) * vv[u];
-                            accB += fwv[u] * vv[u];
+                            accA = fmaf(1.0f - fwv[u], vv[u], accA);
+                            accB = fmaf(fwv[u], vv[u], accB);
                         }
                     }
                 }
             }
-            col_add(col, jc, k, accA, accB, nw);
+            col_add<Mode::kColAtomic>(col, jc, k, accA, accB, nw);
             __syncthreads();
         }
     }
