@@ -256,7 +256,7 @@ int pp_lm_osem_accumulate(const pp_osem_slot_t* d_slots, int32_t n_slots, const 
     if (n_slots < 0 || n_slots > (1 << 20)) return PP_EINVAL_N;
     if (n_slots == 0) return PP_OK;
     if (!d_slots) return PP_EINVAL_PTR;
-    return hip_status(launch_osem_accumulate(d_slots, n_slots, g, t, device_cus() * 2, as_stream(stream)));
+    return hip_status(launch_osem_accumulate(d_slots, n_slots, g, t, device_cus(), as_stream(stream)));
 }
 
 int pp_lm_osem_update(pp_osem_slot_t* d_slots, int32_t n_slots, const pp_image_t* geom, const float* res_fwhm,

@@ -34,8 +34,8 @@ hipError_t launch_count(const float* xs, const float* xe, const int16_t* bins, i
                         const TofK& t, int32_t* counts, hipStream_t s);
 
 int64_t osem_chunks(int64_t n_events, int32_t n_sub);
-hipError_t launch_osem_accumulate(const pp_osem_slot_t* slots, int n_slots, const GeomK& g, const TofK& t,
-                                  int n_blocks, hipStream_t s);
+hipError_t launch_osem_accumulate(const pp_osem_slot_t* slots, int n_slots, const GeomK& g, const TofK& t, int cus,
+                                  hipStream_t s);
 hipError_t launch_osem_update(pp_osem_slot_t* slots, int n_slots, int64_t n_vox, int n_blocks, hipStream_t s);
 hipError_t launch_osem_advance(pp_osem_slot_t* slots, int n_slots, hipStream_t s);
 hipError_t launch_fill(float* dst, int64_t n, float value, hipStream_t s);

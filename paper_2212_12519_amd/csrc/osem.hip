@@ -129,14 +129,19 @@ __global__ void k_fill(float* __restrict__ dst, int64_t n, float value) {
 
 int64_t osem_chunks(int64_t n_events, int32_t n_sub) { return slot_chunks(n_events, n_sub); }
 
-hipError_t launch_osem_accumulate(const pp_osem_slot_t* slots, int n_slots, const GeomK& g, const TofK& t,
-                                  int n_blocks, hipStream_t s) {
+hipError_t launch_osem_accumulate(const pp_osem_slot_t* slots, int n_slots, const GeomK& g, const TofK& t, int cus,
+                                  hipStream_t s) {
     const int nw = (g.n[2] <= kSheetMaxW) ? g.n[2] : 0;
-    const size_t lds = SheetLayout::bytes(nw);
+    const size_t lds = SheetLayout::bytes(nw, g);
     hipError_t e = hipFuncSetAttribute((const void*)k_osem_accumulate, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_osem_accumulate, dim3(n_blocks), dim3(kSheetBlock), lds, s, slots, n_slots, g, t, nw);
+    // persistent grid: as many workgroups as can be resident at once (LDS-limited)
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_osem_accumulate, kSheetBlock, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    hipLaunchKernelGGL(k_osem_accumulate, dim3(cus * per_cu), dim3(kSheetBlock), lds, s, slots, n_slots, g, t, nw);
     return hipGetLastError();
 }
 

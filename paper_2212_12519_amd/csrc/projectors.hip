@@ -201,11 +201,17 @@ template <class Mode>
 static hipError_t launch_runs(const Mode& m, const float* xs, const float* xe, int64_t n, const GeomK& g, float* img,
                               const int32_t* order, hipStream_t s) {
     const int nw = (g.n[2] <= kSheetMaxW) ? g.n[2] : 0;
-    const size_t lds = SheetLayout::bytes(nw);
+    const size_t lds = SheetLayout::bytes(nw, g);
     hipError_t e = hipFuncSetAttribute((const void*)k_back_runs<Mode>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
-    const int64_t groups = kSheetGroups;
+    // enough workgroups for about 4 per CU (small subsets), at most kSheetGroups groups each
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                 hipSuccess || cus <= 0)
+        cus = 256;
+    int64_t groups = (n + (int64_t)kSheetBlock * 4 * cus - 1) / ((int64_t)kSheetBlock * 4 * cus);
+    groups = groups < 1 ? 1 : (groups > kSheetGroups ? kSheetGroups : groups);
     hipLaunchKernelGGL(k_back_runs<Mode>, dim3(grid_for(n, kSheetBlock * groups)), dim3(kSheetBlock), lds, s, m, xs,
                        xe, n, g, img, order, nw, (int)groups);
     return hipGetLastError();

@@ -38,8 +38,14 @@ struct SheetLayout {
     static constexpr int kDoubles = 6;  // W0 dW s0 ds U0 dU
     static constexpr int kWords = 6;    // cv, lohi, pax, start, cnt, list; plus 16 words of masks/counts
     static size_t ray_bytes() { return (size_t)kSheetBlock * (kDoubles * 8 + kWords * 4) + 16 * 4; }
-    static size_t col_floats(int nw) { return (size_t)nw * (kSheetBlock + 1); }
-    static size_t bytes(int nw) { return ray_bytes() + col_floats(nw) * 4; }
+    // column stride: the longest line a sheet can hold (planes along axis 0 or 1, at most one
+    // per thread) + 1; sized to the grid so that two workgroups share a CU's LDS on the
+    // clinical grid (215 planes, 71 z entries: 79.8 KB)
+    __host__ __device__ static int col_stride(const GeomK& g) {
+        const int np = g.n[0] > g.n[1] ? g.n[0] : g.n[1];
+        return (np < kSheetBlock ? np : kSheetBlock) + 1;
+    }
+    static size_t bytes(int nw, const GeomK& g) { return ray_bytes() + (size_t)nw * col_stride(g) * 4; }
 };
 
 // Per-ray value hooks:
@@ -88,25 +94,24 @@ __device__ __forceinline__ double bcast(double v, int src) {
 // seldom along the processing order, listmode); else a read-modify-write (cheaper where z
 // changes at almost every ray, radial-view-plane sinograms).
 template <bool Atomic>
-__device__ __forceinline__ void col_add(float* col, int j, int k, float a, float b, int nw) {
-    constexpr int B = kSheetBlock;
+__device__ __forceinline__ void col_add(float* col, int j, int k, float a, float b, int nw, int cs) {
     if ((unsigned)j < (unsigned)nw && a != 0.0f) {
         if (Atomic)
-            __hip_atomic_fetch_add(col + j * (B + 1) + k, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(col + j * cs + k, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         else
-            col[j * (B + 1) + k] += a;
+            col[j * cs + k] += a;
     }
     if ((unsigned)(j + 1) < (unsigned)nw && b != 0.0f) {
         if (Atomic)
-            __hip_atomic_fetch_add(col + (j + 1) * (B + 1) + k, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(col + (j + 1) * cs + k, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         else
-            col[(j + 1) * (B + 1) + k] += b;
+            col[(j + 1) * cs + k] += b;
     }
 }
 
 // Flush the sheet (planes kmin..kmax of line (p, U0, dU)) with contiguous atomics and clear it.
 __device__ __forceinline__ void sheet_flush(float* __restrict__ img, float* col, const GeomK& g, int p, double U0,
-                                            double dU, int kmin, int kmax, int nw) {
+                                            double dU, int kmin, int kmax, int nw, int cs) {
     constexpr int B = kSheetBlock;
     const int lane = (int)__lane_id();
     const int wave = threadIdx.x >> 6;
@@ -121,7 +126,7 @@ __device__ __forceinline__ void sheet_flush(float* __restrict__ img, float* col,
         const bool ok0 = (unsigned)i0 < (unsigned)nu, ok1 = (unsigned)(i0 + 1) < (unsigned)nu;
         const int base = k * sp + i0 * su;
         for (int j = lane; j < nw; j += 64) {
-            float* cp = col + j * (B + 1) + k;
+            float* cp = col + j * cs + k;
             const float v = *cp;
             if (v != 0.0f) {
                 *cp = 0.0f;
@@ -154,7 +159,8 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
     int* cnt = start + B;
     int* masks = cnt + B;  // 8 words: run-boundary ballots of the 4 waves
     int* list = masks + 8;  // sheet-run heads; count at list[B]; per-wave counts at list[B + 4 ..]
-    float* col = reinterpret_cast<float*>(list + B + 8);  // [nw][B + 1]
+    float* col = reinterpret_cast<float*>(list + B + 8);  // [nw][cs]
+    const int cs = SheetLayout::col_stride(g);
 
     const int tid = threadIdx.x;
     const int lane = (int)__lane_id();
@@ -162,7 +168,7 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
     const int nw = g.n[2];
     const bool sheets = nw_lds > 0 && nw <= nw_lds;
     if (sheets)
-        for (int q = tid; q < nw * (B + 1); q += B) col[q] = 0.0f;
+        for (int q = tid; q < nw * cs; q += B) col[q] = 0.0f;
     // current sheet (block-uniform copies in registers, updated after barriers)
     bool sh_on = false;
     int sh_p = -1, sh_kmin = 0, sh_kmax = -1;
@@ -291,7 +297,7 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
             const int h = list[li];
             const bool same_line = sh_on && pax[h] == sh_p && U0[h] == sh_U0 && dU[h] == sh_dU;
             if (sh_on && !same_line) {
-                sheet_flush(img, col, g, sh_p, sh_U0, sh_dU, sh_kmin, sh_kmax, nw);
+                sheet_flush(img, col, g, sh_p, sh_U0, sh_dU, sh_kmin, sh_kmax, nw, cs);
                 __syncthreads();
                 sh_on = false;
             }
@@ -365,7 +371,7 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
 #pragma unroll
                         for (int u = 0; u < kSheetUnroll; ++u) {
                             if (vv[u] != 0.0f && j0v[u] != jc) {
-                                col_add<Mode::kColAtomic>(col, jc, k, accA, accB, nw);
+                                col_add<Mode::kColAtomic>(col, jc, k, accA, accB, nw, cs);
                                 jc = j0v[u];
                                 accA = 0.0f;
                                 accB = 0.0f;
@@ -376,11 +382,11 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
                     }
                 }
             }
-            col_add<Mode::kColAtomic>(col, jc, k, accA, accB, nw);
+            col_add<Mode::kColAtomic>(col, jc, k, accA, accB, nw, cs);
             __syncthreads();
         }
     }
-    if (sh_on) sheet_flush(img, col, g, sh_p, sh_U0, sh_dU, sh_kmin, sh_kmax, nw);
+    if (sh_on) sheet_flush(img, col, g, sh_p, sh_U0, sh_dU, sh_kmin, sh_kmax, nw, cs);
     __syncthreads();  // the LDS may be reused by the caller
 }
 
