@@ -121,7 +121,7 @@ def parse():
     ap.add_argument("--no-sino", action="store_true", help="skip the sinogram legs")
     ap.add_argument("--no-serve", action="store_true", help="skip the OSEM serving leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=25.0, help="calibrated oracle time for the CPU baseline")
     ap.add_argument("--only", default=None, help="profiling helper: lm | sino | serve")
     ap.add_argument("--serve-requests", type=int, default=None, help="requests in the serving leg (default 256)")
     ap.add_argument("--no-res", action="store_true", help="serving leg without the resolution model")
