@@ -47,7 +47,7 @@ def _load():
     F = ctypes.c_float
     I32 = ctypes.c_int32
     geo = [P, P, I64, P, P, P]
-    tof = [F, F, F, F, I32]
+    tof = [F, F, F, F, I32, P, I32, ctypes.c_double, ctypes.c_double]
     lib.orc_fwd.argtypes = geo + [P, P]
     lib.orc_back.argtypes = geo + [P, P]
     lib.orc_fwd_tof_sino.argtypes = geo + tof + [P, P]
@@ -82,10 +82,30 @@ def _ptr(a):
 
 
 def _tofargs(tof):
-    """tof: object/dict with bin_width, sigma, n_sigmas, n_bins, (center_offset)."""
+    """tof: object/dict with bin_width, sigma, n_sigmas, n_bins, (center_offset) and, for a
+    tabulated kernel, lut (float32 array of the bin weight at lut_x0 + i * lut_dx), lut_x0, lut_dx.
+    The returned tuple keeps the table array alive for the call."""
     g = (lambda k, d=None: tof.get(k, d)) if isinstance(tof, dict) else (lambda k, d=None: getattr(tof, k, d))
-    return (ctypes.c_float(g("bin_width")), ctypes.c_float(g("sigma")), ctypes.c_float(g("n_sigmas")),
-            ctypes.c_float(g("center_offset", 0.0)), ctypes.c_int32(int(g("n_bins"))))
+    lut = g("lut")
+    if lut is not None:
+        lut = np.ascontiguousarray(np.asarray(lut, dtype=np.float32).ravel())
+        if lut.size < 2 or not float(g("lut_dx")) > 0:
+            raise ValueError("lut needs >= 2 entries and lut_dx > 0")
+        lp, ln, x0, dx = _ptr(lut), lut.size, float(g("lut_x0")), float(g("lut_dx"))
+    else:
+        lp, ln, x0, dx = None, 0, 0.0, 1.0
+    return _TofArgs((ctypes.c_float(g("bin_width")), ctypes.c_float(g("sigma")), ctypes.c_float(g("n_sigmas")),
+                     ctypes.c_float(g("center_offset", 0.0)), ctypes.c_int32(int(g("n_bins"))), lp,
+                     ctypes.c_int32(ln), ctypes.c_double(x0), ctypes.c_double(dx)), lut)
+
+
+class _TofArgs(tuple):
+    """The C arguments of a TOF kernel; holds a reference to the table array."""
+
+    def __new__(cls, args, keep):
+        t = super().__new__(cls, args)
+        t._keep = keep
+        return t
 
 
 def max_threads() -> int:

@@ -36,6 +36,11 @@
  *       w_t(s) = G(s - c_t + bw/2) - G(s - c_t - bw/2),
  *       G(x)   = erf(clip(x, -n_sigmas*sigma, n_sigmas*sigma) / (sqrt(2) sigma)) / 2,
  *     not renormalised;
+ *   - the alternative kernel of Sec. 4 (a tabulated, possibly non-Gaussian,
+ *     TOF kernel): a table of the bin weight w(x) as a function of the
+ *     signed distance x of the sample from the bin centre, at
+ *     x_i = x0 + i dx (i = 0 .. n-1), linearly interpolated, 0 outside
+ *     [x0, x_{n-1}]; sigma and n_sigmas are then unused;
  *   - listmode bins outside [0, n_bins) and non-finite or zero-length LORs
  *     contribute nothing;
  *   - listmode OSEM: subset j holds the events with index e mod n_sub == j;
@@ -66,6 +71,9 @@ typedef struct {
     double trunc;  /* n_sigmas * sigma, mm */
     double off;    /* centre offset, mm */
     int nb;        /* number of bins */
+    const float* lut; /* tabulated bin weight w(x_i), or NULL (Gaussian) */
+    int64_t lut_n;
+    double lut_x0, lut_dx;
 } tof64;
 
 typedef struct {
@@ -87,15 +95,22 @@ static grid64 mkgrid(const float* origin, const float* vs, const int32_t* dim) {
     return g;
 }
 
-static tof64 mktof(float bw, float sig, float nsig, float off, int32_t nb) {
+static tof64 mktof(float bw, float sig, float nsig, float off, int32_t nb, const float* lut, int32_t lut_n,
+                   double lut_x0, double lut_dx) {
     tof64 t;
     t.bw = bw;
     t.sig = sig;
     t.trunc = (double)nsig * (double)sig;
     t.off = off;
     t.nb = nb;
+    t.lut = lut;
+    t.lut_n = lut_n;
+    t.lut_x0 = lut_x0;
+    t.lut_dx = lut_dx;
     return t;
 }
+
+#define NOTOF(name) tof64 name = mktof(1.f, 1.f, 1.f, 0.f, 1, NULL, 0, 0.0, 1.0)
 
 static ray64 ray_setup(const float* xs, const float* xe, const grid64* g) {
     ray64 r;
@@ -162,10 +177,30 @@ static double tof_G(double x, const tof64* tf) {
     return 0.5 * erf(x / (sqrt(2.0) * tf->sig));
 }
 
+/* tabulated kernel: linear interpolation between the table entries around x */
+static double tof_lut(double x, const tof64* tf) {
+    double u = (x - tf->lut_x0) / tf->lut_dx;
+    if (!(u >= 0.0) || u > (double)(tf->lut_n - 1)) return 0.0;
+    int64_t i = (int64_t)floor(u);
+    if (i >= tf->lut_n - 1) return (double)tf->lut[tf->lut_n - 1];
+    double f = u - (double)i;
+    return (1.0 - f) * (double)tf->lut[i] + f * (double)tf->lut[i + 1];
+}
+
 /* weight of TOF bin `bin` for a sample at signed position s (mm from the midpoint) */
 static double tof_weight(double s, int bin, const tof64* tf) {
     double c = ((double)bin - 0.5 * (double)(tf->nb - 1)) * tf->bw + tf->off;
+    if (tf->lut) return tof_lut(s - c, tf);
     return tof_G(s - c + 0.5 * tf->bw, tf) - tof_G(s - c - 0.5 * tf->bw, tf);
+}
+
+/* whether a sample at s lies inside the support of bin `bin` (work counter): the
+ * Gaussian's weight is non-zero exactly there, a table's support is its open range */
+static int tof_inside(double s, int bin, const tof64* tf) {
+    if (!tf->lut) return tof_weight(s, bin, tf) != 0.0;
+    double c = ((double)bin - 0.5 * (double)(tf->nb - 1)) * tf->bw + tf->off;
+    double x = s - c;
+    return x > tf->lut_x0 && x < tf->lut_x0 + (double)(tf->lut_n - 1) * tf->lut_dx;
 }
 
 /* interpolated image value of one stencil */
@@ -290,46 +325,50 @@ int orc_max_threads(void) { return nthreads(); }
 void orc_fwd(const float* xs, const float* xe, int64_t n, const float* origin, const float* vs, const int32_t* dim,
              const double* img, double* p) {
     grid64 g = mkgrid(origin, vs, dim);
-    tof64 tf = mktof(1.f, 1.f, 1.f, 0.f, 1);
+    NOTOF(tf);
     forward_all(xs, xe, n, &g, &tf, 0, NULL, img, p);
 }
 
 void orc_back(const float* xs, const float* xe, int64_t n, const float* origin, const float* vs, const int32_t* dim,
               double* img, const double* p) {
     grid64 g = mkgrid(origin, vs, dim);
-    tof64 tf = mktof(1.f, 1.f, 1.f, 0.f, 1);
+    NOTOF(tf);
     back_all(xs, xe, n, &g, &tf, 0, NULL, img, p);
 }
 
 void orc_fwd_tof_sino(const float* xs, const float* xe, int64_t n, const float* origin, const float* vs,
                       const int32_t* dim, float bin_width, float sigma, float n_sigmas, float center_offset,
-                      int32_t n_bins, const double* img, double* p) {
+                      int32_t n_bins, const float* lut, int32_t lut_n, double lut_x0, double lut_dx,
+                      const double* img, double* p) {
     grid64 g = mkgrid(origin, vs, dim);
-    tof64 tf = mktof(bin_width, sigma, n_sigmas, center_offset, n_bins);
+    tof64 tf = mktof(bin_width, sigma, n_sigmas, center_offset, n_bins, lut, lut_n, lut_x0, lut_dx);
     forward_all(xs, xe, n, &g, &tf, 1, NULL, img, p);
 }
 
 void orc_back_tof_sino(const float* xs, const float* xe, int64_t n, const float* origin, const float* vs,
                        const int32_t* dim, float bin_width, float sigma, float n_sigmas, float center_offset,
-                       int32_t n_bins, double* img, const double* p) {
+                       int32_t n_bins, const float* lut, int32_t lut_n, double lut_x0, double lut_dx,
+                       double* img, const double* p) {
     grid64 g = mkgrid(origin, vs, dim);
-    tof64 tf = mktof(bin_width, sigma, n_sigmas, center_offset, n_bins);
+    tof64 tf = mktof(bin_width, sigma, n_sigmas, center_offset, n_bins, lut, lut_n, lut_x0, lut_dx);
     back_all(xs, xe, n, &g, &tf, 1, NULL, img, p);
 }
 
 void orc_fwd_tof_lm(const float* xs, const float* xe, int64_t n, const float* origin, const float* vs,
                     const int32_t* dim, float bin_width, float sigma, float n_sigmas, float center_offset,
-                    int32_t n_bins, const int16_t* bins, const double* img, double* p) {
+                    int32_t n_bins, const float* lut, int32_t lut_n, double lut_x0, double lut_dx,
+                    const int16_t* bins, const double* img, double* p) {
     grid64 g = mkgrid(origin, vs, dim);
-    tof64 tf = mktof(bin_width, sigma, n_sigmas, center_offset, n_bins);
+    tof64 tf = mktof(bin_width, sigma, n_sigmas, center_offset, n_bins, lut, lut_n, lut_x0, lut_dx);
     forward_all(xs, xe, n, &g, &tf, 2, bins, img, p);
 }
 
 void orc_back_tof_lm(const float* xs, const float* xe, int64_t n, const float* origin, const float* vs,
                      const int32_t* dim, float bin_width, float sigma, float n_sigmas, float center_offset,
-                     int32_t n_bins, const int16_t* bins, double* img, const double* p) {
+                     int32_t n_bins, const float* lut, int32_t lut_n, double lut_x0, double lut_dx,
+                     const int16_t* bins, double* img, const double* p) {
     grid64 g = mkgrid(origin, vs, dim);
-    tof64 tf = mktof(bin_width, sigma, n_sigmas, center_offset, n_bins);
+    tof64 tf = mktof(bin_width, sigma, n_sigmas, center_offset, n_bins, lut, lut_n, lut_x0, lut_dx);
     back_all(xs, xe, n, &g, &tf, 2, bins, img, p);
 }
 
@@ -339,9 +378,10 @@ void orc_back_tof_lm(const float* xs, const float* xe, int64_t n, const float* o
  * per_ray (nullable) receives the per-ray counts. */
 int64_t orc_count_samples(const float* xs, const float* xe, int64_t n, const float* origin, const float* vs,
                           const int32_t* dim, float bin_width, float sigma, float n_sigmas, float center_offset,
-                          int32_t n_bins, const int16_t* bins, int64_t* per_ray) {
+                          int32_t n_bins, const float* lut, int32_t lut_n, double lut_x0, double lut_dx,
+                          const int16_t* bins, int64_t* per_ray) {
     grid64 g = mkgrid(origin, vs, dim);
-    tof64 tf = mktof(bin_width, sigma, n_sigmas, center_offset, n_bins);
+    tof64 tf = mktof(bin_width, sigma, n_sigmas, center_offset, n_bins, lut, lut_n, lut_x0, lut_dx);
     int64_t total = 0;
 #pragma omp parallel for schedule(static) reduction(+ : total)
     for (int64_t l = 0; l < n; ++l) {
@@ -354,7 +394,7 @@ int64_t orc_count_samples(const float* xs, const float* xe, int64_t n, const flo
             for (int64_t k = 0; k < g.n[r.p]; ++k) {
                 if (!plane_stencil(&g, &r, k, &t, idx, wt)) continue;
                 if (idx[0] < 0 && idx[1] < 0 && idx[2] < 0 && idx[3] < 0) continue;
-                if (bins && tof_weight((t - 0.5) * r.len, bins[l], &tf) == 0.0) continue;
+                if (bins && !tof_inside((t - 0.5) * r.len, bins[l], &tf)) continue;
                 ++cnt;
             }
         }
@@ -430,10 +470,11 @@ void orc_gauss3d(const double* src, double* dst, const int32_t* dim, const float
  * ones).  x holds the initial image on entry and the result on return. */
 void orc_lm_osem(const float* xs, const float* xe, const int16_t* bins, int64_t n, const float* origin,
                  const float* vs, const int32_t* dim, float bin_width, float sigma, float n_sigmas,
-                 float center_offset, int32_t n_bins, const double* sens, double bg, int32_t n_iter,
+                 float center_offset, int32_t n_bins, const float* lut, int32_t lut_n, double lut_x0,
+                 double lut_dx, const double* sens, double bg, int32_t n_iter,
                  int32_t n_sub, double* x, const double* fwhm) {
     grid64 g = mkgrid(origin, vs, dim);
-    tof64 tf = mktof(bin_width, sigma, n_sigmas, center_offset, n_bins);
+    tof64 tf = mktof(bin_width, sigma, n_sigmas, center_offset, n_bins, lut, lut_n, lut_x0, lut_dx);
     int64_t nv = nvox(&g);
     int nt = nthreads();
     double* priv = (double*)malloc((size_t)nt * (size_t)nv * sizeof(double));

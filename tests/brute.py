@@ -82,14 +82,20 @@ def system_matrix(xstart, xend, origin, voxsize, dim, tof=None, mode="nontof", b
                 A[l, v] = ell * wgt
                 continue
             spos = (t - 0.5) * length
+            wfn = tof.get("weight_fn")  # an explicit bin-weight function of x = s - c_b, if given
+
+            def weight(cb):
+                if wfn is not None:
+                    return wfn(spos - cb)
+                return tof_weight_quadrature(spos, cb, tof["bin_width"], tof["sigma"], tof["n_sigmas"])
+
             if mode == "sino":
                 for b in range(nb):
                     cb = (b - 0.5 * (nb - 1)) * tof["bin_width"] + tof.get("center_offset", 0.0)
-                    A[l, b, v] = ell * wgt * tof_weight_quadrature(spos, cb, tof["bin_width"], tof["sigma"],
-                                                                   tof["n_sigmas"])
+                    A[l, b, v] = ell * wgt * weight(cb)
             else:
                 cb = (b - 0.5 * (int(tof["n_bins"]) - 1)) * tof["bin_width"] + tof.get("center_offset", 0.0)
-                A[l, v] = ell * wgt * tof_weight_quadrature(spos, cb, tof["bin_width"], tof["sigma"], tof["n_sigmas"])
+                A[l, v] = ell * wgt * weight(cb)
     return A
 
 
