@@ -24,7 +24,7 @@
  *   Coordinates: float32, array of structures [n][3] = (x, y, z) in mm.
  *   Image: float32, C order [dim[0]][dim[1]][dim[2]] (axis 2 fastest); the
  *     centre of voxel (i, j, k) is origin + (i, j, k) * voxsize.  Voxels
- *     outside the grid read as zero.  dim[0]*dim[1]*dim[2] < 2^31.
+ *     outside the grid read as zero.  dim[0]*dim[1]*dim[2] <= 2^30.
  *   Principal axis: argmax_a |end_a - start_a| in mm (float32 differences,
  *     first axis on ties).  The ray is the segment start -> end: plane k is
  *     visited iff its ray parameter t in [0, 1].
@@ -33,7 +33,8 @@
  *     c_b = (b - (n_bins - 1)/2) * bin_width + center_offset and weight
  *       w_b(s) = G(s - c_b + bin_width/2) - G(s - c_b - bin_width/2),
  *       G(x)   = erf(clip(x, -n_sigmas*sigma, n_sigmas*sigma) / (sqrt(2) sigma)) / 2
- *     (the Gaussian is truncated before the convolution; no renormalisation).
+ *     (the Gaussian is truncated before the convolution; no renormalisation),
+ *     or a tabulated kernel (pp_tof_t.lut).
  *   Pointers: every array argument is a DEVICE pointer owned by the caller;
  *     the geometry / TOF structs are HOST pointers read during the call.
  *     The library allocates nothing and keeps no state between calls.
@@ -61,13 +62,13 @@
 extern "C" {
 #endif
 
-#define PP_ABI_VERSION 2
+#define PP_ABI_VERSION 3
 
 enum pp_status {
     PP_OK = 0,
     PP_EINVAL_PTR = 1,  /* a required pointer is NULL */
     PP_EINVAL_GEOM = 2, /* dim <= 0, voxel count > 2^30, voxsize <= 0 or non-finite, origin non-finite */
-    PP_EINVAL_TOF = 3,  /* n_bins not in [1, 256], bin_width/sigma/n_sigmas <= 0 or non-finite */
+    PP_EINVAL_TOF = 3,  /* n_bins not in [1, 256], bin_width/sigma/n_sigmas <= 0 or non-finite, bad table */
     PP_EINVAL_N = 4,    /* negative count, or a count/slot argument out of range */
     PP_EHIP = 5,        /* the HIP runtime rejected a launch */
     PP_EINVAL_RES = 6   /* resolution model: FWHM negative or non-finite, or wider than 31 voxels of radius */
@@ -79,12 +80,27 @@ typedef struct pp_image {
     int32_t dim[3];   /* voxels per axis, > 0 */
 } pp_image_t;
 
+/* TOF kernel.  Bin b of a LOR is centred at c_b = (b - (n_bins - 1)/2) bin_width +
+ * center_offset (mm from the LOR midpoint towards its end point).  The weight of bin b for
+ * a plane sample at TOF position s is w(x), x = s - c_b:
+ *   lut == NULL: the Gaussian of the given sigma, truncated at n_sigmas, convolved with the
+ *     bin's rect: G(x + bw/2) - G(x - bw/2), G(x) = erf(clip(x, +-n_sigmas sigma) /
+ *     (sqrt(2) sigma)) / 2 (Sec. 2.1; truncation Sec. 2.6);
+ *   lut != NULL: the tabulated kernel that Sec. 4 proposes (which also allows non-Gaussian
+ *     kernels): lut[i] = w(lut_x0 + i lut_dx), i in [0, lut_n), linearly interpolated and 0
+ *     outside [lut_x0, lut_x0 + (lut_n - 1) lut_dx]; sigma and n_sigmas are ignored.  The
+ *     table is DEVICE memory owned by the caller and must stay valid until the calls that
+ *     use it have run (it is read at run time, also by captured graphs). */
 typedef struct pp_tof {
     float bin_width;     /* mm, > 0 */
     float sigma;         /* mm, > 0 (FWHM / 2.355) */
     float n_sigmas;      /* truncation in sigmas, > 0 */
     float center_offset; /* mm, shift of every bin centre along the LOR */
     int32_t n_bins;      /* 1 .. 256 */
+    const float* lut;    /* DEVICE [lut_n] tabulated bin weight, or NULL (Gaussian) */
+    int32_t lut_n;       /* 2 .. 2^24 when lut is set */
+    float lut_x0;        /* mm, position of lut[0] relative to the bin centre; finite */
+    float lut_dx;        /* mm, table spacing, > 0 */
 } pp_tof_t;
 
 /* Non-TOF forward projection (Sec. 2.1, Fig. 1).

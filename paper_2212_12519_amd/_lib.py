@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from dataclasses import dataclass
+from dataclasses import dataclass, field
 
 import torch
 
@@ -32,7 +32,11 @@ class CImage(ctypes.Structure):
 
 class CTof(ctypes.Structure):
     _fields_ = [("bin_width", ctypes.c_float), ("sigma", ctypes.c_float), ("n_sigmas", ctypes.c_float),
-                ("center_offset", ctypes.c_float), ("n_bins", ctypes.c_int32)]
+                ("center_offset", ctypes.c_float), ("n_bins", ctypes.c_int32), ("lut", ctypes.c_void_p),
+                ("lut_n", ctypes.c_int32), ("lut_x0", ctypes.c_float), ("lut_dx", ctypes.c_float)]
+
+
+assert ctypes.sizeof(CTof) == 48, ctypes.sizeof(CTof)
 
 
 class COsemSlot(ctypes.Structure):
@@ -73,14 +77,31 @@ class ImageGeom:
 
 @dataclass(frozen=True)
 class TofParams:
+    """TOF bins and kernel.  With `lut` (a float32 CUDA tensor: the bin weight at distances
+    lut_x0 + i * lut_dx mm from the bin centre, linearly interpolated, 0 outside) the kernel is
+    the table and sigma / n_sigmas are ignored; the tensor must outlive the calls using it."""
     bin_width: float
     sigma: float
     n_sigmas: float
     n_bins: int
     center_offset: float = 0.0
+    lut: object = field(default=None, compare=False)
+    lut_x0: float = 0.0
+    lut_dx: float = 0.0
+
+    def __post_init__(self):
+        if self.lut is not None:
+            t = self.lut
+            if not (isinstance(t, torch.Tensor) and t.device.type == "cuda" and t.dtype == torch.float32
+                    and t.is_contiguous() and t.dim() == 1 and t.numel() >= 2):
+                raise ValueError("lut must be a contiguous 1-D float32 CUDA tensor of >= 2 entries")
 
     def c(self):
-        return CTof(self.bin_width, self.sigma, self.n_sigmas, self.center_offset, int(self.n_bins))
+        if self.lut is None:
+            return CTof(self.bin_width, self.sigma, self.n_sigmas, self.center_offset, int(self.n_bins), None, 0,
+                        0.0, 0.0)
+        return CTof(self.bin_width, self.sigma, self.n_sigmas, self.center_offset, int(self.n_bins),
+                    self.lut.data_ptr(), int(self.lut.numel()), float(self.lut_x0), float(self.lut_dx))
 
 
 def as_geom(g) -> ImageGeom:
@@ -93,7 +114,8 @@ def as_tof(t) -> TofParams:
     if isinstance(t, TofParams):
         return t
     return TofParams(float(t.bin_width), float(t.sigma), float(t.n_sigmas), int(t.n_bins),
-                     float(getattr(t, "center_offset", 0.0)))
+                     float(getattr(t, "center_offset", 0.0)), getattr(t, "lut", None),
+                     float(getattr(t, "lut_x0", 0.0)), float(getattr(t, "lut_dx", 0.0)))
 
 
 def load():

@@ -11,6 +11,9 @@
 
 using namespace ppmi;
 
+static_assert(sizeof(pp_tof_t) == 48, "pp_tof_t layout");
+static_assert(sizeof(pp_osem_slot_t) == 104, "pp_osem_slot_t layout");
+
 namespace {
 
 thread_local char g_hip_msg[256] = "";
@@ -46,9 +49,28 @@ int make_geom(const pp_image_t* gi, GeomK& g) {
 int make_tof(const pp_tof_t* ti, TofK& t) {
     if (!ti) return PP_EINVAL_PTR;
     if (ti->n_bins < 1 || ti->n_bins > 256) return PP_EINVAL_TOF;
-    if (!std::isfinite(ti->bin_width) || !(ti->bin_width > 0.0f) || !std::isfinite(ti->sigma) ||
-        !(ti->sigma > 0.0f) || !std::isfinite(ti->n_sigmas) || !(ti->n_sigmas > 0.0f) ||
-        !std::isfinite(ti->center_offset))
+    if (!std::isfinite(ti->bin_width) || !(ti->bin_width > 0.0f) || !std::isfinite(ti->center_offset))
+        return PP_EINVAL_TOF;
+    if (ti->lut) {  // tabulated kernel: sigma and n_sigmas are not used
+        const double x0 = ti->lut_x0, dx = ti->lut_dx, x1 = x0 + (double)(ti->lut_n - 1) * dx;
+        if (ti->lut_n < 2 || ti->lut_n > (1 << 24) || !std::isfinite(ti->lut_x0) || !std::isfinite(ti->lut_dx) ||
+            !(ti->lut_dx > 0.0f) || !(std::fabs(x1) <= 3.0e38))  // the table's end must be a float
+            return PP_EINVAL_TOF;
+        t.bw = ti->bin_width;
+        t.c0 = -0.5 * (double)(ti->n_bins - 1) * t.bw + (double)ti->center_offset;
+        t.trunc = 1.0f;
+        t.hbw = (float)(0.5 * t.bw);
+        t.inv_sqrt2_sig = 1.0f;
+        t.nb = ti->n_bins;
+        t.lo = x0;
+        t.hi = x1;
+        t.win = std::fmax(std::fabs(x0), std::fabs(x1));
+        t.lut = ti->lut;
+        t.lut_n = ti->lut_n;
+        t.lut_inv_dx = (float)(1.0 / dx);
+        return PP_OK;
+    }
+    if (!std::isfinite(ti->sigma) || !(ti->sigma > 0.0f) || !std::isfinite(ti->n_sigmas) || !(ti->n_sigmas > 0.0f))
         return PP_EINVAL_TOF;
     const double bw = ti->bin_width, sig = ti->sigma, ns = ti->n_sigmas;
     t.bw = bw;
@@ -58,6 +80,11 @@ int make_tof(const pp_tof_t* ti, TofK& t) {
     t.win = ns * sig + 0.5 * bw;
     t.inv_sqrt2_sig = (float)(1.0 / (std::sqrt(2.0) * sig));
     t.nb = ti->n_bins;
+    t.lo = -t.win;
+    t.hi = t.win;
+    t.lut = nullptr;
+    t.lut_n = 0;
+    t.lut_inv_dx = 0.0f;
     return PP_OK;
 }
 

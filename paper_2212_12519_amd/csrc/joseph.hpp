@@ -29,6 +29,10 @@ struct TofK {
     double bw;            // bin width, mm
     double c0;            // centre of bin 0, mm: -(n_bins - 1)/2 * bw + offset
     double win;           // half support of a bin's weight: n_sigmas * sigma + bw / 2
+    double lo, hi;        // support of a bin's weight relative to its centre (table: its range)
+    const float* lut;     // tabulated bin weight at lo + i * dx, or nullptr (Gaussian)
+    int lut_n;
+    float lut_inv_dx;
     float trunc;          // n_sigmas * sigma, mm
     float hbw;            // bw / 2, mm
     float inv_sqrt2_sig;  // 1 / (sqrt(2) sigma)
@@ -132,10 +136,10 @@ __device__ __forceinline__ bool ray_setup(const float* __restrict__ xs, const fl
     return lo <= hi;
 }
 
-// Plane range of the ray restricted to the TOF window of one bin centre.
-__device__ __forceinline__ bool tof_window(RayK& r, double centre, double win) {
+// Plane range of the ray restricted to the support of one bin (centre + [t.lo, t.hi]).
+__device__ __forceinline__ bool tof_window(RayK& r, double centre, const TofK& t) {
     int lo = r.k_lo, hi = r.k_hi;
-    clip_affine(r.s0, r.ds, centre - win, centre + win, lo, hi);
+    clip_affine(r.s0, r.ds, centre + t.lo, centre + t.hi, lo, hi);
     r.k_lo = lo;
     r.k_hi = hi;
     return lo <= hi;
@@ -143,8 +147,8 @@ __device__ __forceinline__ bool tof_window(RayK& r, double centre, double win) {
 
 // The same, then s(k) made relative to the bin centre (s0 -= centre): fma(k, ds, s0) is
 // the signed distance of plane sample k from the centre, the argument of tof_weight.
-__device__ __forceinline__ bool tof_window_rel(RayK& r, double centre, double win) {
-    const bool any = tof_window(r, centre, win);
+__device__ __forceinline__ bool tof_window_rel(RayK& r, double centre, const TofK& t) {
+    const bool any = tof_window(r, centre, t);
     r.s0 -= centre;
     return any;
 }
@@ -257,17 +261,29 @@ __device__ __forceinline__ float tof_erf(float x, const TofK& t) {
 // G(x) = erf(clip(x, -trunc, trunc) / (sqrt(2) sigma)) / 2
 __device__ __forceinline__ float tof_cdf(double x, const TofK& t) { return 0.5f * tof_erf((float)x, t); }
 
+// Tabulated kernel (the lookup-table alternative of Sec. 4, which also admits non-Gaussian
+// TOF kernels): linear interpolation of the table at u = (x - lo) / dx, 0 outside it.
+__device__ __forceinline__ float tof_lut(double x, const TofK& t) {
+    const float u = (float)(x - t.lo) * t.lut_inv_dx;
+    if (!(u >= 0.0f) || u > (float)(t.lut_n - 1)) return 0.0f;
+    const int i = min((int)u, t.lut_n - 2);
+    const float f = u - (float)i, a = t.lut[i], b = t.lut[i + 1];
+    return fmaf(f, b - a, a);
+}
+
 // weight of a bin for a plane sample at signed distance x (mm) from the bin centre:
-// G(x + bw/2) - G(x - bw/2)
+// G(x + bw/2) - G(x - bw/2) (Lut = false), or the tabulated kernel (Lut = true)
+template <bool Lut>
 __device__ __forceinline__ float tof_weight(double x, const TofK& t) {
+    if (Lut) return tof_lut(x, t);
     const float xf = (float)x;
     return 0.5f * (tof_erf(xf + t.hbw, t) - tof_erf(xf - t.hbw, t));
 }
 
 // TOF bins whose window contains a sample at absolute TOF position s (clamped to [0, n_bins)).
 __device__ __forceinline__ void tof_bin_range(double s, const TofK& t, int& b_lo, int& b_hi) {
-    const double lo = floor((s - t.win - t.c0) / t.bw);
-    const double hi = ceil((s + t.win - t.c0) / t.bw);
+    const double lo = floor((s - t.hi - t.c0) / t.bw);
+    const double hi = ceil((s - t.lo - t.c0) / t.bw);
     b_lo = (int)fmax(lo, 0.0);
     b_hi = (int)fmin(hi, (double)(t.nb - 1));
 }

@@ -42,6 +42,7 @@ __host__ __device__ inline int64_t slot_chunks(int64_t n_events, int32_t n_sub) 
 
 // Per event: forward project through the frame's current image (setup), then scatter
 // ell / ybar times the TOF weight (sample) -- the run/sheet back projection of sheet.hpp.
+template <bool Lut>
 struct ModeOsem {
     static constexpr bool kColAtomic = true;
     const float* __restrict__ x;
@@ -51,10 +52,10 @@ struct ModeOsem {
     __device__ bool setup(int64_t l, const float* xs, const float* xe, const GeomK& g, RayK& r, float& cv) const {
         const int b = bins[l];
         if (b < 0 || b >= t.nb || !ray_setup(xs + 3 * l, xe + 3 * l, g, r)) return false;
-        if (!tof_window_rel(r, t.c0 + b * t.bw, t.win)) return false;
+        if (!tof_window_rel(r, t.c0 + b * t.bw, t)) return false;
         float fwd = 0.0f;
         for (int k = r.k_lo; k <= r.k_hi; ++k) {
-            const float w = tof_weight(fma((double)k, r.ds, r.s0), t);
+            const float w = tof_weight<Lut>(fma((double)k, r.ds, r.s0), t);
             fwd += w * stencil_gather(x, r, stencil_at(r, k));
         }
         const float ybar = r.ell * fwd + bg;
@@ -62,9 +63,10 @@ struct ModeOsem {
         cv = r.ell / ybar;
         return true;
     }
-    __device__ float sample(double x, float cv) const { return tof_weight(x, t) * cv; }
+    __device__ float sample(double x, float cv) const { return tof_weight<Lut>(x, t) * cv; }
 };
 
+template <bool Lut>
 __global__ void __launch_bounds__(kSheetBlock) k_osem_accumulate(const pp_osem_slot_t* __restrict__ slots,
                                                                  int n_slots, GeomK g, TofK t, int nw_lds) {
     extern __shared__ double smem[];
@@ -85,7 +87,7 @@ __global__ void __launch_bounds__(kSheetBlock) k_osem_accumulate(const pp_osem_s
         const int64_t off_j = j * base_n + (j < rem ? j : rem);
         const int64_t q0 = (c - s.chunk_begin) * kOsemChunk;
         if (q0 >= n_j) continue;
-        ModeOsem m{s.x_fwd ? s.x_fwd : s.x, s.tof_bin + off_j, s.bg, t};
+        ModeOsem<Lut> m{s.x_fwd ? s.x_fwd : s.x, s.tof_bin + off_j, s.bg, t};
         back_runs_chunk(m, s.xstart + 3 * off_j, s.xend + 3 * off_j, n_j, g, s.acc, nullptr, nw_lds, kOsemGroups,
                         q0, smem);
     }
@@ -129,20 +131,28 @@ __global__ void k_fill(float* __restrict__ dst, int64_t n, float value) {
 
 int64_t osem_chunks(int64_t n_events, int32_t n_sub) { return slot_chunks(n_events, n_sub); }
 
-hipError_t launch_osem_accumulate(const pp_osem_slot_t* slots, int n_slots, const GeomK& g, const TofK& t, int cus,
-                                  hipStream_t s) {
+template <bool Lut>
+static hipError_t launch_accumulate(const pp_osem_slot_t* slots, int n_slots, const GeomK& g, const TofK& t, int cus,
+                                   hipStream_t s) {
     const int nw = (g.n[2] <= kSheetMaxW) ? g.n[2] : 0;
     const size_t lds = SheetLayout::bytes(nw, g);
-    hipError_t e = hipFuncSetAttribute((const void*)k_osem_accumulate, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
+    hipError_t e = hipFuncSetAttribute((const void*)k_osem_accumulate<Lut>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     // persistent grid: as many workgroups as can be resident at once (LDS-limited)
     int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_osem_accumulate, kSheetBlock, lds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_osem_accumulate<Lut>, kSheetBlock, lds);
     if (e != hipSuccess) return e;
     if (per_cu < 1) per_cu = 1;
-    hipLaunchKernelGGL(k_osem_accumulate, dim3(cus * per_cu), dim3(kSheetBlock), lds, s, slots, n_slots, g, t, nw);
+    hipLaunchKernelGGL(k_osem_accumulate<Lut>, dim3(cus * per_cu), dim3(kSheetBlock), lds, s, slots, n_slots, g, t,
+                       nw);
     return hipGetLastError();
+}
+
+hipError_t launch_osem_accumulate(const pp_osem_slot_t* slots, int n_slots, const GeomK& g, const TofK& t, int cus,
+                                  hipStream_t s) {
+    return t.lut ? launch_accumulate<true>(slots, n_slots, g, t, cus, s)
+                 : launch_accumulate<false>(slots, n_slots, g, t, cus, s);
 }
 
 hipError_t launch_osem_update(pp_osem_slot_t* slots, int n_slots, int64_t n_vox, int n_blocks, hipStream_t s) {

@@ -40,6 +40,7 @@ __global__ void __launch_bounds__(kBlock) k_fwd(const float* __restrict__ xs, co
 
 // ------------------------------------------------------- TOF listmode ----
 
+template <bool Lut>
 __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(const float* __restrict__ xs, const float* __restrict__ xe,
                                                        const int16_t* __restrict__ bins, int64_t n, GeomK g,
                                                        TofK t, const float* __restrict__ img,
@@ -50,9 +51,9 @@ __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(const float* __restrict__
     float acc = 0.0f;
     RayK r;
     if (b >= 0 && b < t.nb && ray_setup(xs + 3 * l, xe + 3 * l, g, r)) {
-        if (tof_window_rel(r, t.c0 + b * t.bw, t.win)) {
+        if (tof_window_rel(r, t.c0 + b * t.bw, t)) {
             for (int k = r.k_lo; k <= r.k_hi; ++k) {
-                const float w = tof_weight(fma((double)k, r.ds, r.s0), t);
+                const float w = tof_weight<Lut>(fma((double)k, r.ds, r.s0), t);
                 acc += w * stencil_gather(img, r, stencil_at(r, k));
             }
             acc *= r.ell;
@@ -86,6 +87,10 @@ __global__ void k_fwd_tof_sino(const float* __restrict__ xs, const float* __rest
             const double s = fma((double)k, r.ds, r.s0);
             int b_lo, b_hi;
             tof_bin_range(s, t, b_lo, b_hi);
+            if (t.lut) {
+                for (int b = b_lo; b <= b_hi; ++b) mine[b * nt] += tof_lut(s - (t.c0 + b * t.bw), t) * v;
+                continue;
+            }
             const double x_hi0 = s - (t.c0 + b_lo * t.bw) + 0.5 * t.bw;  // upper edge argument of bin b_lo
             float g_hi = tof_cdf(x_hi0, t);
             for (int b = b_lo; b <= b_hi; ++b) {
@@ -140,12 +145,16 @@ __global__ void k_back_tof_sino(const float* __restrict__ xs, const float* __res
             const double s = fma((double)k, r.ds, r.s0);
             int b_lo, b_hi;
             tof_bin_range(s, t, b_lo, b_hi);
-            const double x_hi0 = s - (t.c0 + b_lo * t.bw) + 0.5 * t.bw;
-            float g_hi = tof_cdf(x_hi0, t);
-            for (int b = b_lo; b <= b_hi; ++b) {
-                const float g_lo = tof_cdf(x_hi0 - (double)(b - b_lo + 1) * t.bw, t);
-                c += (g_hi - g_lo) * mine[b * nt];
-                g_hi = g_lo;
+            if (t.lut) {
+                for (int b = b_lo; b <= b_hi; ++b) c += tof_lut(s - (t.c0 + b * t.bw), t) * mine[b * nt];
+            } else {
+                const double x_hi0 = s - (t.c0 + b_lo * t.bw) + 0.5 * t.bw;
+                float g_hi = tof_cdf(x_hi0, t);
+                for (int b = b_lo; b <= b_hi; ++b) {
+                    const float g_lo = tof_cdf(x_hi0 - (double)(b - b_lo + 1) * t.bw, t);
+                    c += (g_hi - g_lo) * mine[b * nt];
+                    g_hi = g_lo;
+                }
             }
             c *= r.ell;
             st = stencil_at(r, k);
@@ -173,13 +182,16 @@ __global__ void __launch_bounds__(kBlock) k_count(const float* __restrict__ xs, 
         const int b = bins[l];
         ok = b >= 0 && b < t.nb;
         centre = t.c0 + b * t.bw;
-        ok = ok && tof_window(r, centre, t.win);
+        ok = ok && tof_window(r, centre, t);
     }
     if (ok) {
         for (int k = r.k_lo; k <= r.k_hi; ++k) {
             const Stencil st = stencil_at(r, k);
             if (!((st.i0ok || st.i1ok) && (st.j0ok || st.j1ok))) continue;
-            if (bins && !(fabs(fma((double)k, r.ds, r.s0) - centre) < t.win)) continue;
+            if (bins) {
+                const double x = fma((double)k, r.ds, r.s0) - centre;
+                if (!(x > t.lo && x < t.hi)) continue;
+            }
             ++cnt;
         }
     }
@@ -225,15 +237,15 @@ hipError_t launch_back(const float* xs, const float* xe, int64_t n, const GeomK&
 
 hipError_t launch_fwd_tof_lm(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g,
                              const TofK& t, const float* img, float* p, const int32_t* order, hipStream_t s) {
-    hipLaunchKernelGGL(k_fwd_tof_lm, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, xs, xe, bins, n, g, t, img, p,
-                       order);
+    hipLaunchKernelGGL(t.lut ? k_fwd_tof_lm<true> : k_fwd_tof_lm<false>, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s,
+                       xs, xe, bins, n, g, t, img, p, order);
     return hipGetLastError();
 }
 
 hipError_t launch_back_tof_lm(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g,
                               const TofK& t, float* img, const float* p, const int32_t* order, hipStream_t s) {
-    ModeTofLm m{p, bins, t};
-    return launch_runs(m, xs, xe, n, g, img, order, s);
+    if (t.lut) return launch_runs(ModeTofLm<true>{p, bins, t}, xs, xe, n, g, img, order, s);
+    return launch_runs(ModeTofLm<false>{p, bins, t}, xs, xe, n, g, img, order, s);
 }
 
 static int sino_block(int nb) { return nb <= 64 ? 256 : 64; }  // LDS tile <= 64 KiB

@@ -65,6 +65,7 @@ struct ModeNonTof {
     __device__ float sample(double /*x*/, float cv) const { return cv; }
 };
 
+template <bool Lut>
 struct ModeTofLm {
     static constexpr bool kColAtomic = true;
     const float* __restrict__ p;
@@ -74,11 +75,11 @@ struct ModeTofLm {
         const int b = bins[l];
         const float pl = p[l];
         if (b < 0 || b >= t.nb || pl == 0.0f || !ray_setup(xs + 3 * l, xe + 3 * l, g, r)) return false;
-        if (!tof_window_rel(r, t.c0 + b * t.bw, t.win)) return false;
+        if (!tof_window_rel(r, t.c0 + b * t.bw, t)) return false;
         cv = r.ell * pl;
         return true;
     }
-    __device__ float sample(double x, float cv) const { return tof_weight(x, t) * cv; }
+    __device__ float sample(double x, float cv) const { return tof_weight<Lut>(x, t) * cv; }
 };
 
 // Broadcast lane `src` (wave-uniform) of a double to the whole wave through scalar registers.

@@ -7,10 +7,11 @@ allocate the output with torch and call the ``pp_*`` function.
 from __future__ import annotations
 
 import ctypes
+import math
 
 import torch
 
-from ._lib import _bins, _dev, _img, _order, _rays, as_geom, as_tof, check, load, ptr, stream_of
+from ._lib import TofParams, _bins, _dev, _img, _order, _rays, as_geom, as_tof, check, load, ptr, stream_of
 
 def pp_fwd(xstart, xend, geom, img, p, order=None):
     """Non-TOF forward projection into p[n] (overwritten). Sec. 2.1 of the paper.
@@ -150,6 +151,25 @@ def pp_fill(dst, value):
         raise TypeError("float32 only")
     check(load().pp_fill(ptr(dst), dst.numel(), float(value), stream_of(dst)))
     return dst
+
+
+def gaussian_tof_table(tof, dx, device="cuda"):
+    """TofParams whose kernel is the table of its own Gaussian bin weight
+    w(x) = G(x + bw/2) - G(x - bw/2) over its support [-win, win], win = n_sigmas sigma + bw/2,
+    at the largest spacing <= `dx` mm that puts the last entry exactly on +win (evaluated in
+    float64 on the host)."""
+    t = as_tof(tof)
+    win = t.n_sigmas * t.sigma + 0.5 * t.bin_width
+    n = int(math.ceil(2.0 * win / dx)) + 1
+    dx = 2.0 * win / (n - 1)
+    x = -win + dx * torch.arange(n, dtype=torch.float64)
+    tr = t.n_sigmas * t.sigma
+
+    def G(u):
+        return 0.5 * torch.special.erf(torch.clamp(u, -tr, tr) / (math.sqrt(2.0) * t.sigma))
+
+    w = (G(x + 0.5 * t.bin_width) - G(x - 0.5 * t.bin_width)).to(torch.float32).to(device)
+    return TofParams(t.bin_width, t.sigma, t.n_sigmas, t.n_bins, t.center_offset, w, -win, dx)
 
 
 def fwhm3(fwhm):

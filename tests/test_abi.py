@@ -29,7 +29,7 @@ def test_exports_every_declared_symbol(lib):
     assert len(names) >= 12, names
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.pp_abi_version() == 2
+    assert lib.pp_abi_version() == 3
 
 
 def _geom(dim=(4, 4, 4), vs=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0)):
@@ -63,7 +63,14 @@ def test_error_codes(lib):
                 _geom(dim=(2048, 2048, 512))):
         assert lib.pp_fwd(DUMMY, DUMMY, 5, bad, DUMMY, DUMMY, None, None) == PP_EINVAL_GEOM
         assert lib.pp_back(DUMMY, DUMMY, 5, bad, DUMMY, DUMMY, None, None) == PP_EINVAL_GEOM
-    for bad in (_tof(nb=0), _tof(nb=257), _tof(bw=0.0), _tof(sig=-1.0), _tof(ns=0.0), _tof(sig=float("nan"))):
+    from paper_2212_12519_amd._lib import CTof
+
+    def lut(n=16, x0=-4.0, dx=0.5):
+        return CTof(1.0, 0.0, 0.0, 0.0, 5, 16, n, x0, dx)  # sigma / n_sigmas unused with a table
+
+    for bad in (_tof(nb=0), _tof(nb=257), _tof(bw=0.0), _tof(sig=-1.0), _tof(ns=0.0), _tof(sig=float("nan")),
+                lut(n=1), lut(n=(1 << 24) + 1), lut(dx=0.0), lut(dx=-1.0), lut(x0=float("inf")),
+                lut(dx=float("nan")), lut(x0=3e38, dx=3e38)):
         assert lib.pp_fwd_tof_sino(DUMMY, DUMMY, 5, g, bad, DUMMY, DUMMY, None) == PP_EINVAL_TOF
         assert lib.pp_back_tof_lm(DUMMY, DUMMY, DUMMY, 5, g, bad, DUMMY, DUMMY, None, None) == PP_EINVAL_TOF
     assert lib.pp_fwd_tof_lm(DUMMY, DUMMY, None, 5, g, _tof(), DUMMY, DUMMY, None, None) == PP_EINVAL_PTR
