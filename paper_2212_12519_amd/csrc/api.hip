@@ -57,6 +57,7 @@ int make_tof(const pp_tof_t* ti, TofK& t) {
             !(ti->lut_dx > 0.0f) || !(std::fabs(x1) <= 3.0e38))  // the table's end must be a float
             return PP_EINVAL_TOF;
         t.bw = ti->bin_width;
+        t.inv_bw = 1.0 / t.bw;
         t.c0 = -0.5 * (double)(ti->n_bins - 1) * t.bw + (double)ti->center_offset;
         t.trunc = 1.0f;
         t.hbw = (float)(0.5 * t.bw);
@@ -74,6 +75,7 @@ int make_tof(const pp_tof_t* ti, TofK& t) {
         return PP_EINVAL_TOF;
     const double bw = ti->bin_width, sig = ti->sigma, ns = ti->n_sigmas;
     t.bw = bw;
+    t.inv_bw = 1.0 / bw;
     t.c0 = -0.5 * (double)(ti->n_bins - 1) * bw + (double)ti->center_offset;
     t.trunc = (float)(ns * sig);
     t.hbw = (float)(0.5 * bw);

@@ -27,6 +27,7 @@ struct GeomK {
 
 struct TofK {
     double bw;            // bin width, mm
+    double inv_bw;        // 1 / bw
     double c0;            // centre of bin 0, mm: -(n_bins - 1)/2 * bw + offset
     double win;           // half support of a bin's weight: n_sigmas * sigma + bw / 2
     double lo, hi;        // support of a bin's weight relative to its centre (table: its range)
@@ -258,8 +259,6 @@ __device__ __forceinline__ float tof_erf(float x, const TofK& t) {
     return erf_hastings(fminf(fmaxf(x, -t.trunc), t.trunc) * t.inv_sqrt2_sig);
 }
 
-// G(x) = erf(clip(x, -trunc, trunc) / (sqrt(2) sigma)) / 2
-__device__ __forceinline__ float tof_cdf(double x, const TofK& t) { return 0.5f * tof_erf((float)x, t); }
 
 // Tabulated kernel (the lookup-table alternative of Sec. 4, which also admits non-Gaussian
 // TOF kernels): linear interpolation of the table at u = (x - lo) / dx, 0 outside it.
@@ -282,8 +281,10 @@ __device__ __forceinline__ float tof_weight(double x, const TofK& t) {
 
 // TOF bins whose window contains a sample at absolute TOF position s (clamped to [0, n_bins)).
 __device__ __forceinline__ void tof_bin_range(double s, const TofK& t, int& b_lo, int& b_hi) {
-    const double lo = floor((s - t.hi - t.c0) / t.bw);
-    const double hi = ceil((s - t.lo - t.c0) / t.bw);
+    // bins b with c_b in (s - hi, s - lo); a rounding of the products can only drop a bin whose
+    // centre sits exactly on the open end, whose weight is 0
+    const double lo = floor((s - t.hi - t.c0) * t.inv_bw);
+    const double hi = ceil((s - t.lo - t.c0) * t.inv_bw);
     b_lo = (int)fmax(lo, 0.0);
     b_hi = (int)fmin(hi, (double)(t.nb - 1));
 }

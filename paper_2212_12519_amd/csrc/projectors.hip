@@ -91,12 +91,13 @@ __global__ void k_fwd_tof_sino(const float* __restrict__ xs, const float* __rest
                 for (int b = b_lo; b <= b_hi; ++b) mine[b * nt] += tof_lut(s - (t.c0 + b * t.bw), t) * v;
                 continue;
             }
-            const double x_hi0 = s - (t.c0 + b_lo * t.bw) + 0.5 * t.bw;  // upper edge argument of bin b_lo
-            float g_hi = tof_cdf(x_hi0, t);
+            // upper edge argument of bin b_lo; the next edges follow in float steps of bw
+            const float x_hi0 = (float)(s - (t.c0 + b_lo * t.bw) + 0.5 * t.bw), bwf = (float)t.bw;
+            float e_hi = tof_erf(x_hi0, t);
             for (int b = b_lo; b <= b_hi; ++b) {
-                const float g_lo = tof_cdf(x_hi0 - (double)(b - b_lo + 1) * t.bw, t);
-                mine[b * nt] += (g_hi - g_lo) * v;
-                g_hi = g_lo;
+                const float e_lo = tof_erf(x_hi0 - (float)(b - b_lo + 1) * bwf, t);
+                mine[b * nt] += 0.5f * (e_hi - e_lo) * v;
+                e_hi = e_lo;
             }
         }
         const float ell = r.ell;
@@ -148,12 +149,12 @@ __global__ void k_back_tof_sino(const float* __restrict__ xs, const float* __res
             if (t.lut) {
                 for (int b = b_lo; b <= b_hi; ++b) c += tof_lut(s - (t.c0 + b * t.bw), t) * mine[b * nt];
             } else {
-                const double x_hi0 = s - (t.c0 + b_lo * t.bw) + 0.5 * t.bw;
-                float g_hi = tof_cdf(x_hi0, t);
+                const float x_hi0 = (float)(s - (t.c0 + b_lo * t.bw) + 0.5 * t.bw), bwf = (float)t.bw;
+                float e_hi = tof_erf(x_hi0, t);
                 for (int b = b_lo; b <= b_hi; ++b) {
-                    const float g_lo = tof_cdf(x_hi0 - (double)(b - b_lo + 1) * t.bw, t);
-                    c += (g_hi - g_lo) * mine[b * nt];
-                    g_hi = g_lo;
+                    const float e_lo = tof_erf(x_hi0 - (float)(b - b_lo + 1) * bwf, t);
+                    c += 0.5f * (e_hi - e_lo) * mine[b * nt];
+                    e_hi = e_lo;
                 }
             }
             c *= r.ell;
