@@ -14,9 +14,12 @@
 // them into runs (bitwise-equal p, U0, dU).  For every run of >= kRunMin rays
 // each thread becomes a plane k: it walks the run's rays and accumulates the
 // W-interpolated values into its own LDS column (thread-private addresses: no
-// atomics, no bank conflicts), then the waves flush the sheet with
-// contiguous, duplicate-free atomics -- one memory request per ~16 values
-// instead of one per value.  The u-weights (1 - fu, fu) are shared by the
+// atomics, no bank conflicts; the current pair of z entries is kept in
+// registers and written back by read-modify-write when z changes), then the
+// waves flush the sheet with contiguous, duplicate-free atomics -- one memory
+// request per ~16 values instead of one per value.  The column stride is the
+// grid's longest line + 1, so that two workgroups fit a CU's LDS on clinical
+// grids: the loop is latency-bound and needs the second workgroup's waves.  The u-weights (1 - fu, fu) are shared by the
 // run and applied at the flush.  Rays in short runs (or with p == 2, or grids
 // whose axis 2 exceeds the LDS column) take the direct wave-synchronous,
 // run-combined scatter.  The arithmetic per (ray, plane) sample is the same
@@ -313,8 +316,9 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
             }
             // thread tid accumulates the column of absolute plane k = tid.  Each wave loads 64 of
             // the run's rays with one vector LDS read and broadcasts them lane by lane (readlane);
-            // four rays are evaluated branch-free per step so their dependency chains interleave,
-            // and the current pair of z entries stays in registers until z changes.
+            // kSheetUnroll rays are evaluated branch-free per step (one measured best: the loop
+            // waits on the z-change write-backs, not on arithmetic), and the current pair of z
+            // entries stays in registers until z changes.
             const int k = tid;
             const int len = cnt[h];
             const bool kin = k <= sh_kmax;
