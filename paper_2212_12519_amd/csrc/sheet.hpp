@@ -31,16 +31,17 @@
 namespace ppmi {
 
 constexpr int kSheetBlock = 256;
-constexpr int kRunMin = 8;
+constexpr int kRunMin = 4;
 constexpr int kSheetMaxW = 128;  // largest axis-2 size with an LDS sheet
 constexpr int kSheetGroups = 8;  // groups of 256 rays per workgroup (a sheet persists across them)
 constexpr int kSheetUnroll = 1;  // rays evaluated together in the sheet loop
+constexpr int kNoEntry = -(1 << 30);  // "no z entry cached": no ray's floor(W) comes near it
 
 // LDS layout of k_back_runs (bytes): per-ray arrays, then the column buffer.
 struct SheetLayout {
     static constexpr int kDoubles = 6;  // W0 dW s0 ds U0 dU
-    static constexpr int kWords = 6;    // cv, lohi, pax, start, cnt, list; plus 16 words of masks/counts
-    static size_t ray_bytes() { return (size_t)kSheetBlock * (kDoubles * 8 + kWords * 4) + 16 * 4; }
+    static constexpr int kWords = 7;    // cv, lohi, pax, start, cnt, list, touched planes; + 24 words
+    static size_t ray_bytes() { return (size_t)kSheetBlock * (kDoubles * 8 + kWords * 4) + 24 * 4; }
     // column stride: the longest line a sheet can hold (planes along axis 0 or 1, at most one
     // per thread) + 1; sized to the grid so that two workgroups share a CU's LDS on the
     // clinical grid (215 planes, 71 z entries: 79.8 KB)
@@ -114,30 +115,45 @@ __device__ __forceinline__ void col_add(float* col, int j, int k, float a, float
     }
 }
 
-// Flush the sheet (planes kmin..kmax of line (p, U0, dU)) with contiguous atomics and clear it.
+// Flush the sheet of line (p, U0, dU) with contiguous atomics and clear it: only the planes
+// whose thread accumulated something (touched), listed in tl[], and with the (plane, z)
+// entries spread over all threads (consecutive threads take consecutive z of a plane).
+// Every thread of the workgroup calls it; the caller synchronises before and after.
 __device__ __forceinline__ void sheet_flush(float* __restrict__ img, float* col, const GeomK& g, int p, double U0,
-                                            double dU, int kmin, int kmax, int nw, int cs) {
+                                            double dU, bool touched, int nw, int cs, int* tl) {
     constexpr int B = kSheetBlock;
-    const int lane = (int)__lane_id();
-    const int wave = threadIdx.x >> 6;
+    const int tid = threadIdx.x, lane = (int)__lane_id(), wave = tid >> 6;
+    const unsigned long long bal = __ballot(touched);
+    if (lane == 0) tl[B + wave] = __popcll(bal);
+    __syncthreads();
+    int off = 0, nt = 0;
+    for (int w = 0; w < B / 64; ++w) {
+        const int c = tl[B + w];
+        off += (w < wave) ? c : 0;
+        nt += c;
+    }
+    if (touched) tl[off + __popcll(bal & ((1ull << lane) - 1ull))] = tid;
+    __syncthreads();
     const int su = (p == 0) ? g.stride[1] : g.stride[0];
     const int sp = g.stride[p];
     const int nu = (p == 0) ? g.n[1] : g.n[0];
-    for (int k = kmin + wave; k <= kmax; k += B / 64) {
-        const double U = fma((double)k, dU, U0);
-        const double fi = floor(U);
-        const int i0 = (int)fi;
-        const float fu = (float)(U - fi);
-        const bool ok0 = (unsigned)i0 < (unsigned)nu, ok1 = (unsigned)(i0 + 1) < (unsigned)nu;
-        const int base = k * sp + i0 * su;
-        for (int j = lane; j < nw; j += 64) {
-            float* cp = col + j * cs + k;
-            const float v = *cp;
-            if (v != 0.0f) {
-                *cp = 0.0f;
-                if (ok0) unsafeAtomicAdd(img + base + j, (1.0f - fu) * v);
-                if (ok1) unsafeAtomicAdd(img + base + su + j, fu * v);
-            }
+    const int total = nt * nw;
+    const float inv_nw = 1.0f / (float)nw;
+    for (int e = tid; e < total; e += B) {
+        // e / nw: (e + 1/2) / nw stays >= 1/(2 nw) away from an integer, far above float error
+        const int pi = (int)(((float)e + 0.5f) * inv_nw), j = e - pi * nw;
+        const int k = tl[pi];
+        float* cp = col + j * cs + k;
+        const float v = *cp;
+        if (v != 0.0f) {
+            *cp = 0.0f;
+            const double U = fma((double)k, dU, U0);
+            const double fi = floor(U);
+            const int i0 = (int)fi;
+            const float fu = (float)(U - fi);
+            const int base = k * sp + i0 * su;
+            if ((unsigned)i0 < (unsigned)nu) unsafeAtomicAdd(img + base + j, (1.0f - fu) * v);
+            if ((unsigned)(i0 + 1) < (unsigned)nu) unsafeAtomicAdd(img + base + su + j, fu * v);
         }
     }
 }
@@ -164,7 +180,8 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
     int* cnt = start + B;
     int* masks = cnt + B;  // 8 words: run-boundary ballots of the 4 waves
     int* list = masks + 8;  // sheet-run heads; count at list[B]; per-wave counts at list[B + 4 ..]
-    float* col = reinterpret_cast<float*>(list + B + 8);  // [nw][cs]
+    int* tl = list + B + 8;  // flush: touched planes, per-wave counts at tl[B ..]
+    float* col = reinterpret_cast<float*>(tl + B + 8);  // [nw][cs]
     const int cs = SheetLayout::col_stride(g);
 
     const int tid = threadIdx.x;
@@ -175,8 +192,8 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
     if (sheets)
         for (int q = tid; q < nw * cs; q += B) col[q] = 0.0f;
     // current sheet (block-uniform copies in registers, updated after barriers)
-    bool sh_on = false;
-    int sh_p = -1, sh_kmin = 0, sh_kmax = -1;
+    bool sh_on = false, touched = false;  // touched: this thread's plane holds sheet values
+    int sh_p = -1, sh_kmax = -1;
     double sh_U0 = 0.0, sh_dU = 0.0;
     for (int grp = 0; grp < groups; ++grp) {
         const int64_t i = chunk0 + (int64_t)grp * B + tid;
@@ -302,7 +319,8 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
             const int h = list[li];
             const bool same_line = sh_on && pax[h] == sh_p && U0[h] == sh_U0 && dU[h] == sh_dU;
             if (sh_on && !same_line) {
-                sheet_flush(img, col, g, sh_p, sh_U0, sh_dU, sh_kmin, sh_kmax, nw, cs);
+                sheet_flush(img, col, g, sh_p, sh_U0, sh_dU, touched, nw, cs, tl);
+                touched = false;
                 __syncthreads();
                 sh_on = false;
             }
@@ -311,7 +329,6 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
                 sh_p = pax[h];
                 sh_U0 = U0[h];
                 sh_dU = dU[h];
-                sh_kmin = 0;
                 sh_kmax = g.n[sh_p] - 1;
             }
             // thread tid accumulates the column of absolute plane k = tid.  Each wave loads 64 of
@@ -322,7 +339,7 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
             const int k = tid;
             const int len = cnt[h];
             const bool kin = k <= sh_kmax;
-            int jc = -2;
+            int jc = kNoEntry;
             float accA = 0.0f, accB = 0.0f;
             for (int b0 = h; b0 < h + len; b0 += 64) {
                 const int nb = min(64, h + len - b0);
@@ -389,10 +406,11 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
                 }
             }
             col_add<Mode::kColAtomic>(col, jc, k, accA, accB, nw, cs);
+            touched = touched || jc != kNoEntry;  // jc may be an out-of-grid entry after writes
             __syncthreads();
         }
     }
-    if (sh_on) sheet_flush(img, col, g, sh_p, sh_U0, sh_dU, sh_kmin, sh_kmax, nw, cs);
+    if (sh_on) sheet_flush(img, col, g, sh_p, sh_U0, sh_dU, touched, nw, cs, tl);
     __syncthreads();  // the LDS may be reused by the caller
 }
 
