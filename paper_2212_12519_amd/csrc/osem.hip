@@ -44,7 +44,6 @@ __host__ __device__ inline int64_t slot_chunks(int64_t n_events, int32_t n_sub) 
 // ell / ybar times the TOF weight (sample) -- the run/sheet back projection of sheet.hpp.
 template <bool Lut>
 struct ModeOsem {
-    static constexpr bool kColAtomic = false;
     const float* __restrict__ x;
     const int16_t* __restrict__ bins;
     float bg;

@@ -58,7 +58,6 @@ struct SheetLayout {
 //   sample(x, cv):   the value scattered at the plane sample with TOF coordinate
 //                    x = fma(k, r.ds, r.s0)
 struct ModeNonTof {
-    static constexpr bool kColAtomic = false;
     const float* __restrict__ p;
     __device__ bool setup(int64_t l, const float* xs, const float* xe, const GeomK& g, RayK& r, float& cv) const {
         const float pl = p[l];
@@ -71,7 +70,6 @@ struct ModeNonTof {
 
 template <bool Lut>
 struct ModeTofLm {
-    static constexpr bool kColAtomic = false;
     const float* __restrict__ p;
     const int16_t* __restrict__ bins;
     TofK t;
@@ -94,25 +92,12 @@ __device__ __forceinline__ double bcast(double v, int src) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// col[j][k] += a, col[j + 1][k] += b for the in-range entries (thread-private column k).
-// Atomic: LDS adds without return (no wait for the old value); else a read-modify-write.
-// LDS float atomics run at ~0.2 T adds/s on this GPU against ~2.7 T/s for read-modify-write
-// of thread-private words, so every mode uses the read-modify-write now that two workgroups
-// per CU hide its latency.
-template <bool Atomic>
+// col[j][k] += a, col[j + 1][k] += b for the in-range entries (thread-private column k), by
+// read-modify-write: LDS float atomics run at ~0.2 T adds/s on this GPU against ~2.7 T/s
+// for read-modify-write of thread-private words.
 __device__ __forceinline__ void col_add(float* col, int j, int k, float a, float b, int nw, int cs) {
-    if ((unsigned)j < (unsigned)nw && a != 0.0f) {
-        if (Atomic)
-            __hip_atomic_fetch_add(col + j * cs + k, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        else
-            col[j * cs + k] += a;
-    }
-    if ((unsigned)(j + 1) < (unsigned)nw && b != 0.0f) {
-        if (Atomic)
-            __hip_atomic_fetch_add(col + (j + 1) * cs + k, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        else
-            col[(j + 1) * cs + k] += b;
-    }
+    if ((unsigned)j < (unsigned)nw && a != 0.0f) col[j * cs + k] += a;
+    if ((unsigned)(j + 1) < (unsigned)nw && b != 0.0f) col[(j + 1) * cs + k] += b;
 }
 
 // Flush the sheet of line (p, U0, dU) with contiguous atomics and clear it: only the planes
@@ -394,7 +379,7 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
 #pragma unroll
                         for (int u = 0; u < kSheetUnroll; ++u) {
                             if (vv[u] != 0.0f && j0v[u] != jc) {
-                                col_add<Mode::kColAtomic>(col, jc, k, accA, accB, nw, cs);
+                                col_add(col, jc, k, accA, accB, nw, cs);
                                 jc = j0v[u];
                                 accA = 0.0f;
                                 accB = 0.0f;
@@ -405,7 +390,7 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
                     }
                 }
             }
-            col_add<Mode::kColAtomic>(col, jc, k, accA, accB, nw, cs);
+            col_add(col, jc, k, accA, accB, nw, cs);
             touched = touched || jc != kNoEntry;  // jc may be an out-of-grid entry after writes
             __syncthreads();
         }
