@@ -44,11 +44,13 @@ __host__ __device__ inline int64_t slot_chunks(int64_t n_events, int32_t n_sub) 
 // ell / ybar times the TOF weight (sample) -- the run/sheet back projection of sheet.hpp.
 template <bool Lut>
 struct ModeOsem {
+    static constexpr bool kAux = false;
     const float* __restrict__ x;
     const int16_t* __restrict__ bins;
     float bg;
     TofK t;
-    __device__ bool setup(int64_t l, const float* xs, const float* xe, const GeomK& g, RayK& r, float& cv) const {
+    __device__ bool setup(int64_t l, const float* xs, const float* xe, const GeomK& g, RayK& r, float& cv,
+                          int& /*aux*/) const {
         const int b = bins[l];
         if (b < 0 || b >= t.nb || !ray_setup(xs + 3 * l, xe + 3 * l, g, r)) return false;
         if (!tof_window_rel(r, t.c0 + b * t.bw, t)) return false;
@@ -62,7 +64,7 @@ struct ModeOsem {
         cv = r.ell / ybar;
         return true;
     }
-    __device__ float sample(double x, float cv) const { return tof_weight<Lut>(x, t) * cv; }
+    __device__ float sample(double x, float cv, int /*aux*/) const { return tof_weight<Lut>(x, t) * cv; }
 };
 
 template <bool Lut>

@@ -261,6 +261,11 @@ hipError_t launch_fwd_tof_sino(const float* xs, const float* xe, int64_t n, cons
 
 hipError_t launch_back_tof_sino(const float* xs, const float* xe, int64_t n, const GeomK& g, const TofK& t,
                                 float* img, const float* p, hipStream_t s) {
+    // the run/sheet kernel carries ray indices in 32 bits
+    if (n < (int64_t(1) << 31)) {
+        if (t.lut) return launch_runs(ModeTofSino<true>{p, t}, xs, xe, n, g, img, nullptr, s);
+        return launch_runs(ModeTofSino<false>{p, t}, xs, xe, n, g, img, nullptr, s);
+    }
     const int blk = sino_block(t.nb);
     const size_t lds = (size_t)t.nb * blk * sizeof(float);
     hipLaunchKernelGGL(k_back_tof_sino, dim3(grid_for(n, blk)), dim3(blk), lds, s, xs, xe, n, g, t, img, p);

@@ -19,9 +19,10 @@
 // waves flush the sheet with contiguous, duplicate-free atomics -- one memory
 // request per ~16 values instead of one per value.  The column stride is the
 // grid's longest line + 1, so that two workgroups fit a CU's LDS on clinical
-// grids: the loop is latency-bound and needs the second workgroup's waves.  The u-weights (1 - fu, fu) are shared by the
-// run and applied at the flush.  Rays in short runs (or with p == 2, or grids
-// whose axis 2 exceeds the LDS column) take the direct wave-synchronous,
+// grids: the loop is latency-bound and needs the second workgroup's waves.  The
+// u-weights (1 - fu, fu) are shared by the run and applied at the flush.  Rays
+// in short runs (or with p == 2, or grids whose axis 2 exceeds the LDS column)
+// take the direct wave-synchronous,
 // run-combined scatter.  The arithmetic per (ray, plane) sample is the same
 // as in the direct path; only the order of float additions differs.
 #pragma once
@@ -40,7 +41,7 @@ constexpr int kNoEntry = -(1 << 30);  // "no z entry cached": no ray's floor(W) 
 // LDS layout of k_back_runs (bytes): per-ray arrays, then the column buffer.
 struct SheetLayout {
     static constexpr int kDoubles = 6;  // W0 dW s0 ds U0 dU
-    static constexpr int kWords = 7;    // cv, lohi, pax, start, cnt, list, touched planes; + 24 words
+    static constexpr int kWords = 7;    // cv, lohi, pax, start, cnt, list, aux; + 24 words
     static size_t ray_bytes() { return (size_t)kSheetBlock * (kDoubles * 8 + kWords * 4) + 24 * 4; }
     // column stride: the longest line a sheet can hold (planes along axis 0 or 1, at most one
     // per thread) + 1; sized to the grid so that two workgroups share a CU's LDS on the
@@ -53,27 +54,32 @@ struct SheetLayout {
 };
 
 // Per-ray value hooks:
-//   setup(l, r, cv): prepare ray l (false = no contribution); cv = ell * p (the constant
-//                    factor of every sample); for TOF, r.s0 is made relative to the bin centre
-//   sample(x, cv):   the value scattered at the plane sample with TOF coordinate
+//   setup(l, r, cv, aux): prepare ray l (false = no contribution); cv = ell * p (the constant
+//                    factor of every sample); for listmode TOF, r.s0 is made relative to the bin
+//                    centre; aux: a per-ray word the mode keeps (kAux)
+//   sample(x, cv, aux): the value scattered at the plane sample with TOF coordinate
 //                    x = fma(k, r.ds, r.s0)
 struct ModeNonTof {
+    static constexpr bool kAux = false;
     const float* __restrict__ p;
-    __device__ bool setup(int64_t l, const float* xs, const float* xe, const GeomK& g, RayK& r, float& cv) const {
+    __device__ bool setup(int64_t l, const float* xs, const float* xe, const GeomK& g, RayK& r, float& cv,
+                          int& /*aux*/) const {
         const float pl = p[l];
         if (pl == 0.0f || !ray_setup(xs + 3 * l, xe + 3 * l, g, r)) return false;
         cv = r.ell * pl;
         return true;
     }
-    __device__ float sample(double /*x*/, float cv) const { return cv; }
+    __device__ float sample(double /*x*/, float cv, int /*aux*/) const { return cv; }
 };
 
 template <bool Lut>
 struct ModeTofLm {
+    static constexpr bool kAux = false;
     const float* __restrict__ p;
     const int16_t* __restrict__ bins;
     TofK t;
-    __device__ bool setup(int64_t l, const float* xs, const float* xe, const GeomK& g, RayK& r, float& cv) const {
+    __device__ bool setup(int64_t l, const float* xs, const float* xe, const GeomK& g, RayK& r, float& cv,
+                          int& /*aux*/) const {
         const int b = bins[l];
         const float pl = p[l];
         if (b < 0 || b >= t.nb || pl == 0.0f || !ray_setup(xs + 3 * l, xe + 3 * l, g, r)) return false;
@@ -81,7 +87,46 @@ struct ModeTofLm {
         cv = r.ell * pl;
         return true;
     }
-    __device__ float sample(double x, float cv) const { return tof_weight<Lut>(x, t) * cv; }
+    __device__ float sample(double x, float cv, int /*aux*/) const { return tof_weight<Lut>(x, t) * cv; }
+};
+
+// Sinogram TOF: the value at a plane sample is ell * sum over the bins b of its TOF window of
+// w_b(s) p[l][b] (neighbouring bins share their erf edge).  aux carries the ray index l (the
+// sheet path is used for fewer than 2^31 rays); all lanes of a wave read the same ray's bin
+// values, so those loads hit one or two cache lines.
+template <bool Lut>
+struct ModeTofSino {
+    static constexpr bool kAux = true;
+    const float* __restrict__ p;  // [n][n_bins]
+    TofK t;
+    __device__ bool setup(int64_t l, const float* xs, const float* xe, const GeomK& g, RayK& r, float& cv,
+                          int& aux) const {
+        const float* pr = p + l * t.nb;
+        bool any = false;
+        for (int b = 0; b < t.nb; ++b) any |= (pr[b] != 0.0f);
+        if (!any || !ray_setup(xs + 3 * l, xe + 3 * l, g, r)) return false;
+        cv = r.ell;
+        aux = (int)l;
+        return true;
+    }
+    __device__ float sample(double s, float cv, int aux) const {
+        const float* pr = p + (int64_t)aux * t.nb;
+        int b_lo, b_hi;
+        tof_bin_range(s, t, b_lo, b_hi);
+        float c = 0.0f;
+        if (Lut) {
+            for (int b = b_lo; b <= b_hi; ++b) c += tof_lut(s - (t.c0 + b * t.bw), t) * pr[b];
+        } else {
+            const float x_hi0 = (float)(s - (t.c0 + b_lo * t.bw) + 0.5 * t.bw), bwf = (float)t.bw;
+            float e_hi = tof_erf(x_hi0, t);
+            for (int b = b_lo; b <= b_hi; ++b) {
+                const float e_lo = tof_erf(x_hi0 - (float)(b - b_lo + 1) * bwf, t);
+                c += 0.5f * (e_hi - e_lo) * pr[b];
+                e_hi = e_lo;
+            }
+        }
+        return c * cv;
+    }
 };
 
 // Broadcast lane `src` (wave-uniform) of a double to the whole wave through scalar registers.
@@ -105,15 +150,15 @@ __device__ __forceinline__ void col_add(float* col, int j, int k, float a, float
 // entries spread over all threads (consecutive threads take consecutive z of a plane).
 // Every thread of the workgroup calls it; the caller synchronises before and after.
 __device__ __forceinline__ void sheet_flush(float* __restrict__ img, float* col, const GeomK& g, int p, double U0,
-                                            double dU, bool touched, int nw, int cs, int* tl) {
+                                            double dU, bool touched, int nw, int cs, int* tl, int* tcount) {
     constexpr int B = kSheetBlock;
     const int tid = threadIdx.x, lane = (int)__lane_id(), wave = tid >> 6;
     const unsigned long long bal = __ballot(touched);
-    if (lane == 0) tl[B + wave] = __popcll(bal);
+    if (lane == 0) tcount[wave] = __popcll(bal);
     __syncthreads();
     int off = 0, nt = 0;
     for (int w = 0; w < B / 64; ++w) {
-        const int c = tl[B + w];
+        const int c = tcount[w];
         off += (w < wave) ? c : 0;
         nt += c;
     }
@@ -165,8 +210,11 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
     int* cnt = start + B;
     int* masks = cnt + B;  // 8 words: run-boundary ballots of the 4 waves
     int* list = masks + 8;  // sheet-run heads; count at list[B]; per-wave counts at list[B + 4 ..]
-    int* tl = list + B + 8;  // flush: touched planes, per-wave counts at tl[B ..]
-    float* col = reinterpret_cast<float*>(tl + B + 8);  // [nw][cs]
+    int* aux = list + B + 8;  // per-ray word of the mode (sinogram TOF: the ray index)
+    // the flush's list of touched planes reuses start[] and masks[], which only the run
+    // detection before the sheet loop uses
+    int* tl = start;
+    float* col = reinterpret_cast<float*>(aux + B + 8);  // [nw][cs]
     const int cs = SheetLayout::col_stride(g);
 
     const int tid = threadIdx.x;
@@ -190,7 +238,8 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
         }
         RayK r;
         float cv = 0.0f;
-        const bool ok = l >= 0 && m.setup(l, xs, xe, g, r, cv);
+        int ax = 0;
+        const bool ok = l >= 0 && m.setup(l, xs, xe, g, r, cv, ax);
         // compact the valid rays to the front of the group (stable order), so that rays
         // without a contribution do not break runs
         const unsigned long long vb = __ballot(ok);
@@ -212,6 +261,7 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
             U0[cp] = r.U0;
             dU[cp] = r.dU;
             cvs[cp] = cv;
+            aux[cp] = ax;
             lohi[cp] = (r.k_lo & 0xffff) | (r.k_hi << 16);
             pax[cp] = r.p;
         }
@@ -293,7 +343,7 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
                 float v = 0.0f;
                 if (act) {
                     stn = stencil_at(r, k);
-                    v = m.sample(fma((double)k, r.ds, r.s0), cv);
+                    v = m.sample(fma((double)k, r.ds, r.s0), cv, ax);
                 }
                 wave_stencil_scatter(img, act && v != 0.0f, r, stn, v);
             }
@@ -304,7 +354,7 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
             const int h = list[li];
             const bool same_line = sh_on && pax[h] == sh_p && U0[h] == sh_U0 && dU[h] == sh_dU;
             if (sh_on && !same_line) {
-                sheet_flush(img, col, g, sh_p, sh_U0, sh_dU, touched, nw, cs, tl);
+                sheet_flush(img, col, g, sh_p, sh_U0, sh_dU, touched, nw, cs, tl, masks);
                 touched = false;
                 __syncthreads();
                 sh_on = false;
@@ -331,6 +381,7 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
                 const int q = b0 + min(lane, nb - 1);
                 const double qW0 = W0[q], qdW = dW[q], qs0 = s0[q], qds = ds[q];
                 const int qcv = __float_as_int(cvs[q]);
+                const int qax = aux[q];
                 const int qlh = lohi[q];
                 // rays whose plane window meets this wave's 64 planes (wave-uniform bit mask)
                 const int kw0 = wave * 64, kw1 = min(kw0 + 63, sh_kmax);
@@ -360,7 +411,8 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
                         j0v[u] = (int)fj;
                         fwv[u] = (float)(W - fj);
                         const float v = m.sample(fma((double)k, bcast(qds, ru[u]), bcast(qs0, ru[u])),
-                                                 __int_as_float(__builtin_amdgcn_readlane(qcv, ru[u])));
+                                                 __int_as_float(__builtin_amdgcn_readlane(qcv, ru[u])),
+                                                 Mode::kAux ? __builtin_amdgcn_readlane(qax, ru[u]) : 0);
                         vv[u] = act ? v : 0.0f;
                     }
                     // then accumulate: the pair of z entries stays in registers until z changes.
@@ -395,7 +447,7 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
             __syncthreads();
         }
     }
-    if (sh_on) sheet_flush(img, col, g, sh_p, sh_U0, sh_dU, touched, nw, cs, tl);
+    if (sh_on) sheet_flush(img, col, g, sh_p, sh_U0, sh_dU, touched, nw, cs, tl, masks);
     __syncthreads();  // the LDS may be reused by the caller
 }
 
