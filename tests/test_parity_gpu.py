@@ -353,3 +353,62 @@ def test_presort_order(gpu, lm40):
     ref = oracle.back(xs[:m].cpu().numpy(), xe[:m].cpu().numpy(), g["origin"], g["voxsize"], g["dim"],
                       y.cpu().numpy())
     assert rel_l2(np64(bm), ref) <= BACK_TOL
+
+
+SHEET_GRIDS = [
+    ((300, 40, 16), (1.0, 2.0, 2.0)),  # lines along axis 0 longer than 256 planes: direct path
+    ((30, 20, 200), (2.0, 2.0, 0.5)),  # axis 2 longer than the LDS column: direct path only
+    ((64, 48, 7), (1.5, 2.0, 2.0)),    # ordinary sheets, short lines
+]
+
+
+@pytest.mark.parametrize("gi", range(len(SHEET_GRIDS)))
+def test_run_sheet_paths_on_grid_shapes(gpu, gi):
+    """Ray lists made of long runs on few transaxial lines (the sheet path's input) on grids that
+    switch the sheet path off for some or all lines, or stretch its column stride to the clamp:
+    back projections of every variant against the oracle, in list order and presorted."""
+    dim, vs = SHEET_GRIDS[gi]
+    G = gpu.ImageGeom(dim, vs)
+    origin = G.origin
+    rng = np.random.default_rng(320 + gi)
+    ext = np.array(dim) * np.array(vs)
+    R = 0.75 * float(np.hypot(ext[0], ext[1])) + 5.0
+    xs_l, xe_l = [], []
+    for _ in range(40):  # 40 lines x 96 rays with random axial endpoints
+        phi = rng.uniform(0, np.pi)
+        off = rng.uniform(-0.3, 0.3) * min(ext[0], ext[1])
+        c, s_ = np.cos(phi), np.sin(phi)
+        p0 = np.array([-R * c - off * s_, -R * s_ + off * c])
+        p1 = np.array([R * c - off * s_, R * s_ + off * c])
+        z = rng.uniform(-0.5 * ext[2], 0.5 * ext[2], size=(96, 2))
+        xs_l.append(np.column_stack([np.full(96, p0[0]), np.full(96, p0[1]), z[:, 0]]))
+        xe_l.append(np.column_stack([np.full(96, p1[0]), np.full(96, p1[1]), z[:, 1]]))
+    xs = np.concatenate(xs_l).astype(np.float32)
+    xe = np.concatenate(xe_l).astype(np.float32)
+    n = xs.shape[0]
+    tof = tofd(6.0, 5.0, 3.0, 11)
+    T = gpu.TofParams(tof["bin_width"], tof["sigma"], tof["n_sigmas"], tof["n_bins"])
+    bins = rng.integers(0, 11, size=n).astype(np.int16)
+    y = rng.uniform(0, 1, size=n).astype(np.float32)
+    yt = rng.uniform(0, 1, size=(n, 11)).astype(np.float32)
+    d = torch.device("cuda")
+    xs_d, xe_d, b_d = torch.from_numpy(xs).to(d), torch.from_numpy(xe).to(d), torch.from_numpy(bins).to(d)
+    y_d, yt_d = torch.from_numpy(y).to(d), torch.from_numpy(yt).to(d)
+    ref = {
+        "back": oracle.back(xs, xe, origin, vs, dim, y),
+        "back_lm": oracle.back_tof_lm(xs, xe, origin, vs, dim, tof, bins, y),
+        "back_sino": oracle.back_tof_sino(xs, xe, origin, vs, dim, tof, yt),
+    }
+    order = gpu.presort(xs_d, xe_d, G, b_d, T)
+    got = {
+        "back": gpu.back(xs_d, xe_d, G, y_d),
+        "back_lm": gpu.back_tof_lm(xs_d, xe_d, b_d, G, T, y_d),
+        "back_sino": gpu.back_tof_sino(xs_d, xe_d, G, T, yt_d),
+        "back_lm_sorted": gpu.back_tof_lm(xs_d, xe_d, b_d, G, T, y_d, order=order),
+    }
+    torch.cuda.synchronize()
+    for k, v in got.items():
+        assert rel_l2(np64(v), ref[k.replace("_sorted", "")]) <= BACK_TOL, k
+    p = gpu.fwd_tof_lm(xs_d, xe_d, b_d, G, T, torch.ones(dim, device=d), order=order)
+    p_ref = oracle.fwd_tof_lm(xs, xe, origin, vs, dim, tof, bins, np.ones(dim))
+    assert rel_l2(np64(p), p_ref) <= FWD_TOL
