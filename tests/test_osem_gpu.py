@@ -122,3 +122,37 @@ def test_graph_replay_matches_eager(gpu, clin_frames):
         for i in range(2):
             assert rel_l2(np64(x_g[i]), np64(x_e[i])) <= OSEM_TOL, (rep, i)
         _ = (x_e[0] * 2.0).sum().item()  # eager work between replays
+
+
+@pytest.mark.parametrize("n_ev,n_sub", [(7, 8), (1000, 1), (257, 3)])
+def test_osem_edge_sizes_match_oracle(gpu, small_osem, n_ev, n_sub):
+    """Frames with fewer events than subsets (empty subsets), a single subset, and ragged
+    subset sizes, in one slot table with an empty slot between live ones."""
+    from paper_2212_12519_amd import osem
+
+    xs, xe, bins, lxs, lxe = small_osem
+    g = geom_of(C.GRID_SMALL)
+    tof = tof_of(C.TOF_CLIN)
+    G = gpu.ImageGeom(g["dim"], g["voxsize"], g["origin"])
+    T = gpu.TofParams(tof["bin_width"], tof["sigma"], tof["n_sigmas"], tof["n_bins"])
+    d = torch.device("cuda")
+    sens = osem.sensitivity(lxs.to(d), lxe.to(d), G)
+    sens_ref = oracle.back(lxs.numpy(), lxe.numpy(), g["origin"], g["voxsize"], g["dim"], np.ones(lxs.shape[0]))
+    frames = [(xs[:n_ev], xe[:n_ev], bins[:n_ev]), (xs[5000:5000 + 2 * n_ev], xe[5000:5000 + 2 * n_ev],
+                                                      bins[5000:5000 + 2 * n_ev])]
+    table = osem.SlotTable(3, d)
+    imgs, keep = [], []
+    for slot, (a, b, c) in zip((0, 2), frames):
+        prep = osem.prepare_frame(a.to(d).contiguous(), b.to(d).contiguous(), c.to(d).contiguous(), G, T, n_sub)
+        x = osem.init_image(sens)
+        acc = torch.zeros_like(sens)
+        table.set(slot, *prep, x, acc, sens, n_sub, 2 * n_sub, 0.1)
+        imgs.append(x)
+        keep.append((prep, acc))
+    table.upload()
+    osem.osem_steps(table, G, T, 2 * n_sub)
+    torch.cuda.synchronize()
+    for x, (a, b, c) in zip(imgs, frames):
+        x_ref = oracle.lm_osem(a.numpy(), b.numpy(), c.numpy(), g["origin"], g["voxsize"], g["dim"], tof, sens_ref,
+                               0.1, 2, n_sub, (sens_ref > 0).astype(np.float64))
+        assert rel_l2(np64(x), x_ref) <= OSEM_TOL
