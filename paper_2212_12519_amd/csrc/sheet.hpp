@@ -32,7 +32,7 @@
 namespace ppmi {
 
 constexpr int kSheetBlock = 256;
-constexpr int kRunMin = 4;
+constexpr int kRunMin = 2;
 constexpr int kSheetMaxW = 128;  // largest axis-2 size with an LDS sheet
 constexpr int kSheetGroups = 8;  // groups of 256 rays per workgroup (a sheet persists across them)
 constexpr int kSheetUnroll = 1;  // rays evaluated together in the sheet loop
