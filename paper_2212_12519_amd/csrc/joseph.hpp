@@ -302,12 +302,4 @@ __device__ __forceinline__ int wave_max(int v) {
     return v;
 }
 
-// XCD-aware block order: hardware hands consecutive workgroups to the 8 XCDs
-// in turn; remap so that each XCD walks one contiguous eighth of the work
-// list, keeping neighbouring rays (which share image voxels) in one L2.
-__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
-    const unsigned x = b & 7u, q = nb >> 3, rem = nb & 7u;
-    return x * q + min(x, rem) + (b >> 3);
-}
-
 }  // namespace ppmi

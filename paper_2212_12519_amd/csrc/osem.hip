@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(kSheetBlock) k_osem_accumulate(const pp_osem_s
     extern __shared__ double smem[];
     const pp_osem_slot_t& last = slots[n_slots - 1];
     const int64_t total = last.chunk_begin + (last.active ? slot_chunks(last.n_events, last.n_sub) : 0);
-    for (int64_t c = xcd_block(blockIdx.x, gridDim.x); c < total; c += gridDim.x) {
+    for (int64_t c = blockIdx.x; c < total; c += gridDim.x) {
         // largest slot index whose first chunk is <= c (block-uniform)
         int lo_s = 0, hi_s = n_slots - 1;
         while (lo_s < hi_s) {

@@ -1,6 +1,6 @@
 // Joseph forward / back projection kernels for gfx950 (non-TOF, TOF sinogram,
-// TOF listmode).  One thread per ray; 256-thread workgroups (4 wave64s);
-// XCD-aware workgroup order.  See joseph.hpp for the traversal itself.
+// TOF listmode).  One thread per ray; 256-thread workgroups (4 wave64s) in
+// plain workgroup order.  See joseph.hpp for the traversal itself.
 #include <hip/hip_runtime.h>
 
 #include "joseph.hpp"
@@ -17,7 +17,7 @@ constexpr int kBlock = 256;
 // or a permutation such as the one pp_lm_presort produces).  Entries outside
 // [0, n) are skipped.
 __device__ __forceinline__ int64_t ray_index(const int32_t* __restrict__ order, int64_t n) {
-    const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return -1;
     if (!order) return i;
     const int64_t l = order[i];
@@ -75,7 +75,7 @@ __global__ void k_fwd_tof_sino(const float* __restrict__ xs, const float* __rest
                                TofK t, const float* __restrict__ img, float* __restrict__ p) {
     extern __shared__ float lds[];  // [nb][blockDim]
     const int nt = blockDim.x;
-    const int64_t l0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * nt;
+    const int64_t l0 = (int64_t)blockIdx.x * nt;
     const int64_t l = l0 + threadIdx.x;
     for (int b = 0; b < t.nb; ++b) lds[b * nt + threadIdx.x] = 0.0f;
     RayK r;
@@ -117,7 +117,7 @@ __global__ void k_back_tof_sino(const float* __restrict__ xs, const float* __res
                                 TofK t, float* __restrict__ img, const float* __restrict__ p) {
     extern __shared__ float lds[];  // [nb][blockDim]: the block's projection tile, transposed
     const int nt = blockDim.x;
-    const int64_t l0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * nt;
+    const int64_t l0 = (int64_t)blockIdx.x * nt;
     const int64_t l = l0 + threadIdx.x;
     const int64_t nrays = (n - l0 < nt) ? (n - l0) : nt;
     const int64_t total = nrays * t.nb;
@@ -173,7 +173,7 @@ __global__ void k_back_tof_sino(const float* __restrict__ xs, const float* __res
 __global__ void __launch_bounds__(kBlock) k_count(const float* __restrict__ xs, const float* __restrict__ xe,
                                                   const int16_t* __restrict__ bins, int64_t n, GeomK g, TofK t,
                                                   int32_t* __restrict__ counts) {
-    const int64_t l = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int64_t l = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (l >= n) return;
     int cnt = 0;
     RayK r;

@@ -457,7 +457,7 @@ __global__ void __launch_bounds__(kSheetBlock) k_back_runs(Mode m, const float* 
                                                           float* __restrict__ img, const int32_t* __restrict__ order,
                                                           int nw_lds, int groups) {
     extern __shared__ double smem[];
-    const int64_t chunk0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * groups * kSheetBlock;
+    const int64_t chunk0 = (int64_t)blockIdx.x * groups * kSheetBlock;
     back_runs_chunk(m, xs, xe, n, g, img, order, nw_lds, groups, chunk0, smem);
 }
 
