@@ -47,7 +47,7 @@ def _load():
     F = ctypes.c_float
     I32 = ctypes.c_int32
     geo = [P, P, I64, P, P, P]
-    tof = [F, F, F, F, I32, P, I32, ctypes.c_double, ctypes.c_double]
+    tof = [F, F, F, F, I32, P, I32, ctypes.c_double, ctypes.c_double, P, P]
     lib.orc_fwd.argtypes = geo + [P, P]
     lib.orc_back.argtypes = geo + [P, P]
     lib.orc_fwd_tof_sino.argtypes = geo + tof + [P, P]
@@ -81,11 +81,20 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def _tofargs(tof):
+def _tofargs(tof, n=None):
     """tof: object/dict with bin_width, sigma, n_sigmas, n_bins, (center_offset) and, for a
-    tabulated kernel, lut (float32 array of the bin weight at lut_x0 + i * lut_dx), lut_x0, lut_dx.
-    The returned tuple keeps the table array alive for the call."""
+    tabulated kernel, lut (float32 array of the bin weight at lut_x0 + i * lut_dx), lut_x0, lut_dx;
+    optionally sigma_per_ray / offset_per_ray (float32 [n]: ray l's sigma / centre offset in place
+    of the scalar).  The returned tuple keeps the arrays alive for the call."""
     g = (lambda k, d=None: tof.get(k, d)) if isinstance(tof, dict) else (lambda k, d=None: getattr(tof, k, d))
+    per = []
+    for key in ("sigma_per_ray", "offset_per_ray"):
+        a = g(key)
+        if a is not None:
+            a = np.ascontiguousarray(np.asarray(a, dtype=np.float32).ravel())
+            if n is None or a.size != n:
+                raise ValueError(f"{key} needs one entry per ray")
+        per.append(a)
     lut = g("lut")
     if lut is not None:
         lut = np.ascontiguousarray(np.asarray(lut, dtype=np.float32).ravel())
@@ -96,11 +105,12 @@ def _tofargs(tof):
         lp, ln, x0, dx = None, 0, 0.0, 1.0
     return _TofArgs((ctypes.c_float(g("bin_width")), ctypes.c_float(g("sigma")), ctypes.c_float(g("n_sigmas")),
                      ctypes.c_float(g("center_offset", 0.0)), ctypes.c_int32(int(g("n_bins"))), lp,
-                     ctypes.c_int32(ln), ctypes.c_double(x0), ctypes.c_double(dx)), lut)
+                     ctypes.c_int32(ln), ctypes.c_double(x0), ctypes.c_double(dx),
+                     *[None if a is None else _ptr(a) for a in per]), (lut, per))
 
 
 class _TofArgs(tuple):
-    """The C arguments of a TOF kernel; holds a reference to the table array."""
+    """The C arguments of a TOF kernel; holds references to the arrays they point into."""
 
     def __new__(cls, args, keep):
         t = super().__new__(cls, args)
@@ -139,7 +149,7 @@ def fwd_tof_sino(xstart, xend, origin, voxsize, dim, tof, img):
     lib = _load()
     xs, xe = _f32(xstart, 3), _f32(xend, 3)
     o, h, d = _geom(origin, voxsize, dim)
-    ta = _tofargs(tof)
+    ta = _tofargs(tof, xs.shape[0])
     x = np.ascontiguousarray(np.asarray(img, dtype=np.float64).reshape(tuple(d)))
     out = np.zeros((xs.shape[0], ta[4].value), dtype=np.float64)
     lib.orc_fwd_tof_sino(_ptr(xs), _ptr(xe), xs.shape[0], _ptr(o), _ptr(h), _ptr(d), *ta, _ptr(x), _ptr(out))
@@ -150,7 +160,7 @@ def back_tof_sino(xstart, xend, origin, voxsize, dim, tof, p):
     lib = _load()
     xs, xe = _f32(xstart, 3), _f32(xend, 3)
     o, h, d = _geom(origin, voxsize, dim)
-    ta = _tofargs(tof)
+    ta = _tofargs(tof, xs.shape[0])
     y = np.ascontiguousarray(np.asarray(p, dtype=np.float64).reshape(xs.shape[0], ta[4].value))
     out = np.zeros(tuple(d), dtype=np.float64)
     lib.orc_back_tof_sino(_ptr(xs), _ptr(xe), xs.shape[0], _ptr(o), _ptr(h), _ptr(d), *ta, _ptr(out), _ptr(y))
@@ -167,7 +177,7 @@ def fwd_tof_lm(xstart, xend, origin, voxsize, dim, tof, bins, img):
     lib = _load()
     xs, xe = _f32(xstart, 3), _f32(xend, 3)
     o, h, d = _geom(origin, voxsize, dim)
-    ta = _tofargs(tof)
+    ta = _tofargs(tof, xs.shape[0])
     b = _bins(bins, xs.shape[0])
     x = np.ascontiguousarray(np.asarray(img, dtype=np.float64).reshape(tuple(d)))
     out = np.zeros(xs.shape[0], dtype=np.float64)
@@ -180,7 +190,7 @@ def back_tof_lm(xstart, xend, origin, voxsize, dim, tof, bins, p):
     lib = _load()
     xs, xe = _f32(xstart, 3), _f32(xend, 3)
     o, h, d = _geom(origin, voxsize, dim)
-    ta = _tofargs(tof)
+    ta = _tofargs(tof, xs.shape[0])
     b = _bins(bins, xs.shape[0])
     y = np.ascontiguousarray(np.asarray(p, dtype=np.float64).reshape(xs.shape[0]))
     out = np.zeros(tuple(d), dtype=np.float64)
@@ -194,7 +204,7 @@ def count_samples(xstart, xend, origin, voxsize, dim, tof=None, bins=None, per_r
     lib = _load()
     xs, xe = _f32(xstart, 3), _f32(xend, 3)
     o, h, d = _geom(origin, voxsize, dim)
-    ta = _tofargs(tof) if tof is not None else _tofargs({"bin_width": 1.0, "sigma": 1.0, "n_sigmas": 1.0,
+    ta = _tofargs(tof, xs.shape[0]) if tof is not None else _tofargs({"bin_width": 1.0, "sigma": 1.0, "n_sigmas": 1.0,
                                                           "n_bins": 1})
     b = _bins(bins, xs.shape[0]) if bins is not None else None
     pr = np.zeros(xs.shape[0], dtype=np.int64) if per_ray else None
@@ -231,7 +241,7 @@ def lm_osem(xstart, xend, bins, origin, voxsize, dim, tof, sens, bg, n_iter, n_s
     lib = _load()
     xs, xe = _f32(xstart, 3), _f32(xend, 3)
     o, h, d = _geom(origin, voxsize, dim)
-    ta = _tofargs(tof)
+    ta = _tofargs(tof, xs.shape[0])
     b = _bins(bins, xs.shape[0])
     s = np.ascontiguousarray(np.asarray(sens, dtype=np.float64).reshape(tuple(d)))
     x = np.array(np.asarray(x0, dtype=np.float64).reshape(tuple(d)), copy=True, order="C")

@@ -41,6 +41,12 @@
  *     signed distance x of the sample from the bin centre, at
  *     x_i = x0 + i dx (i = 0 .. n-1), linearly interpolated, 0 outside
  *     [x0, x_{n-1}]; sigma and n_sigmas are then unused;
+ *   - per-ray TOF parameters (a generalisation of the single kernel of
+ *     Sec. 2.2, where every LOR shares one Gaussian width and one bin-centre
+ *     convention): where an array of one sigma or one centre offset per ray
+ *     is given, ray l uses sigma[l] (with the same n_sigmas) or offset[l]
+ *     in place of the scalar; a ray whose sigma is not a positive finite
+ *     number, or whose offset is not finite, contributes nothing;
  *   - listmode bins outside [0, n_bins) and non-finite or zero-length LORs
  *     contribute nothing;
  *   - listmode OSEM: subset j holds the events with index e mod n_sub == j;
@@ -70,7 +76,10 @@ typedef struct {
     double sig;    /* Gaussian sigma, mm */
     double trunc;  /* n_sigmas * sigma, mm */
     double off;    /* centre offset, mm */
+    double nsig;   /* truncation in units of sigma */
     int nb;        /* number of bins */
+    const float* sig_l; /* sigma of each ray, or NULL (all rays: sig) */
+    const float* off_l; /* centre offset of each ray, or NULL (all rays: off) */
     const float* lut; /* tabulated bin weight w(x_i), or NULL (Gaussian) */
     int64_t lut_n;
     double lut_x0, lut_dx;
@@ -96,12 +105,15 @@ static grid64 mkgrid(const float* origin, const float* vs, const int32_t* dim) {
 }
 
 static tof64 mktof(float bw, float sig, float nsig, float off, int32_t nb, const float* lut, int32_t lut_n,
-                   double lut_x0, double lut_dx) {
+                   double lut_x0, double lut_dx, const float* sig_l, const float* off_l) {
     tof64 t;
     t.bw = bw;
     t.sig = sig;
+    t.nsig = nsig;
     t.trunc = (double)nsig * (double)sig;
     t.off = off;
+    t.sig_l = sig_l;
+    t.off_l = off_l;
     t.nb = nb;
     t.lut = lut;
     t.lut_n = lut_n;
@@ -110,7 +122,26 @@ static tof64 mktof(float bw, float sig, float nsig, float off, int32_t nb, const
     return t;
 }
 
-#define NOTOF(name) tof64 name = mktof(1.f, 1.f, 1.f, 0.f, 1, NULL, 0, 0.0, 1.0)
+#define NOTOF(name) tof64 name = mktof(1.f, 1.f, 1.f, 0.f, 1, NULL, 0, 0.0, 1.0, NULL, NULL)
+
+/* TOF parameters of ray l: its own sigma and centre offset where per-ray
+ * arrays are given.  Returns 0 if they are unusable (the ray contributes
+ * nothing). */
+static int ray_tof(const tof64* tf, int64_t l, tof64* out) {
+    *out = *tf;
+    if (tf->sig_l) {
+        double s = tf->sig_l[l];
+        if (!(s > 0.0) || !isfinite(s)) return 0;
+        out->sig = s;
+        out->trunc = tf->nsig * s;
+    }
+    if (tf->off_l) {
+        double o = tf->off_l[l];
+        if (!isfinite(o)) return 0;
+        out->off = o;
+    }
+    return 1;
+}
 
 static ray64 ray_setup(const float* xs, const float* xe, const grid64* g) {
     ray64 r;
@@ -290,8 +321,14 @@ static void forward_all(const float* xs, const float* xe, int64_t n, const grid6
                         const int16_t* bins, const double* img, double* p) {
     int nout = (mode == 1) ? tf->nb : 1;
 #pragma omp parallel for schedule(static)
-    for (int64_t l = 0; l < n; ++l)
-        ray_forward(xs + 3 * l, xe + 3 * l, g, tf, mode, bins ? bins[l] : 0, img, p + (int64_t)nout * l);
+    for (int64_t l = 0; l < n; ++l) {
+        tof64 tl;
+        if (!ray_tof(tf, l, &tl)) {
+            for (int q = 0; q < nout; ++q) p[(int64_t)nout * l + q] = 0.0;
+            continue;
+        }
+        ray_forward(xs + 3 * l, xe + 3 * l, g, &tl, mode, bins ? bins[l] : 0, img, p + (int64_t)nout * l);
+    }
 }
 
 /* events l with l % stride == phase only (stride 1: all) */
@@ -306,8 +343,11 @@ static void back_all(const float* xs, const float* xe, int64_t n, const grid64* 
     {
         double* mine = priv + (size_t)thread_id() * (size_t)nv;
 #pragma omp for schedule(static)
-        for (int64_t l = 0; l < n; ++l)
-            ray_back(xs + 3 * l, xe + 3 * l, g, tf, mode, bins ? bins[l] : 0, mine, p + (int64_t)nout * l);
+        for (int64_t l = 0; l < n; ++l) {
+            tof64 tl;
+            if (!ray_tof(tf, l, &tl)) continue;
+            ray_back(xs + 3 * l, xe + 3 * l, g, &tl, mode, bins ? bins[l] : 0, mine, p + (int64_t)nout * l);
+        }
     }
 #pragma omp parallel for schedule(static)
     for (int64_t v = 0; v < nv; ++v) {
@@ -339,36 +379,44 @@ void orc_back(const float* xs, const float* xe, int64_t n, const float* origin, 
 void orc_fwd_tof_sino(const float* xs, const float* xe, int64_t n, const float* origin, const float* vs,
                       const int32_t* dim, float bin_width, float sigma, float n_sigmas, float center_offset,
                       int32_t n_bins, const float* lut, int32_t lut_n, double lut_x0, double lut_dx,
+                      const float* sigma_per_ray, const float* offset_per_ray,
                       const double* img, double* p) {
     grid64 g = mkgrid(origin, vs, dim);
-    tof64 tf = mktof(bin_width, sigma, n_sigmas, center_offset, n_bins, lut, lut_n, lut_x0, lut_dx);
+    tof64 tf = mktof(bin_width, sigma, n_sigmas, center_offset, n_bins, lut, lut_n, lut_x0, lut_dx, sigma_per_ray,
+                     offset_per_ray);
     forward_all(xs, xe, n, &g, &tf, 1, NULL, img, p);
 }
 
 void orc_back_tof_sino(const float* xs, const float* xe, int64_t n, const float* origin, const float* vs,
                        const int32_t* dim, float bin_width, float sigma, float n_sigmas, float center_offset,
                        int32_t n_bins, const float* lut, int32_t lut_n, double lut_x0, double lut_dx,
+                       const float* sigma_per_ray, const float* offset_per_ray,
                        double* img, const double* p) {
     grid64 g = mkgrid(origin, vs, dim);
-    tof64 tf = mktof(bin_width, sigma, n_sigmas, center_offset, n_bins, lut, lut_n, lut_x0, lut_dx);
+    tof64 tf = mktof(bin_width, sigma, n_sigmas, center_offset, n_bins, lut, lut_n, lut_x0, lut_dx, sigma_per_ray,
+                     offset_per_ray);
     back_all(xs, xe, n, &g, &tf, 1, NULL, img, p);
 }
 
 void orc_fwd_tof_lm(const float* xs, const float* xe, int64_t n, const float* origin, const float* vs,
                     const int32_t* dim, float bin_width, float sigma, float n_sigmas, float center_offset,
                     int32_t n_bins, const float* lut, int32_t lut_n, double lut_x0, double lut_dx,
+                    const float* sigma_per_ray, const float* offset_per_ray,
                     const int16_t* bins, const double* img, double* p) {
     grid64 g = mkgrid(origin, vs, dim);
-    tof64 tf = mktof(bin_width, sigma, n_sigmas, center_offset, n_bins, lut, lut_n, lut_x0, lut_dx);
+    tof64 tf = mktof(bin_width, sigma, n_sigmas, center_offset, n_bins, lut, lut_n, lut_x0, lut_dx, sigma_per_ray,
+                     offset_per_ray);
     forward_all(xs, xe, n, &g, &tf, 2, bins, img, p);
 }
 
 void orc_back_tof_lm(const float* xs, const float* xe, int64_t n, const float* origin, const float* vs,
                      const int32_t* dim, float bin_width, float sigma, float n_sigmas, float center_offset,
                      int32_t n_bins, const float* lut, int32_t lut_n, double lut_x0, double lut_dx,
+                     const float* sigma_per_ray, const float* offset_per_ray,
                      const int16_t* bins, double* img, const double* p) {
     grid64 g = mkgrid(origin, vs, dim);
-    tof64 tf = mktof(bin_width, sigma, n_sigmas, center_offset, n_bins, lut, lut_n, lut_x0, lut_dx);
+    tof64 tf = mktof(bin_width, sigma, n_sigmas, center_offset, n_bins, lut, lut_n, lut_x0, lut_dx, sigma_per_ray,
+                     offset_per_ray);
     back_all(xs, xe, n, &g, &tf, 2, bins, img, p);
 }
 
@@ -379,14 +427,17 @@ void orc_back_tof_lm(const float* xs, const float* xe, int64_t n, const float* o
 int64_t orc_count_samples(const float* xs, const float* xe, int64_t n, const float* origin, const float* vs,
                           const int32_t* dim, float bin_width, float sigma, float n_sigmas, float center_offset,
                           int32_t n_bins, const float* lut, int32_t lut_n, double lut_x0, double lut_dx,
+                          const float* sigma_per_ray, const float* offset_per_ray,
                           const int16_t* bins, int64_t* per_ray) {
     grid64 g = mkgrid(origin, vs, dim);
-    tof64 tf = mktof(bin_width, sigma, n_sigmas, center_offset, n_bins, lut, lut_n, lut_x0, lut_dx);
+    tof64 tf = mktof(bin_width, sigma, n_sigmas, center_offset, n_bins, lut, lut_n, lut_x0, lut_dx, sigma_per_ray,
+                     offset_per_ray);
     int64_t total = 0;
 #pragma omp parallel for schedule(static) reduction(+ : total)
     for (int64_t l = 0; l < n; ++l) {
         int64_t cnt = 0;
-        int ok = !bins || (bins[l] >= 0 && bins[l] < tf.nb);
+        tof64 tl;
+        int ok = (!bins || (bins[l] >= 0 && bins[l] < tf.nb)) && ray_tof(&tf, l, &tl);
         ray64 r = ray_setup(xs + 3 * l, xe + 3 * l, &g);
         if (ok && r.ok) {
             int64_t idx[4];
@@ -394,7 +445,7 @@ int64_t orc_count_samples(const float* xs, const float* xe, int64_t n, const flo
             for (int64_t k = 0; k < g.n[r.p]; ++k) {
                 if (!plane_stencil(&g, &r, k, &t, idx, wt)) continue;
                 if (idx[0] < 0 && idx[1] < 0 && idx[2] < 0 && idx[3] < 0) continue;
-                if (bins && !tof_inside((t - 0.5) * r.len, bins[l], &tf)) continue;
+                if (bins && !tof_inside((t - 0.5) * r.len, bins[l], &tl)) continue;
                 ++cnt;
             }
         }
@@ -471,10 +522,12 @@ void orc_gauss3d(const double* src, double* dst, const int32_t* dim, const float
 void orc_lm_osem(const float* xs, const float* xe, const int16_t* bins, int64_t n, const float* origin,
                  const float* vs, const int32_t* dim, float bin_width, float sigma, float n_sigmas,
                  float center_offset, int32_t n_bins, const float* lut, int32_t lut_n, double lut_x0,
-                 double lut_dx, const double* sens, double bg, int32_t n_iter,
+                 double lut_dx, const float* sigma_per_ray, const float* offset_per_ray, const double* sens,
+                 double bg, int32_t n_iter,
                  int32_t n_sub, double* x, const double* fwhm) {
     grid64 g = mkgrid(origin, vs, dim);
-    tof64 tf = mktof(bin_width, sigma, n_sigmas, center_offset, n_bins, lut, lut_n, lut_x0, lut_dx);
+    tof64 tf = mktof(bin_width, sigma, n_sigmas, center_offset, n_bins, lut, lut_n, lut_x0, lut_dx, sigma_per_ray,
+                     offset_per_ray);
     int64_t nv = nvox(&g);
     int nt = nthreads();
     double* priv = (double*)malloc((size_t)nt * (size_t)nv * sizeof(double));
@@ -492,12 +545,14 @@ void orc_lm_osem(const float* xs, const float* xe, const int16_t* bins, int64_t 
 #pragma omp for schedule(static)
                 for (int64_t q = 0; q < n_j; ++q) {
                     int64_t e = (int64_t)j + q * n_sub;
+                    tof64 tl;
+                    if (!ray_tof(&tf, e, &tl)) continue;
                     double ybar;
-                    ray_forward(xs + 3 * e, xe + 3 * e, &g, &tf, 2, bins[e], xf, &ybar);
+                    ray_forward(xs + 3 * e, xe + 3 * e, &g, &tl, 2, bins[e], xf, &ybar);
                     ybar += bg;
                     if (!(ybar > 0.0)) continue;
                     double r = 1.0 / ybar;
-                    ray_back(xs + 3 * e, xe + 3 * e, &g, &tf, 2, bins[e], mine, &r);
+                    ray_back(xs + 3 * e, xe + 3 * e, &g, &tl, 2, bins[e], mine, &r);
                 }
             }
 #pragma omp parallel for schedule(static)

@@ -10,7 +10,9 @@ written as a tent function (no floor, no neighbour enumeration, zero padding
 is automatic because only grid voxels exist), the plane parameter ``t`` is
 computed in mm (not voxel-index) space, and the TOF weight is obtained by
 Gauss-Legendre quadrature of the truncated Gaussian density over the TOF bin
-(the convolution with the rect written out), not from an erf formula.
+(the convolution with the rect written out), not from an erf formula.  Per-ray
+TOF parameters (``sigma_per_ray`` / ``offset_per_ray`` in the tof dict) replace
+the scalar sigma / centre offset row by row; rows with an unusable entry stay 0.
 """
 from __future__ import annotations
 
@@ -67,6 +69,15 @@ def system_matrix(xstart, xend, origin, voxsize, dim, tof=None, mode="nontof", b
             b = int(bins[l])
             if b < 0 or b >= int(tof["n_bins"]):
                 continue
+        sig_l, off_l = (tof.get("sigma"), tof.get("center_offset", 0.0)) if tof is not None else (None, 0.0)
+        if tof is not None and tof.get("sigma_per_ray") is not None:  # this ray's own kernel width
+            sig_l = float(np.float32(tof["sigma_per_ray"][l]))
+            if not (math.isfinite(sig_l) and sig_l > 0.0):
+                continue
+        if tof is not None and tof.get("offset_per_ray") is not None:  # this ray's own centre offset
+            off_l = float(np.float32(tof["offset_per_ray"][l]))
+            if not math.isfinite(off_l):
+                continue
         for v in range(nv):
             c = centres[v]
             t = (c[p] - s[p]) / d[p]  # the plane through this voxel's centre
@@ -87,14 +98,14 @@ def system_matrix(xstart, xend, origin, voxsize, dim, tof=None, mode="nontof", b
             def weight(cb):
                 if wfn is not None:
                     return wfn(spos - cb)
-                return tof_weight_quadrature(spos, cb, tof["bin_width"], tof["sigma"], tof["n_sigmas"])
+                return tof_weight_quadrature(spos, cb, tof["bin_width"], sig_l, tof["n_sigmas"])
 
             if mode == "sino":
                 for b in range(nb):
-                    cb = (b - 0.5 * (nb - 1)) * tof["bin_width"] + tof.get("center_offset", 0.0)
+                    cb = (b - 0.5 * (nb - 1)) * tof["bin_width"] + off_l
                     A[l, b, v] = ell * wgt * weight(cb)
             else:
-                cb = (b - 0.5 * (int(tof["n_bins"]) - 1)) * tof["bin_width"] + tof.get("center_offset", 0.0)
+                cb = (b - 0.5 * (int(tof["n_bins"]) - 1)) * tof["bin_width"] + off_l
                 A[l, v] = ell * wgt * weight(cb)
     return A
 

@@ -572,3 +572,128 @@ def test_lut_adjoint_and_listmode_equals_sinogram():
     lhs = float(np.sum(sino * y))
     rhs = float(np.sum(img * oracle.back_tof_sino(xs, xe, origin, vs, dim, tof, y)))
     assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+# ------------------------------------- per-ray TOF parameters (generalising Sec. 2.2)
+
+def _per_ray(rng, n, bad=True):
+    """Per-ray sigma in [0.6, 2.5] mm and centre offset in [-3, 3] mm; with `bad`, a few entries
+    that make their ray contribute nothing (sigma 0, negative, NaN; offset infinite)."""
+    sig = rng.uniform(0.6, 2.5, size=n).astype(np.float32)
+    off = rng.uniform(-3.0, 3.0, size=n).astype(np.float32)
+    if bad:
+        sig[3], sig[7], sig[11], off[15] = 0.0, -1.0, np.nan, np.inf
+    return sig, off
+
+
+@pytest.mark.parametrize("gi", range(len(GRIDS)))
+def test_per_ray_tof_matches_bruteforce(gi):
+    """Per-LOR TOF kernel width and centre offset: oracle == brute force whose rows use each
+    ray's own sigma / offset in the quadrature weights; rays with an unusable entry give zero
+    rows.  Catches the scalar sigma or offset leaking into a per-ray computation (in the erf
+    scale, the truncation or the bin centre) and a per-ray array indexed by the wrong ray."""
+    dim, vs, origin = GRIDS[gi]
+    rng = np.random.default_rng(300 + gi)
+    n = 30
+    xs, xe = random_rays(rng, n, origin, vs, dim, inside_frac=0.2)
+    sig, off = _per_ray(rng, n)
+    for per in ({"sigma_per_ray": sig}, {"offset_per_ray": off}, {"sigma_per_ray": sig, "offset_per_ray": off}):
+        tof = dict(tofd(bin_width=2.5, sigma=1.7, n_sigmas=2.5, n_bins=9, center_offset=0.4), **per)
+        A = system_matrix(xs, xe, origin, vs, dim, tof=tof, mode="sino")
+        x = rng.uniform(0, 1, size=dim)
+        y = rng.uniform(0, 1, size=(n, tof["n_bins"]))
+        fs = oracle.fwd_tof_sino(xs, xe, origin, vs, dim, tof, x)
+        np.testing.assert_allclose(fs, np.einsum("lbv,v->lb", A, x.ravel()), rtol=1e-11, atol=1e-12)
+        np.testing.assert_allclose(oracle.back_tof_sino(xs, xe, origin, vs, dim, tof, y).ravel(),
+                                   np.einsum("lbv,lb->v", A, y), rtol=1e-11, atol=1e-12)
+        bins = rng.integers(0, tof["n_bins"], size=n).astype(np.int16)
+        Alm = system_matrix(xs, xe, origin, vs, dim, tof=tof, mode="lm", bins=bins)
+        ylm = rng.uniform(0, 1, size=n)
+        fl = oracle.fwd_tof_lm(xs, xe, origin, vs, dim, tof, bins, x)
+        np.testing.assert_allclose(fl, Alm @ x.ravel(), rtol=1e-11, atol=1e-12)
+        np.testing.assert_allclose(oracle.back_tof_lm(xs, xe, origin, vs, dim, tof, bins, ylm).ravel(),
+                                   Alm.T @ ylm, rtol=1e-11, atol=1e-12)
+        dead = [3, 7, 11] if "sigma_per_ray" in per else []
+        dead += [15] if "offset_per_ray" in per else []
+        assert not np.any(fs[dead]) and not np.any(fl[dead])
+        assert np.count_nonzero(fs.sum(1)) > 10
+
+
+def test_per_ray_tof_work_counter():
+    """The work counter with per-ray sigma / offset: a sample counts iff its stencil touches the
+    grid and it lies strictly inside the bin's support |s - c_b| < n_sigmas sigma_l + bw / 2
+    (written out per plane here, centre from the ray's own offset)."""
+    dim, vs, origin = GRIDS[0]
+    rng = np.random.default_rng(17)
+    n = 40
+    xs, xe = random_rays(rng, n, origin, vs, dim, inside_frac=0.2)
+    sig, off = _per_ray(rng, n)
+    tof = dict(tofd(bin_width=2.0, sigma=1.0, n_sigmas=2.5, n_bins=7), sigma_per_ray=sig, offset_per_ray=off)
+    bins = rng.integers(0, 7, size=n).astype(np.int16)
+    tot, per = oracle.count_samples(xs, xe, origin, vs, dim, tof=tof, bins=bins, per_ray=True)
+    for l in range(n):
+        s_l, o_l = float(sig[l]), float(off[l])
+        usable = math.isfinite(s_l) and s_l > 0 and math.isfinite(o_l)
+        d32 = (xe[l] - xs[l]).astype(np.float32)
+        p = int(np.argmax(np.abs(d32)))
+        inplane = [a for a in range(3) if a != p]
+        a64, b64 = xs[l].astype(float), xe[l].astype(float)
+        length = float(np.linalg.norm(b64 - a64))
+        cb = (int(bins[l]) - 3) * float(tof["bin_width"]) + o_l if usable else 0.0
+        cnt = 0
+        for k in range(dim[p]):
+            t = (origin[p] + k * vs[p] - a64[p]) / (b64[p] - a64[p])
+            if not usable or t < 0 or t > 1:
+                continue
+            X = a64 + t * (b64 - a64)
+            idx = [(X[a] - origin[a]) / vs[a] for a in inplane]
+            touch = all(math.floor(i) + 1 >= 0 and math.floor(i) <= dim[a] - 1 for i, a in zip(idx, inplane))
+            inside = abs((t - 0.5) * length - cb) < float(tof["n_sigmas"]) * s_l + 0.5 * float(tof["bin_width"])
+            cnt += touch and inside
+        assert per[l] == cnt, l
+    assert tot == per.sum() > 0
+
+
+def test_per_ray_offset_shifts_bins():
+    """A per-ray centre offset of k bin widths moves every bin centre of that ray by k bins
+    towards the end point: column t with offset k * bw equals column t + k without offset.
+    Catches a sign error of the offset, or an offset applied to the sample instead of the bin."""
+    rng = np.random.default_rng(18)
+    dim, vs, origin = (20, 18, 8), (2.0, 2.0, 2.0), (-19.0, -17.0, -7.0)
+    n, nb, bw = 40, 41, 4.0
+    xs, xe = random_rays(rng, n, origin, vs, dim)
+    x = rng.uniform(size=dim)
+    k = rng.integers(-3, 4, size=n)
+    tof0 = tofd(bw, 3.0, 3.0, nb)
+    ref = oracle.fwd_tof_sino(xs, xe, origin, vs, dim, tof0, x)
+    sh = oracle.fwd_tof_sino(xs, xe, origin, vs, dim, dict(tof0, offset_per_ray=(k * bw).astype(np.float32)), x)
+    for l in range(n):
+        t = np.arange(max(0, -k[l]), min(nb, nb - k[l]))
+        np.testing.assert_allclose(sh[l, t], ref[l, t + k[l]], rtol=1e-12, atol=1e-15)
+    assert np.any(k != 0) and np.count_nonzero(ref) > 0
+
+
+def test_per_ray_sigma_bin_sum_and_adjoint():
+    """With each ray's own sigma the TOF weights of a fully covered LOR still telescope to
+    erf(n_sigmas / sqrt 2) times the non-TOF projection (the mass of the truncated Gaussian does
+    not depend on its width), and the per-ray back projection is the exact adjoint.  Catches a
+    truncation or an erf scale that mixes the scalar and the per-ray sigma."""
+    rng = np.random.default_rng(19)
+    dim, vs, origin = (20, 18, 8), (2.0, 2.0, 2.0), (-19.0, -17.0, -7.0)
+    n = 50
+    xs, xe = random_rays(rng, n, origin, vs, dim)
+    x = rng.uniform(size=dim)
+    sig = rng.uniform(1.0, 6.0, size=n).astype(np.float32)
+    tof = dict(tofd(4.0, 3.0, 3.0, 41), sigma_per_ray=sig)  # bins cover +-82 mm
+    pt = oracle.fwd_tof_sino(xs, xe, origin, vs, dim, tof, x)
+    pn = oracle.fwd(xs, xe, origin, vs, dim, x)
+    np.testing.assert_allclose(pt.sum(1), special.erf(3.0 / math.sqrt(2.0)) * pn, rtol=1e-13, atol=1e-13)
+    y = rng.uniform(size=(n, 41))
+    lhs = float(np.sum(pt * y))
+    rhs = float(np.sum(x * oracle.back_tof_sino(xs, xe, origin, vs, dim, tof, y)))
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+    # arrays holding the scalar values reproduce the scalar path exactly
+    same = dict(tofd(4.0, 3.0, 3.0, 41, center_offset=1.5), sigma_per_ray=np.full(n, 3.0, np.float32),
+                offset_per_ray=np.full(n, 1.5, np.float32))
+    assert np.array_equal(oracle.fwd_tof_sino(xs, xe, origin, vs, dim, same, x),
+                          oracle.fwd_tof_sino(xs, xe, origin, vs, dim, tofd(4.0, 3.0, 3.0, 41, 1.5), x))
