@@ -49,8 +49,8 @@ def kernel_sources_sha():
 
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "tof_lm_40M_traffic.json")
 # the device kernel each timed entry point of the listmode step launches
-KERNEL_OF = {"pp_lm_presort": "ppmi::k_lm_keys", "pp_fwd_tof_lm": "ppmi::k_fwd_tof_lm<false>",
-             "pp_back_tof_lm": "ppmi::k_back_runs<ppmi::ModeTofLm<false> >"}
+KERNEL_OF = {"pp_lm_presort": "ppmi::k_lm_keys", "pp_fwd_tof_lm": "ppmi::k_fwd_tof_lm<false, false>",
+             "pp_back_tof_lm": "ppmi::k_back_runs<ppmi::ModeTofLm<false, false> >"}
 
 
 def profiled_traffic(entry):

@@ -62,13 +62,14 @@
 extern "C" {
 #endif
 
-#define PP_ABI_VERSION 3
+#define PP_ABI_VERSION 4
 
 enum pp_status {
     PP_OK = 0,
     PP_EINVAL_PTR = 1,  /* a required pointer is NULL */
     PP_EINVAL_GEOM = 2, /* dim <= 0, voxel count > 2^30, voxsize <= 0 or non-finite, origin non-finite */
-    PP_EINVAL_TOF = 3,  /* n_bins not in [1, 256], bin_width/sigma/n_sigmas <= 0 or non-finite, bad table */
+    PP_EINVAL_TOF = 3,  /* n_bins not in [1, 256], bin_width/sigma/n_sigmas <= 0 or non-finite, bad table,
+                         * per-ray sigma with a table, per-ray parameters where unsupported */
     PP_EINVAL_N = 4,    /* negative count, or a count/slot argument out of range */
     PP_EHIP = 5,        /* the HIP runtime rejected a launch */
     PP_EINVAL_RES = 6   /* resolution model: FWHM negative or non-finite, or wider than 31 voxels of radius */
@@ -90,7 +91,17 @@ typedef struct pp_image {
  *     kernels): lut[i] = w(lut_x0 + i lut_dx), i in [0, lut_n), linearly interpolated and 0
  *     outside [lut_x0, lut_x0 + (lut_n - 1) lut_dx]; sigma and n_sigmas are ignored.  The
  *     table is DEVICE memory owned by the caller and must stay valid until the calls that
- *     use it have run (it is read at run time, also by captured graphs). */
+ *     use it have run (it is read at run time, also by captured graphs).
+ * Per-ray parameters (a generalisation of the single kernel of Sec. 2.2, for scanners whose
+ * timing resolution or timing offset varies with the LOR or the event): sigma_per_ray and
+ * offset_per_ray are optional DEVICE float32 arrays with one entry per ray (per LOR of a
+ * sinogram call, per event of a listmode call, indexed like xstart), owned by the caller and
+ * read at run time.  Ray l then uses sigma_per_ray[l] in place of sigma (truncation at
+ * n_sigmas * sigma_per_ray[l]) and offset_per_ray[l] in place of center_offset.  A ray whose
+ * sigma is not a positive finite number, or whose offset is not finite, contributes nothing
+ * (data, not an error; a sigma below 1e-30 mm is taken as 1e-30 mm).  A table kernel takes
+ * offset_per_ray but not sigma_per_ray (PP_EINVAL_TOF).  Accepted by the projectors and
+ * pp_count_samples; pp_lm_osem_accumulate returns PP_EINVAL_TOF when either is set. */
 typedef struct pp_tof {
     float bin_width;     /* mm, > 0 */
     float sigma;         /* mm, > 0 (FWHM / 2.355) */
@@ -101,6 +112,8 @@ typedef struct pp_tof {
     int32_t lut_n;       /* 2 .. 2^24 when lut is set */
     float lut_x0;        /* mm, position of lut[0] relative to the bin centre; finite */
     float lut_dx;        /* mm, table spacing, > 0 */
+    const float* sigma_per_ray;  /* DEVICE [n] sigma of each ray (mm), or NULL */
+    const float* offset_per_ray; /* DEVICE [n] centre offset of each ray (mm), or NULL */
 } pp_tof_t;
 
 /* Non-TOF forward projection (Sec. 2.1, Fig. 1).
@@ -223,7 +236,8 @@ typedef struct pp_osem_slot {
 int64_t pp_osem_chunks(int64_t n_events, int32_t n_sub);
 
 /* Fused forward -> 1/(ybar) -> back projection of the current subset of
- * every live slot into its acc.  d_slots: DEVICE array of n_slots entries. */
+ * every live slot into its acc.  d_slots: DEVICE array of n_slots entries.
+ * tof: one kernel for all slots (per-ray parameters: PP_EINVAL_TOF). */
 int pp_lm_osem_accumulate(const pp_osem_slot_t* d_slots, int32_t n_slots, const pp_image_t* geom,
                           const pp_tof_t* tof, void* stream);
 

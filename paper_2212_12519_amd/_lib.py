@@ -33,10 +33,11 @@ class CImage(ctypes.Structure):
 class CTof(ctypes.Structure):
     _fields_ = [("bin_width", ctypes.c_float), ("sigma", ctypes.c_float), ("n_sigmas", ctypes.c_float),
                 ("center_offset", ctypes.c_float), ("n_bins", ctypes.c_int32), ("lut", ctypes.c_void_p),
-                ("lut_n", ctypes.c_int32), ("lut_x0", ctypes.c_float), ("lut_dx", ctypes.c_float)]
+                ("lut_n", ctypes.c_int32), ("lut_x0", ctypes.c_float), ("lut_dx", ctypes.c_float),
+                ("sigma_per_ray", ctypes.c_void_p), ("offset_per_ray", ctypes.c_void_p)]
 
 
-assert ctypes.sizeof(CTof) == 48, ctypes.sizeof(CTof)
+assert ctypes.sizeof(CTof) == 64, ctypes.sizeof(CTof)
 
 
 class COsemSlot(ctypes.Structure):
@@ -79,7 +80,9 @@ class ImageGeom:
 class TofParams:
     """TOF bins and kernel.  With `lut` (a float32 CUDA tensor: the bin weight at distances
     lut_x0 + i * lut_dx mm from the bin centre, linearly interpolated, 0 outside) the kernel is
-    the table and sigma / n_sigmas are ignored; the tensor must outlive the calls using it."""
+    the table and sigma / n_sigmas are ignored.  `sigma_per_ray` / `offset_per_ray` (float32
+    CUDA tensors [n], one entry per ray of the calls they are used with) replace sigma /
+    center_offset ray by ray.  Tensors must outlive the calls using them."""
     bin_width: float
     sigma: float
     n_sigmas: float
@@ -88,6 +91,8 @@ class TofParams:
     lut: object = field(default=None, compare=False)
     lut_x0: float = 0.0
     lut_dx: float = 0.0
+    sigma_per_ray: object = field(default=None, compare=False)
+    offset_per_ray: object = field(default=None, compare=False)
 
     def __post_init__(self):
         if self.lut is not None:
@@ -95,13 +100,28 @@ class TofParams:
             if not (isinstance(t, torch.Tensor) and t.device.type == "cuda" and t.dtype == torch.float32
                     and t.is_contiguous() and t.dim() == 1 and t.numel() >= 2):
                 raise ValueError("lut must be a contiguous 1-D float32 CUDA tensor of >= 2 entries")
+        for name in ("sigma_per_ray", "offset_per_ray"):
+            t = getattr(self, name)
+            if t is not None and not (isinstance(t, torch.Tensor) and t.device.type == "cuda"
+                                      and t.dtype == torch.float32 and t.is_contiguous() and t.dim() == 1):
+                raise ValueError(f"{name} must be a contiguous 1-D float32 CUDA tensor")
 
-    def c(self):
+    @property
+    def per_ray(self):
+        return self.sigma_per_ray is not None or self.offset_per_ray is not None
+
+    def c(self, n=None):
+        """The C struct; `n` = the call's ray count, checked against the per-ray arrays."""
+        per = []
+        for t in (self.sigma_per_ray, self.offset_per_ray):
+            if t is not None and (n is None or t.numel() != n):
+                raise ValueError("per-ray TOF parameters need one entry per ray of the call")
+            per.append(t.data_ptr() if t is not None else None)
         if self.lut is None:
             return CTof(self.bin_width, self.sigma, self.n_sigmas, self.center_offset, int(self.n_bins), None, 0,
-                        0.0, 0.0)
+                        0.0, 0.0, *per)
         return CTof(self.bin_width, self.sigma, self.n_sigmas, self.center_offset, int(self.n_bins),
-                    self.lut.data_ptr(), int(self.lut.numel()), float(self.lut_x0), float(self.lut_dx))
+                    self.lut.data_ptr(), int(self.lut.numel()), float(self.lut_x0), float(self.lut_dx), *per)
 
 
 def as_geom(g) -> ImageGeom:
@@ -115,7 +135,8 @@ def as_tof(t) -> TofParams:
         return t
     return TofParams(float(t.bin_width), float(t.sigma), float(t.n_sigmas), int(t.n_bins),
                      float(getattr(t, "center_offset", 0.0)), getattr(t, "lut", None),
-                     float(getattr(t, "lut_x0", 0.0)), float(getattr(t, "lut_dx", 0.0)))
+                     float(getattr(t, "lut_x0", 0.0)), float(getattr(t, "lut_dx", 0.0)),
+                     getattr(t, "sigma_per_ray", None), getattr(t, "offset_per_ray", None))
 
 
 def load():

@@ -11,7 +11,7 @@
 
 using namespace ppmi;
 
-static_assert(sizeof(pp_tof_t) == 48, "pp_tof_t layout");
+static_assert(sizeof(pp_tof_t) == 64, "pp_tof_t layout");
 static_assert(sizeof(pp_osem_slot_t) == 104, "pp_osem_slot_t layout");
 
 namespace {
@@ -51,17 +51,23 @@ int make_tof(const pp_tof_t* ti, TofK& t) {
     if (ti->n_bins < 1 || ti->n_bins > 256) return PP_EINVAL_TOF;
     if (!std::isfinite(ti->bin_width) || !(ti->bin_width > 0.0f) || !std::isfinite(ti->center_offset))
         return PP_EINVAL_TOF;
+    t.sig_ray = ti->sigma_per_ray;
+    t.off_ray = ti->offset_per_ray;
+    // with per-ray offsets, c0 is the centre of bin 0 before the offset (each ray adds its own)
+    const double offset = ti->offset_per_ray ? 0.0 : (double)ti->center_offset;
     if (ti->lut) {  // tabulated kernel: sigma and n_sigmas are not used
         const double x0 = ti->lut_x0, dx = ti->lut_dx, x1 = x0 + (double)(ti->lut_n - 1) * dx;
         if (ti->lut_n < 2 || ti->lut_n > (1 << 24) || !std::isfinite(ti->lut_x0) || !std::isfinite(ti->lut_dx) ||
-            !(ti->lut_dx > 0.0f) || !(std::fabs(x1) <= 3.0e38))  // the table's end must be a float
+            !(ti->lut_dx > 0.0f) || !(std::fabs(x1) <= 3.0e38) ||  // the table's end must be a float
+            ti->sigma_per_ray)                                      // the table fixes the kernel's shape
             return PP_EINVAL_TOF;
         t.bw = ti->bin_width;
         t.inv_bw = 1.0 / t.bw;
-        t.c0 = -0.5 * (double)(ti->n_bins - 1) * t.bw + (double)ti->center_offset;
-        t.trunc = 1.0f;
+        t.c0 = -0.5 * (double)(ti->n_bins - 1) * t.bw + offset;
         t.hbw = (float)(0.5 * t.bw);
         t.inv_sqrt2_sig = 1.0f;
+        t.cmax = 1.0f;
+        t.nsig = 1.0f;
         t.nb = ti->n_bins;
         t.lo = x0;
         t.hi = x1;
@@ -76,9 +82,10 @@ int make_tof(const pp_tof_t* ti, TofK& t) {
     const double bw = ti->bin_width, sig = ti->sigma, ns = ti->n_sigmas;
     t.bw = bw;
     t.inv_bw = 1.0 / bw;
-    t.c0 = -0.5 * (double)(ti->n_bins - 1) * bw + (double)ti->center_offset;
-    t.trunc = (float)(ns * sig);
+    t.c0 = -0.5 * (double)(ti->n_bins - 1) * bw + offset;
     t.hbw = (float)(0.5 * bw);
+    t.cmax = (float)(ns / std::sqrt(2.0));
+    t.nsig = ti->n_sigmas;
     t.win = ns * sig + 0.5 * bw;
     t.inv_sqrt2_sig = (float)(1.0 / (std::sqrt(2.0) * sig));
     t.nb = ti->n_bins;
@@ -150,7 +157,9 @@ const char* pp_strerror(int code) {
         case PP_OK: return "ok";
         case PP_EINVAL_PTR: return "a required pointer is NULL";
         case PP_EINVAL_GEOM: return "invalid image geometry (dim <= 0, >= 2^30 voxels, voxsize <= 0 or non-finite)";
-        case PP_EINVAL_TOF: return "invalid TOF parameters (n_bins not in [1,256], or width/sigma/n_sigmas <= 0)";
+        case PP_EINVAL_TOF:
+            return "invalid TOF parameters (n_bins not in [1,256], width/sigma/n_sigmas <= 0, bad table, or per-ray "
+                   "parameters where unsupported)";
         case PP_EINVAL_N: return "count or slot argument out of range";
         case PP_EHIP: return g_hip_msg[0] ? g_hip_msg : "HIP launch error";
         case PP_EINVAL_RES: return "invalid resolution model (FWHM < 0 or non-finite, or radius > 31 voxels)";
@@ -282,6 +291,7 @@ int pp_lm_osem_accumulate(const pp_osem_slot_t* d_slots, int32_t n_slots, const 
     TofK t;
     PP_TRY(make_geom(geom, g));
     PP_TRY(make_tof(tof, t));
+    if (t.sig_ray || t.off_ray) return PP_EINVAL_TOF;  // one kernel for every slot
     if (n_slots < 0 || n_slots > (1 << 20)) return PP_EINVAL_N;
     if (n_slots == 0) return PP_OK;
     if (!d_slots) return PP_EINVAL_PTR;

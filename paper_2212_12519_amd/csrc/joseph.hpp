@@ -13,6 +13,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <float.h>
 #include <limits.h>
 #include <stdint.h>
 
@@ -34,10 +35,13 @@ struct TofK {
     const float* lut;     // tabulated bin weight at lo + i * dx, or nullptr (Gaussian)
     int lut_n;
     float lut_inv_dx;
-    float trunc;          // n_sigmas * sigma, mm
     float hbw;            // bw / 2, mm
     float inv_sqrt2_sig;  // 1 / (sqrt(2) sigma)
+    float cmax;           // n_sigmas / sqrt(2): the truncation in units of the erf argument
+    float nsig;           // n_sigmas
     int nb;               // bins
+    const float* sig_ray; // sigma of each ray (mm), or nullptr: every ray has sigma
+    const float* off_ray; // centre offset of each ray (mm), or nullptr: c0 holds the offset
 };
 
 // Resolution-model blur taps per axis: w[a][i + r[a]] for |i| <= r[a].
@@ -137,10 +141,47 @@ __device__ __forceinline__ bool ray_setup(const float* __restrict__ xs, const fl
     return lo <= hi;
 }
 
-// Plane range of the ray restricted to the support of one bin (centre + [t.lo, t.hi]).
-__device__ __forceinline__ bool tof_window(RayK& r, double centre, const TofK& t) {
+// The TOF parameters of one ray.  Without per-ray arrays these are the kernel's; with them
+// ray l has its own width (sigma_l, same n_sigmas) and/or its own centre offset, which is
+// folded into the ray's TOF coordinate (s0 -= shift) so that bin centres stay c0 + b bw.
+struct TofRay {
+    double shift;   // the ray's centre offset (0 without per-ray offsets: c0 holds it)
+    double lo, hi;  // support of a bin's weight relative to its centre
+    float inv;      // 1 / (sqrt(2) sigma_l)
+};
+
+// 1 / (sqrt(2) sigma) of a per-ray sigma (sigma below 1e-30 mm taken as 1e-30 mm, a kernel far
+// narrower than any voxel, so that the product never overflows)
+__device__ __forceinline__ float tof_inv_sigma(float sigma) { return 1.0f / (1.41421356f * fmaxf(sigma, 1e-30f)); }
+
+// Parameters of ray l; false if its per-ray entries are unusable (sigma not a positive
+// finite number, offset not finite): the ray contributes nothing.
+template <bool PerRay>
+__device__ __forceinline__ bool tof_ray(const TofK& t, int64_t l, TofRay& q) {
+    q.shift = 0.0;
+    q.lo = t.lo;
+    q.hi = t.hi;
+    q.inv = t.inv_sqrt2_sig;
+    if (!PerRay) return true;
+    if (t.sig_ray) {
+        const float sg = t.sig_ray[l];
+        if (!(sg > 0.0f && sg <= FLT_MAX)) return false;
+        q.inv = tof_inv_sigma(sg);
+        q.hi = (double)t.nsig * (double)sg + 0.5 * t.bw;
+        q.lo = -q.hi;
+    }
+    if (t.off_ray) {
+        const float o = t.off_ray[l];
+        if (!(fabsf(o) <= FLT_MAX)) return false;
+        q.shift = o;
+    }
+    return true;
+}
+
+// Plane range of the ray restricted to the support of one bin (centre + [lo, hi]).
+__device__ __forceinline__ bool tof_window(RayK& r, double centre, double lo_x, double hi_x) {
     int lo = r.k_lo, hi = r.k_hi;
-    clip_affine(r.s0, r.ds, centre + t.lo, centre + t.hi, lo, hi);
+    clip_affine(r.s0, r.ds, centre + lo_x, centre + hi_x, lo, hi);
     r.k_lo = lo;
     r.k_hi = hi;
     return lo <= hi;
@@ -148,8 +189,8 @@ __device__ __forceinline__ bool tof_window(RayK& r, double centre, const TofK& t
 
 // The same, then s(k) made relative to the bin centre (s0 -= centre): fma(k, ds, s0) is
 // the signed distance of plane sample k from the centre, the argument of tof_weight.
-__device__ __forceinline__ bool tof_window_rel(RayK& r, double centre, const TofK& t) {
-    const bool any = tof_window(r, centre, t);
+__device__ __forceinline__ bool tof_window_rel(RayK& r, double centre, double lo_x, double hi_x) {
+    const bool any = tof_window(r, centre, lo_x, hi_x);
     r.s0 -= centre;
     return any;
 }
@@ -254,9 +295,11 @@ __device__ __forceinline__ float erf_hastings(float x) {
     return copysignf(fmaf(-(t * P), e, 1.0f), x);
 }
 
-// erf(clip(x, -trunc, trunc) / (sqrt(2) sigma)), x in mm
-__device__ __forceinline__ float tof_erf(float x, const TofK& t) {
-    return erf_hastings(fminf(fmaxf(x, -t.trunc), t.trunc) * t.inv_sqrt2_sig);
+// erf(clip(x, -n_sigmas sigma, n_sigmas sigma) / (sqrt(2) sigma)), x in mm, with inv =
+// 1 / (sqrt(2) sigma): the clip is taken on the scaled argument (at +-n_sigmas / sqrt 2), so a
+// ray with its own sigma needs nothing but its own inv
+__device__ __forceinline__ float tof_erf(float x, float inv, const TofK& t) {
+    return erf_hastings(fminf(fmaxf(x * inv, -t.cmax), t.cmax));
 }
 
 
@@ -271,20 +314,23 @@ __device__ __forceinline__ float tof_lut(double x, const TofK& t) {
 }
 
 // weight of a bin for a plane sample at signed distance x (mm) from the bin centre:
-// G(x + bw/2) - G(x - bw/2) (Lut = false), or the tabulated kernel (Lut = true)
+// G(x + bw/2) - G(x - bw/2) with inv = 1 / (sqrt(2) sigma) (Lut = false), or the tabulated
+// kernel (Lut = true)
 template <bool Lut>
-__device__ __forceinline__ float tof_weight(double x, const TofK& t) {
+__device__ __forceinline__ float tof_weight(double x, const TofK& t, float inv) {
     if (Lut) return tof_lut(x, t);
     const float xf = (float)x;
-    return 0.5f * (tof_erf(xf + t.hbw, t) - tof_erf(xf - t.hbw, t));
+    return 0.5f * (tof_erf(xf + t.hbw, inv, t) - tof_erf(xf - t.hbw, inv, t));
 }
 
-// TOF bins whose window contains a sample at absolute TOF position s (clamped to [0, n_bins)).
-__device__ __forceinline__ void tof_bin_range(double s, const TofK& t, int& b_lo, int& b_hi) {
+// TOF bins whose support [lo_x, hi_x] (relative to the bin centre) contains a sample at TOF
+// position s (clamped to [0, n_bins)).
+__device__ __forceinline__ void tof_bin_range(double s, const TofK& t, double lo_x, double hi_x, int& b_lo,
+                                              int& b_hi) {
     // bins b with c_b in (s - hi, s - lo); a rounding of the products can only drop a bin whose
     // centre sits exactly on the open end, whose weight is 0
-    const double lo = floor((s - t.hi - t.c0) * t.inv_bw);
-    const double hi = ceil((s - t.lo - t.c0) * t.inv_bw);
+    const double lo = floor((s - hi_x - t.c0) * t.inv_bw);
+    const double hi = ceil((s - lo_x - t.c0) * t.inv_bw);
     b_lo = (int)fmax(lo, 0.0);
     b_hi = (int)fmin(hi, (double)(t.nb - 1));
 }

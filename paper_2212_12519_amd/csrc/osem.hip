@@ -53,10 +53,10 @@ struct ModeOsem {
                           int& /*aux*/) const {
         const int b = bins[l];
         if (b < 0 || b >= t.nb || !ray_setup(xs + 3 * l, xe + 3 * l, g, r)) return false;
-        if (!tof_window_rel(r, t.c0 + b * t.bw, t)) return false;
+        if (!tof_window_rel(r, t.c0 + b * t.bw, t.lo, t.hi)) return false;
         float fwd = 0.0f;
         for (int k = r.k_lo; k <= r.k_hi; ++k) {
-            const float w = tof_weight<Lut>(fma((double)k, r.ds, r.s0), t);
+            const float w = tof_weight<Lut>(fma((double)k, r.ds, r.s0), t, t.inv_sqrt2_sig);
             fwd += w * stencil_gather(x, r, stencil_at(r, k));
         }
         const float ybar = r.ell * fwd + bg;
@@ -64,7 +64,9 @@ struct ModeOsem {
         cv = r.ell / ybar;
         return true;
     }
-    __device__ float sample(double x, float cv, int /*aux*/) const { return tof_weight<Lut>(x, t) * cv; }
+    __device__ float sample(double x, float cv, int /*aux*/) const {
+        return tof_weight<Lut>(x, t, t.inv_sqrt2_sig) * cv;
+    }
 };
 
 template <bool Lut>

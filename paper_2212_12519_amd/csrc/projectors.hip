@@ -40,7 +40,8 @@ __global__ void __launch_bounds__(kBlock) k_fwd(const float* __restrict__ xs, co
 
 // ------------------------------------------------------- TOF listmode ----
 
-template <bool Lut>
+// PerRay: per-ray sigma / centre offset arrays are set (TofRay in joseph.hpp)
+template <bool Lut, bool PerRay>
 __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(const float* __restrict__ xs, const float* __restrict__ xe,
                                                        const int16_t* __restrict__ bins, int64_t n, GeomK g,
                                                        TofK t, const float* __restrict__ img,
@@ -50,10 +51,12 @@ __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(const float* __restrict__
     const int b = bins[l];
     float acc = 0.0f;
     RayK r;
-    if (b >= 0 && b < t.nb && ray_setup(xs + 3 * l, xe + 3 * l, g, r)) {
-        if (tof_window_rel(r, t.c0 + b * t.bw, t)) {
+    TofRay q;
+    if (b >= 0 && b < t.nb && tof_ray<PerRay>(t, l, q) && ray_setup(xs + 3 * l, xe + 3 * l, g, r)) {
+        if (PerRay) r.s0 -= q.shift;
+        if (tof_window_rel(r, t.c0 + b * t.bw, q.lo, q.hi)) {
             for (int k = r.k_lo; k <= r.k_hi; ++k) {
-                const float w = tof_weight<Lut>(fma((double)k, r.ds, r.s0), t);
+                const float w = tof_weight<Lut>(fma((double)k, r.ds, r.s0), t, q.inv);
                 acc += w * stencil_gather(img, r, stencil_at(r, k));
             }
             acc *= r.ell;
@@ -69,8 +72,9 @@ __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(const float* __restrict__
 // the bins inside the TOF window are evaluated; neighbouring bins share their
 // edge, so a window of m bins costs m + 1 erf evaluations.  The block's
 // [rays][bins] output tile is contiguous in memory and is written with
-// coalesced stores at the end.
+// coalesced stores at the end.  PerRay: per-ray sigma / centre offset arrays are set.
 
+template <bool PerRay>
 __global__ void k_fwd_tof_sino(const float* __restrict__ xs, const float* __restrict__ xe, int64_t n, GeomK g,
                                TofK t, const float* __restrict__ img, float* __restrict__ p) {
     extern __shared__ float lds[];  // [nb][blockDim]
@@ -79,23 +83,25 @@ __global__ void k_fwd_tof_sino(const float* __restrict__ xs, const float* __rest
     const int64_t l = l0 + threadIdx.x;
     for (int b = 0; b < t.nb; ++b) lds[b * nt + threadIdx.x] = 0.0f;
     RayK r;
-    if (l < n && ray_setup(xs + 3 * l, xe + 3 * l, g, r)) {
+    TofRay q;
+    if (l < n && tof_ray<PerRay>(t, l, q) && ray_setup(xs + 3 * l, xe + 3 * l, g, r)) {
+        if (PerRay) r.s0 -= q.shift;
         float* mine = lds + threadIdx.x;
         for (int k = r.k_lo; k <= r.k_hi; ++k) {
             const float v = stencil_gather(img, r, stencil_at(r, k));
             if (v == 0.0f) continue;
             const double s = fma((double)k, r.ds, r.s0);
             int b_lo, b_hi;
-            tof_bin_range(s, t, b_lo, b_hi);
+            tof_bin_range(s, t, q.lo, q.hi, b_lo, b_hi);
             if (t.lut) {
                 for (int b = b_lo; b <= b_hi; ++b) mine[b * nt] += tof_lut(s - (t.c0 + b * t.bw), t) * v;
                 continue;
             }
             // upper edge argument of bin b_lo; the next edges follow in float steps of bw
             const float x_hi0 = (float)(s - (t.c0 + b_lo * t.bw) + 0.5 * t.bw), bwf = (float)t.bw;
-            float e_hi = tof_erf(x_hi0, t);
+            float e_hi = tof_erf(x_hi0, q.inv, t);
             for (int b = b_lo; b <= b_hi; ++b) {
-                const float e_lo = tof_erf(x_hi0 - (float)(b - b_lo + 1) * bwf, t);
+                const float e_lo = tof_erf(x_hi0 - (float)(b - b_lo + 1) * bwf, q.inv, t);
                 mine[b * nt] += 0.5f * (e_hi - e_lo) * v;
                 e_hi = e_lo;
             }
@@ -113,6 +119,7 @@ __global__ void k_fwd_tof_sino(const float* __restrict__ xs, const float* __rest
     }
 }
 
+template <bool PerRay>
 __global__ void k_back_tof_sino(const float* __restrict__ xs, const float* __restrict__ xe, int64_t n, GeomK g,
                                 TofK t, float* __restrict__ img, const float* __restrict__ p) {
     extern __shared__ float lds[];  // [nb][blockDim]: the block's projection tile, transposed
@@ -128,7 +135,9 @@ __global__ void k_back_tof_sino(const float* __restrict__ xs, const float* __res
     }
     __syncthreads();
     RayK r;
-    bool ok = l < n && ray_setup(xs + 3 * l, xe + 3 * l, g, r);
+    TofRay q;
+    bool ok = l < n && tof_ray<PerRay>(t, l, q) && ray_setup(xs + 3 * l, xe + 3 * l, g, r);
+    if (PerRay && ok) r.s0 -= q.shift;
     const float* mine = lds + threadIdx.x;
     if (ok) {
         bool any = false;
@@ -145,14 +154,14 @@ __global__ void k_back_tof_sino(const float* __restrict__ xs, const float* __res
         if (act) {
             const double s = fma((double)k, r.ds, r.s0);
             int b_lo, b_hi;
-            tof_bin_range(s, t, b_lo, b_hi);
+            tof_bin_range(s, t, q.lo, q.hi, b_lo, b_hi);
             if (t.lut) {
                 for (int b = b_lo; b <= b_hi; ++b) c += tof_lut(s - (t.c0 + b * t.bw), t) * mine[b * nt];
             } else {
                 const float x_hi0 = (float)(s - (t.c0 + b_lo * t.bw) + 0.5 * t.bw), bwf = (float)t.bw;
-                float e_hi = tof_erf(x_hi0, t);
+                float e_hi = tof_erf(x_hi0, q.inv, t);
                 for (int b = b_lo; b <= b_hi; ++b) {
-                    const float e_lo = tof_erf(x_hi0 - (float)(b - b_lo + 1) * bwf, t);
+                    const float e_lo = tof_erf(x_hi0 - (float)(b - b_lo + 1) * bwf, q.inv, t);
                     c += 0.5f * (e_hi - e_lo) * mine[b * nt];
                     e_hi = e_lo;
                 }
@@ -177,13 +186,15 @@ __global__ void __launch_bounds__(kBlock) k_count(const float* __restrict__ xs, 
     if (l >= n) return;
     int cnt = 0;
     RayK r;
+    TofRay q{};
     bool ok = ray_setup(xs + 3 * l, xe + 3 * l, g, r);
     double centre = 0.0;
     if (ok && bins) {
         const int b = bins[l];
-        ok = b >= 0 && b < t.nb;
+        ok = b >= 0 && b < t.nb && tof_ray<true>(t, l, q);
+        r.s0 -= q.shift;
         centre = t.c0 + b * t.bw;
-        ok = ok && tof_window(r, centre, t);
+        ok = ok && tof_window(r, centre, q.lo, q.hi);
     }
     if (ok) {
         for (int k = r.k_lo; k <= r.k_hi; ++k) {
@@ -191,7 +202,7 @@ __global__ void __launch_bounds__(kBlock) k_count(const float* __restrict__ xs, 
             if (!((st.i0ok || st.i1ok) && (st.j0ok || st.j1ok))) continue;
             if (bins) {
                 const double x = fma((double)k, r.ds, r.s0) - centre;
-                if (!(x > t.lo && x < t.hi)) continue;
+                if (!(x > q.lo && x < q.hi)) continue;
             }
             ++cnt;
         }
@@ -238,13 +249,19 @@ hipError_t launch_back(const float* xs, const float* xe, int64_t n, const GeomK&
 
 hipError_t launch_fwd_tof_lm(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g,
                              const TofK& t, const float* img, float* p, const int32_t* order, hipStream_t s) {
-    hipLaunchKernelGGL(t.lut ? k_fwd_tof_lm<true> : k_fwd_tof_lm<false>, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s,
-                       xs, xe, bins, n, g, t, img, p, order);
+    const bool per = t.sig_ray || t.off_ray;
+    auto* k = t.lut ? (per ? k_fwd_tof_lm<true, true> : k_fwd_tof_lm<true, false>)
+                    : (per ? k_fwd_tof_lm<false, true> : k_fwd_tof_lm<false, false>);
+    hipLaunchKernelGGL(k, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, xs, xe, bins, n, g, t, img, p, order);
     return hipGetLastError();
 }
 
 hipError_t launch_back_tof_lm(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g,
                               const TofK& t, float* img, const float* p, const int32_t* order, hipStream_t s) {
+    if (t.sig_ray || t.off_ray) {
+        if (t.lut) return launch_runs(ModeTofLm<true, true>{p, bins, t}, xs, xe, n, g, img, order, s);
+        return launch_runs(ModeTofLm<false, true>{p, bins, t}, xs, xe, n, g, img, order, s);
+    }
     if (t.lut) return launch_runs(ModeTofLm<true>{p, bins, t}, xs, xe, n, g, img, order, s);
     return launch_runs(ModeTofLm<false>{p, bins, t}, xs, xe, n, g, img, order, s);
 }
@@ -255,20 +272,27 @@ hipError_t launch_fwd_tof_sino(const float* xs, const float* xe, int64_t n, cons
                                const float* img, float* p, hipStream_t s) {
     const int blk = sino_block(t.nb);
     const size_t lds = (size_t)t.nb * blk * sizeof(float);
-    hipLaunchKernelGGL(k_fwd_tof_sino, dim3(grid_for(n, blk)), dim3(blk), lds, s, xs, xe, n, g, t, img, p);
+    hipLaunchKernelGGL((t.sig_ray || t.off_ray) ? k_fwd_tof_sino<true> : k_fwd_tof_sino<false>, dim3(grid_for(n, blk)),
+                       dim3(blk), lds, s, xs, xe, n, g, t, img, p);
     return hipGetLastError();
 }
 
 hipError_t launch_back_tof_sino(const float* xs, const float* xe, int64_t n, const GeomK& g, const TofK& t,
                                 float* img, const float* p, hipStream_t s) {
     // the run/sheet kernel carries ray indices in 32 bits
+    const bool per = t.sig_ray || t.off_ray;
     if (n < (int64_t(1) << 31)) {
+        if (per) {
+            if (t.lut) return launch_runs(ModeTofSino<true, true>{p, t}, xs, xe, n, g, img, nullptr, s);
+            return launch_runs(ModeTofSino<false, true>{p, t}, xs, xe, n, g, img, nullptr, s);
+        }
         if (t.lut) return launch_runs(ModeTofSino<true>{p, t}, xs, xe, n, g, img, nullptr, s);
         return launch_runs(ModeTofSino<false>{p, t}, xs, xe, n, g, img, nullptr, s);
     }
     const int blk = sino_block(t.nb);
     const size_t lds = (size_t)t.nb * blk * sizeof(float);
-    hipLaunchKernelGGL(k_back_tof_sino, dim3(grid_for(n, blk)), dim3(blk), lds, s, xs, xe, n, g, t, img, p);
+    hipLaunchKernelGGL(per ? k_back_tof_sino<true> : k_back_tof_sino<false>, dim3(grid_for(n, blk)), dim3(blk), lds, s,
+                       xs, xe, n, g, t, img, p);
     return hipGetLastError();
 }
 

@@ -72,29 +72,38 @@ struct ModeNonTof {
     __device__ float sample(double /*x*/, float cv, int /*aux*/) const { return cv; }
 };
 
-template <bool Lut>
+// Listmode TOF.  With per-ray TOF parameters (PerRay) the ray's offset is folded into its TOF
+// coordinate at setup and aux carries the bits of its 1 / (sqrt(2) sigma).
+template <bool Lut, bool PerRay = false>
 struct ModeTofLm {
-    static constexpr bool kAux = false;
+    static constexpr bool kAux = PerRay;
     const float* __restrict__ p;
     const int16_t* __restrict__ bins;
     TofK t;
     __device__ bool setup(int64_t l, const float* xs, const float* xe, const GeomK& g, RayK& r, float& cv,
-                          int& /*aux*/) const {
+                          int& aux) const {
         const int b = bins[l];
         const float pl = p[l];
-        if (b < 0 || b >= t.nb || pl == 0.0f || !ray_setup(xs + 3 * l, xe + 3 * l, g, r)) return false;
-        if (!tof_window_rel(r, t.c0 + b * t.bw, t)) return false;
+        TofRay q;
+        if (b < 0 || b >= t.nb || pl == 0.0f || !tof_ray<PerRay>(t, l, q) || !ray_setup(xs + 3 * l, xe + 3 * l, g, r))
+            return false;
+        if (PerRay) r.s0 -= q.shift;
+        if (!tof_window_rel(r, t.c0 + b * t.bw, q.lo, q.hi)) return false;
         cv = r.ell * pl;
+        if (PerRay) aux = __float_as_int(q.inv);
         return true;
     }
-    __device__ float sample(double x, float cv, int /*aux*/) const { return tof_weight<Lut>(x, t) * cv; }
+    __device__ float sample(double x, float cv, int aux) const {
+        return tof_weight<Lut>(x, t, PerRay ? __int_as_float(aux) : t.inv_sqrt2_sig) * cv;
+    }
 };
 
 // Sinogram TOF: the value at a plane sample is ell * sum over the bins b of its TOF window of
 // w_b(s) p[l][b] (neighbouring bins share their erf edge).  aux carries the ray index l (the
 // sheet path is used for fewer than 2^31 rays); all lanes of a wave read the same ray's bin
-// values, so those loads hit one or two cache lines.
-template <bool Lut>
+// values, so those loads hit one or two cache lines.  With per-ray TOF parameters (PerRay) the
+// ray's offset is folded into its TOF coordinate at setup and its sigma is read per sample.
+template <bool Lut, bool PerRay = false>
 struct ModeTofSino {
     static constexpr bool kAux = true;
     const float* __restrict__ p;  // [n][n_bins]
@@ -104,23 +113,27 @@ struct ModeTofSino {
         const float* pr = p + l * t.nb;
         bool any = false;
         for (int b = 0; b < t.nb; ++b) any |= (pr[b] != 0.0f);
-        if (!any || !ray_setup(xs + 3 * l, xe + 3 * l, g, r)) return false;
+        TofRay q;
+        if (!any || !tof_ray<PerRay>(t, l, q) || !ray_setup(xs + 3 * l, xe + 3 * l, g, r)) return false;
+        if (PerRay) r.s0 -= q.shift;
         cv = r.ell;
         aux = (int)l;
         return true;
     }
     __device__ float sample(double s, float cv, int aux) const {
         const float* pr = p + (int64_t)aux * t.nb;
+        TofRay q;
+        tof_ray<PerRay>(t, aux, q);  // usable: checked at setup
         int b_lo, b_hi;
-        tof_bin_range(s, t, b_lo, b_hi);
+        tof_bin_range(s, t, q.lo, q.hi, b_lo, b_hi);
         float c = 0.0f;
         if (Lut) {
             for (int b = b_lo; b <= b_hi; ++b) c += tof_lut(s - (t.c0 + b * t.bw), t) * pr[b];
         } else {
             const float x_hi0 = (float)(s - (t.c0 + b_lo * t.bw) + 0.5 * t.bw), bwf = (float)t.bw;
-            float e_hi = tof_erf(x_hi0, t);
+            float e_hi = tof_erf(x_hi0, q.inv, t);
             for (int b = b_lo; b <= b_hi; ++b) {
-                const float e_lo = tof_erf(x_hi0 - (float)(b - b_lo + 1) * bwf, t);
+                const float e_lo = tof_erf(x_hi0 - (float)(b - b_lo + 1) * bwf, q.inv, t);
                 c += 0.5f * (e_hi - e_lo) * pr[b];
                 e_hi = e_lo;
             }

@@ -109,6 +109,8 @@ def osem_steps(table: SlotTable, geom, tof, n_steps=1, res_fwhm=None):
     res_fwhm (mm) is the resolution model of the slots that have x_fwd set."""
     g, t = as_geom(geom), as_tof(tof)
     lib = load()
+    if t.per_ray:
+        raise ValueError("listmode OSEM takes one TOF kernel for every event (no per-ray parameters)")
     gc, tc = g.c(), t.c()
     fw = None if res_fwhm is None else fwhm3(res_fwhm)
     st = stream_of(table.dev)

@@ -43,38 +43,38 @@ def pp_back(xstart, xend, geom, img, p, order=None):
 def pp_fwd_tof_sino(xstart, xend, geom, tof, img, p):
     """TOF sinogram forward projection into p[n, n_bins] (overwritten)."""
     g, t = as_geom(geom), as_tof(tof)
-    _dev(xstart, xend, img, p)
+    _dev(xstart, xend, img, p, t.sigma_per_ray, t.offset_per_ray)
     n = _rays(xstart, xend)
     _img(img, g)
     if p.dtype != torch.float32 or p.numel() != n * t.n_bins:
         raise ValueError("p must be float32 [n, n_bins]")
-    check(load().pp_fwd_tof_sino(ptr(xstart), ptr(xend), n, g.c(), t.c(), ptr(img), ptr(p), stream_of(p)))
+    check(load().pp_fwd_tof_sino(ptr(xstart), ptr(xend), n, g.c(), t.c(n), ptr(img), ptr(p), stream_of(p)))
     return p
 
 
 def pp_back_tof_sino(xstart, xend, geom, tof, img, p):
     """TOF sinogram back projection, img += A^T p."""
     g, t = as_geom(geom), as_tof(tof)
-    _dev(xstart, xend, img, p)
+    _dev(xstart, xend, img, p, t.sigma_per_ray, t.offset_per_ray)
     n = _rays(xstart, xend)
     _img(img, g)
     if p.dtype != torch.float32 or p.numel() != n * t.n_bins:
         raise ValueError("p must be float32 [n, n_bins]")
-    check(load().pp_back_tof_sino(ptr(xstart), ptr(xend), n, g.c(), t.c(), ptr(img), ptr(p), stream_of(img)))
+    check(load().pp_back_tof_sino(ptr(xstart), ptr(xend), n, g.c(), t.c(n), ptr(img), ptr(p), stream_of(img)))
     return img
 
 
 def pp_fwd_tof_lm(xstart, xend, tof_bin, geom, tof, img, p, order=None):
     """TOF listmode forward projection (event's bin only) into p[n] (overwritten)."""
     g, t = as_geom(geom), as_tof(tof)
-    _dev(xstart, xend, tof_bin, img, p, order)
+    _dev(xstart, xend, tof_bin, img, p, order, t.sigma_per_ray, t.offset_per_ray)
     n = _rays(xstart, xend)
     _bins(tof_bin, n)
     _img(img, g)
     _order(order, n)
     if p.dtype != torch.float32 or p.numel() != n:
         raise ValueError("p must be float32 [n]")
-    check(load().pp_fwd_tof_lm(ptr(xstart), ptr(xend), ptr(tof_bin), n, g.c(), t.c(), ptr(img), ptr(p),
+    check(load().pp_fwd_tof_lm(ptr(xstart), ptr(xend), ptr(tof_bin), n, g.c(), t.c(n), ptr(img), ptr(p),
                                ptr(order), stream_of(p)))
     return p
 
@@ -82,14 +82,14 @@ def pp_fwd_tof_lm(xstart, xend, tof_bin, geom, tof, img, p, order=None):
 def pp_back_tof_lm(xstart, xend, tof_bin, geom, tof, img, p, order=None):
     """TOF listmode back projection, img += A^T p."""
     g, t = as_geom(geom), as_tof(tof)
-    _dev(xstart, xend, tof_bin, img, p, order)
+    _dev(xstart, xend, tof_bin, img, p, order, t.sigma_per_ray, t.offset_per_ray)
     n = _rays(xstart, xend)
     _bins(tof_bin, n)
     _img(img, g)
     _order(order, n)
     if p.dtype != torch.float32 or p.numel() != n:
         raise ValueError("p must be float32 [n]")
-    check(load().pp_back_tof_lm(ptr(xstart), ptr(xend), ptr(tof_bin), n, g.c(), t.c(), ptr(img), ptr(p),
+    check(load().pp_back_tof_lm(ptr(xstart), ptr(xend), ptr(tof_bin), n, g.c(), t.c(n), ptr(img), ptr(p),
                                 ptr(order), stream_of(img)))
     return img
 
@@ -109,7 +109,7 @@ def pp_lm_presort(xstart, xend, tof_bin, geom, tof, order, workspace, n_sub=1):
     tc = None
     if tof_bin is not None:
         _bins(tof_bin, n)
-        tc = as_tof(tof).c()
+        tc = as_tof(tof).c(n)
     check(load().pp_lm_presort(ptr(xstart), ptr(xend), ptr(tof_bin), n, g.c(), tc, int(n_sub), ptr(order),
                                ptr(workspace), workspace.numel() * workspace.element_size(), stream_of(order)))
     return order
@@ -208,7 +208,9 @@ def pp_count_samples(xstart, xend, tof_bin, geom, tof, counts):
     tc = None
     if tof_bin is not None:
         _bins(tof_bin, n)
-        tc = as_tof(tof).c()
+        t = as_tof(tof)
+        _dev(xstart, t.sigma_per_ray, t.offset_per_ray)
+        tc = t.c(n)
     check(load().pp_count_samples(ptr(xstart), ptr(xend), ptr(tof_bin), n, g.c(), tc, ptr(counts),
                                   stream_of(counts)))
     return counts

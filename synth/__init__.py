@@ -13,7 +13,7 @@ sinogram ordered radial/view/plane, unsorted listmode events with TOF bins).
 """
 from .scanner import CylinderScanner, sinogram_planes, sinogram_crystal_pairs
 from .phantom import ImageGrid, cylinder_sphere_phantom, ellipsoid_lesion_phantom
-from .events import generate_tof_lm_events
+from .events import generate_tof_lm_events, tof_per_ray_params
 from . import configs
 
 __all__ = [
@@ -24,5 +24,6 @@ __all__ = [
     "cylinder_sphere_phantom",
     "ellipsoid_lesion_phantom",
     "generate_tof_lm_events",
+    "tof_per_ray_params",
     "configs",
 ]

@@ -114,3 +114,21 @@ def generate_tof_lm_events(scanner: CylinderScanner, n_rad: int, max_rd: int, gr
         n_have += take.numel()
     res = [torch.cat([o[k] for o in outs]).contiguous() for k in range(len(outs[0]))]
     return tuple(res)
+
+
+def tof_per_ray_params(n, sigma, seed, width_range=(0.8, 1.25), offset_sd=5.0, n_bad=0, device="cpu"):
+    """Per-ray TOF parameters for `n` rays: sigma_l = sigma * U(width_range) (a timing resolution
+    that varies with the crystal pair or the count rate) and a centre offset ~ N(0, offset_sd) mm
+    (a per-LOR timing calibration).  With n_bad > 0 the first entries are made unusable in turn:
+    sigma 0, sigma < 0, sigma NaN, offset +inf (such rays must contribute nothing).  Returns
+    float32 (sigma_per_ray, offset_per_ray) tensors on `device`."""
+    g = torch.Generator().manual_seed(int(seed))
+    lo, hi = width_range
+    sig = sigma * (lo + (hi - lo) * torch.rand(n, generator=g, dtype=torch.float64))
+    off = offset_sd * torch.randn(n, generator=g, dtype=torch.float64)
+    sig, off = sig.to(torch.float32), off.to(torch.float32)
+    bad = [(sig, 0.0), (sig, -1.0), (sig, float("nan")), (off, float("inf"))]
+    for i in range(min(n_bad, n)):
+        arr, val = bad[i % 4]
+        arr[i] = val
+    return sig.to(device), off.to(device)

@@ -29,7 +29,7 @@ def test_exports_every_declared_symbol(lib):
     assert len(names) >= 12, names
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.pp_abi_version() == 3
+    assert lib.pp_abi_version() == 4
 
 
 def _geom(dim=(4, 4, 4), vs=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0)):
@@ -73,6 +73,19 @@ def test_error_codes(lib):
                 lut(dx=float("nan")), lut(x0=3e38, dx=3e38)):
         assert lib.pp_fwd_tof_sino(DUMMY, DUMMY, 5, g, bad, DUMMY, DUMMY, None) == PP_EINVAL_TOF
         assert lib.pp_back_tof_lm(DUMMY, DUMMY, DUMMY, 5, g, bad, DUMMY, DUMMY, None, None) == PP_EINVAL_TOF
+    # per-ray TOF parameters: a table takes per-ray offsets but not per-ray sigmas; OSEM takes neither
+    lut_sig = lut()
+    lut_sig.sigma_per_ray = DUMMY2.value
+    assert lib.pp_fwd_tof_sino(DUMMY, DUMMY, 5, g, lut_sig, DUMMY, DUMMY, None) == PP_EINVAL_TOF
+    assert lib.pp_back_tof_lm(DUMMY, DUMMY, DUMMY, 5, g, lut_sig, DUMMY, DUMMY, None, None) == PP_EINVAL_TOF
+    lut_off = lut()
+    lut_off.offset_per_ray = DUMMY2.value
+    assert lib.pp_fwd_tof_sino(DUMMY, DUMMY, 0, g, lut_off, DUMMY, DUMMY, None) == PP_OK  # valid (n == 0)
+    for field in ("sigma_per_ray", "offset_per_ray"):
+        t = _tof()
+        setattr(t, field, DUMMY2.value)
+        assert lib.pp_lm_osem_accumulate(DUMMY, 3, g, t, None) == PP_EINVAL_TOF
+        assert lib.pp_fwd_tof_lm(DUMMY, DUMMY, DUMMY, 0, g, t, DUMMY, DUMMY, None, None) == PP_OK
     assert lib.pp_fwd_tof_lm(DUMMY, DUMMY, None, 5, g, _tof(), DUMMY, DUMMY, None, None) == PP_EINVAL_PTR
     assert lib.pp_fwd_tof_lm(DUMMY, DUMMY, DUMMY, 5, g, None, DUMMY, DUMMY, None, None) == PP_EINVAL_PTR
     assert lib.pp_lm_osem_accumulate(DUMMY, -1, g, _tof(), None) == PP_EINVAL_N
@@ -117,6 +130,18 @@ def test_osem_chunks(lib):
     assert lib.pp_osem_chunks(8 * 1024, 8) == 1
     assert lib.pp_osem_chunks(8 * 1024 + 1, 8) == 2
     assert lib.pp_osem_chunks(20_000_000, 8) == (2_500_000 + 1023) // 1024
+
+
+def test_python_tof_params_per_ray_checks():
+    """The binding rejects per-ray arrays that are not float32 CUDA tensors, and a call whose
+    ray count differs from their length (no GPU needed: both checks come first)."""
+    import paper_2212_12519_amd as pp
+
+    with pytest.raises(ValueError):
+        pp.TofParams(28.0, 24.8, 3.0, 29, sigma_per_ray=[1.0, 2.0])
+    t = pp.TofParams(28.0, 24.8, 3.0, 29)
+    assert not t.per_ray
+    assert t.c(5).sigma_per_ray is None and t.c().offset_per_ray is None
 
 
 def test_python_binding_rejects_cpu_tensors():
