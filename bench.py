@@ -168,9 +168,10 @@ def lm_leg(args, pp, C, dev):
     grid, tofs = C.GRID_CLIN, C.TOF_CLIN
     img = C.phantom_clin(device=dev)
     t0 = time.perf_counter()
-    xs, xe, bins = generate_tof_lm_events(C.SCANNER_CLIN, C.SINO_CLIN.n_rad, C.SINO_CLIN.max_rd, grid, img, n_ev,
-                                          seed=C.SEED_EVENTS, tof_bin_width=tofs.bin_width, tof_sigma=tofs.sigma,
-                                          n_tof_bins=tofs.n_bins, device=dev)
+    xs, xe, bins, pair = generate_tof_lm_events(C.SCANNER_CLIN, C.SINO_CLIN.n_rad, C.SINO_CLIN.max_rd, grid, img,
+                                                n_ev, seed=C.SEED_EVENTS, tof_bin_width=tofs.bin_width,
+                                                tof_sigma=tofs.sigma, n_tof_bins=tofs.n_bins, device=dev,
+                                                return_crystals=True)
     torch.cuda.synchronize()
     log(f"generated {n_ev} events in {time.perf_counter() - t0:.1f} s")
     G = pp.ImageGeom(grid.dim, grid.voxsize, grid.origin)
@@ -189,10 +190,20 @@ def lm_leg(args, pp, C, dev):
         lambda: pp.pp_fill(bimg, 0.0), args.steps, args.warmup)
     # the same projector pair in the events' own (unsorted) order (skipped when profiling the step)
     t_fwd_u = t_back_u = float("nan")
+    crys = {}
     if args.only is None:
         _, t_fwd_u, t_back_u = timed_pairs(lambda: pp.pp_fwd_tof_lm(xs, xe, bins, G, T, img, p),
                                            lambda: pp.pp_back_tof_lm(xs, xe, bins, G, T, bimg, p),
                                            lambda: pp.pp_fill(bimg, 0.0), 2, 1)
+        # the same step on crystal-index events (8 instead of 24 bytes of geometry per event)
+        table = C.SCANNER_CLIN.crystal_table(device=dev)
+        wall_c, (cs, cf, cb) = timed_phases(
+            [lambda: pp.pp_lm_presort_crystals(table, pair, bins, G, T, order, sort_ws),
+             lambda: pp.pp_fwd_tof_lm_crystals(table, pair, bins, G, T, img, p, order),
+             lambda: pp.pp_back_tof_lm_crystals(table, pair, bins, G, T, bimg, p, order)],
+            lambda: pp.pp_fill(bimg, 0.0), 3, 1)
+        crys = {"t_presort_ms": cs, "t_fwd_ms": cf, "t_back_ms": cb, "events_per_s": n_ev / (wall_c / 3)}
+        log(f"TOF-LM crystal-index events: presort {cs:.2f} ms, fwd {cf:.2f} ms, back {cb:.2f} ms")
     log(f"TOF-LM: presort {t_sort:.2f} ms, fwd {t_fwd:.2f} ms, back {t_back:.2f} ms, wall "
         f"{1e3 * wall / args.steps:.2f} ms/step; unsorted order: fwd {t_fwd_u:.2f} ms back {t_back_u:.2f} ms; "
         f"{n_samples / n_ev:.1f} samples/event")
@@ -206,6 +217,7 @@ def lm_leg(args, pp, C, dev):
         "samples_per_event": n_samples / n_ev, "alg_bytes_per_launch": alg_bytes,
         "dominant": dom_name, "achieved_gbs": achieved,
         "fwd_alg_gbs": alg_bytes / (t_fwd * 1e-3) / 1e9, "back_alg_gbs": alg_bytes / (t_back * 1e-3) / 1e9,
+        "crystal_index_events": crys,
     }
     return res, (xs, xe, bins, img, G, T)
 

@@ -62,7 +62,7 @@
 extern "C" {
 #endif
 
-#define PP_ABI_VERSION 4
+#define PP_ABI_VERSION 5
 
 enum pp_status {
     PP_OK = 0,
@@ -183,6 +183,44 @@ int pp_count_samples(const float* xstart, const float* xend, const int16_t* tof_
                      const pp_image_t* geom, const pp_tof_t* tof, int32_t* counts, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Crystal-index events (index-based LOR geometry).  A scanner identifies a
+ * listmode event by the two crystals that detected it; the entry points
+ * above take the rays' end points as coordinates (the generic ray lists of
+ * Sec. 2.2).  The _crystals variants take them as indices into a table of
+ * crystal positions: event e runs from crystal_xyz[pair[e][0]] to
+ * crystal_xyz[pair[e][1]], exactly the ray the coordinate entry point
+ * computes for those coordinates, at 8 instead of 24 bytes per event.
+ *   crystal_xyz: DEVICE float32 [n_crystals][3], mm, caller owned;
+ *   pair:        DEVICE int32 [n][2] (start crystal, end crystal), 8-byte
+ *                aligned (else PP_EINVAL_PTR);
+ *   n_crystals:  >= 1 (else PP_EINVAL_N).  A pair entry outside
+ *                [0, n_crystals) makes its event contribute nothing (p = 0,
+ *                sorted last by the presort): data, not an error.
+ * Every other argument, the order and the error codes are those of the
+ * coordinate entry point of the same name.
+ * ------------------------------------------------------------------------ */
+int pp_fwd_crystals(const float* crystal_xyz, int32_t n_crystals, const int32_t* pair, int64_t n_events,
+                    const pp_image_t* geom, const float* img, float* p, const int32_t* order, void* stream);
+int pp_back_crystals(const float* crystal_xyz, int32_t n_crystals, const int32_t* pair, int64_t n_events,
+                     const pp_image_t* geom, float* img, const float* p, const int32_t* order, void* stream);
+int pp_fwd_tof_lm_crystals(const float* crystal_xyz, int32_t n_crystals, const int32_t* pair,
+                           const int16_t* tof_bin, int64_t n_events, const pp_image_t* geom, const pp_tof_t* tof,
+                           const float* img, float* p, const int32_t* order, void* stream);
+int pp_back_tof_lm_crystals(const float* crystal_xyz, int32_t n_crystals, const int32_t* pair,
+                            const int16_t* tof_bin, int64_t n_events, const pp_image_t* geom, const pp_tof_t* tof,
+                            float* img, const float* p, const int32_t* order, void* stream);
+int pp_lm_presort_crystals(const float* crystal_xyz, int32_t n_crystals, const int32_t* pair,
+                           const int16_t* tof_bin, int64_t n, const pp_image_t* geom, const pp_tof_t* tof,
+                           int32_t n_sub, int32_t* order, void* workspace, size_t workspace_bytes, void* stream);
+int pp_count_samples_crystals(const float* crystal_xyz, int32_t n_crystals, const int32_t* pair,
+                              const int16_t* tof_bin, int64_t n, const pp_image_t* geom, const pp_tof_t* tof,
+                              int32_t* counts, void* stream);
+/* out[i] = in[order[i]] for pair (int32 [n][2]) and tof_bin (int16 [n], may be
+ * NULL together with tof_bin_out), as pp_gather_events. */
+int pp_gather_crystal_events(const int32_t* pair, const int16_t* tof_bin, const int32_t* order, int64_t n,
+                             int32_t* pair_out, int16_t* tof_bin_out, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batched listmode TOF OSEM (the paper's listmode OSEM of Sec. 2.6, run for
  * many short frames at once).  One "step" of a frame is one ordered-subset
  * update with subset j = {events e : e mod n_sub == j}:
@@ -211,8 +249,8 @@ int pp_count_samples(const float* xstart, const float* xend, const int16_t* tof_
  * the order of atomic adds).
  * ------------------------------------------------------------------------ */
 typedef struct pp_osem_slot {
-    const float* xstart;     /* [n_events][3] */
-    const float* xend;       /* [n_events][3] */
+    const float* xstart;     /* [n_events][3] (unused with crystal_pair) */
+    const float* xend;       /* [n_events][3] (unused with crystal_pair) */
     const int16_t* tof_bin;  /* [n_events] */
     float* x;                /* [n_vox] current image, updated in place */
     float* acc;              /* [n_vox] accumulator, zero between steps */
@@ -224,10 +262,13 @@ typedef struct pp_osem_slot {
     int32_t subset;          /* subset of the next step, in [0, n_sub) */
     int32_t steps_left;      /* steps still to run; 0 = finished */
     int32_t active;          /* 0 = empty slot */
-    int32_t reserved;
+    int32_t n_crystals;      /* entries of crystal_xyz (with crystal_pair) */
     float* x_fwd;            /* [n_vox] G x for the resolution model, or NULL (no model) */
     float* tmp;              /* [n_vox] scratch of the resolution model; required when x_fwd is set
                               * (a slot with x_fwd but no tmp is skipped by every call) */
+    const int32_t* crystal_pair; /* [n_events][2] crystal-index events (8-byte aligned), or NULL */
+    const float* crystal_xyz;    /* [n_crystals][3] crystal table, used with crystal_pair (a slot with
+                                  * crystal_pair but no table or n_crystals < 1 is skipped by every call) */
 } pp_osem_slot_t;
 
 /* Work chunks a slot needs per step (events of the largest subset / 1024,

@@ -45,11 +45,12 @@ class COsemSlot(ctypes.Structure):
                 ("x", ctypes.c_void_p), ("acc", ctypes.c_void_p), ("sens", ctypes.c_void_p),
                 ("n_events", ctypes.c_int64), ("chunk_begin", ctypes.c_int64), ("bg", ctypes.c_float),
                 ("n_sub", ctypes.c_int32), ("subset", ctypes.c_int32), ("steps_left", ctypes.c_int32),
-                ("active", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("x_fwd", ctypes.c_void_p), ("tmp", ctypes.c_void_p)]
+                ("active", ctypes.c_int32), ("n_crystals", ctypes.c_int32),
+                ("x_fwd", ctypes.c_void_p), ("tmp", ctypes.c_void_p),
+                ("crystal_pair", ctypes.c_void_p), ("crystal_xyz", ctypes.c_void_p)]
 
 
-assert ctypes.sizeof(COsemSlot) == 104, ctypes.sizeof(COsemSlot)
+assert ctypes.sizeof(COsemSlot) == 120, ctypes.sizeof(COsemSlot)
 
 
 @dataclass(frozen=True)
@@ -165,6 +166,13 @@ def load():
         "pp_gauss3d": [P, P, P, G, P, P],
         "pp_fill": [P, I64, ctypes.c_float, P],
         "pp_count_samples": [P, P, P, I64, G, T, P, P],
+        "pp_fwd_crystals": [P, I32, P, I64, G, P, P, P, P],
+        "pp_back_crystals": [P, I32, P, I64, G, P, P, P, P],
+        "pp_fwd_tof_lm_crystals": [P, I32, P, P, I64, G, T, P, P, P, P],
+        "pp_back_tof_lm_crystals": [P, I32, P, P, I64, G, T, P, P, P, P],
+        "pp_lm_presort_crystals": [P, I32, P, P, I64, G, T, I32, P, P, ctypes.c_size_t, P],
+        "pp_count_samples_crystals": [P, I32, P, P, I64, G, T, P, P],
+        "pp_gather_crystal_events": [P, P, P, I64, P, P, P],
     }
     for name, argt in sig.items():
         f = getattr(lib, name)
@@ -228,6 +236,19 @@ def _order(order, n):
         return
     if order.dtype != torch.int32 or order.numel() != n:
         raise ValueError("order must be int32 [n]")
+
+
+def _crystal_events(crystal_xyz, pair):
+    """(n events, n crystals) of a crystal table [n_crystals, 3] float32 and pairs [n, 2] int32."""
+    if crystal_xyz.dtype != torch.float32 or crystal_xyz.dim() != 2 or crystal_xyz.shape[1] != 3:
+        raise ValueError("crystal_xyz must be float32 [n_crystals, 3]")
+    if not 1 <= crystal_xyz.shape[0] < 2**31:
+        raise ValueError("crystal table size out of range")
+    if pair.dtype != torch.int32 or pair.dim() != 2 or pair.shape[1] != 2:
+        raise ValueError("pair must be int32 [n, 2]")
+    if pair.numel() and pair.data_ptr() % 8:
+        raise ValueError("pair must be 8-byte aligned")
+    return pair.shape[0], crystal_xyz.shape[0]
 
 
 def _bins(bins, n):

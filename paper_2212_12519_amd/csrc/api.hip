@@ -12,7 +12,7 @@
 using namespace ppmi;
 
 static_assert(sizeof(pp_tof_t) == 64, "pp_tof_t layout");
-static_assert(sizeof(pp_osem_slot_t) == 104, "pp_osem_slot_t layout");
+static_assert(sizeof(pp_osem_slot_t) == 120, "pp_osem_slot_t layout");
 
 namespace {
 
@@ -133,6 +133,16 @@ int check_n(int64_t n) { return (n < 0 || n > kMaxRays) ? PP_EINVAL_N : PP_OK; }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+RaySrc coords(const float* xs, const float* xe) { return RaySrc{xs, xe, nullptr, 0}; }
+
+// Crystal-index events: table and pairs checked (pointers when n > 0, alignment of the pairs).
+int crystals(const float* xyz, int32_t n_crystals, const int32_t* pair, int64_t n, RaySrc& src) {
+    if (n_crystals < 1) return PP_EINVAL_N;
+    if (n > 0 && (!xyz || !pair || (reinterpret_cast<uintptr_t>(pair) & 7u) != 0)) return PP_EINVAL_PTR;
+    src = RaySrc{xyz, nullptr, reinterpret_cast<const int2*>(pair), n_crystals};
+    return PP_OK;
+}
+
 int device_cus() {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 256;
@@ -174,7 +184,7 @@ int pp_fwd(const float* xstart, const float* xend, int64_t n, const pp_image_t* 
     PP_TRY(check_n(n));
     if (n == 0) return PP_OK;
     if (!xstart || !xend || !img || !p) return PP_EINVAL_PTR;
-    return hip_status(launch_fwd(xstart, xend, n, g, img, p, order, as_stream(stream)));
+    return hip_status(launch_fwd(coords(xstart, xend), n, g, img, p, order, as_stream(stream)));
 }
 
 int pp_back(const float* xstart, const float* xend, int64_t n, const pp_image_t* geom, float* img, const float* p,
@@ -184,7 +194,7 @@ int pp_back(const float* xstart, const float* xend, int64_t n, const pp_image_t*
     PP_TRY(check_n(n));
     if (n == 0) return PP_OK;
     if (!xstart || !xend || !img || !p) return PP_EINVAL_PTR;
-    return hip_status(launch_back(xstart, xend, n, g, img, p, order, as_stream(stream)));
+    return hip_status(launch_back(coords(xstart, xend), n, g, img, p, order, as_stream(stream)));
 }
 
 int pp_fwd_tof_sino(const float* xstart, const float* xend, int64_t n, const pp_image_t* geom, const pp_tof_t* tof,
@@ -196,7 +206,7 @@ int pp_fwd_tof_sino(const float* xstart, const float* xend, int64_t n, const pp_
     PP_TRY(check_n(n));
     if (n == 0) return PP_OK;
     if (!xstart || !xend || !img || !p) return PP_EINVAL_PTR;
-    return hip_status(launch_fwd_tof_sino(xstart, xend, n, g, t, img, p, as_stream(stream)));
+    return hip_status(launch_fwd_tof_sino(coords(xstart, xend), n, g, t, img, p, as_stream(stream)));
 }
 
 int pp_back_tof_sino(const float* xstart, const float* xend, int64_t n, const pp_image_t* geom, const pp_tof_t* tof,
@@ -208,7 +218,7 @@ int pp_back_tof_sino(const float* xstart, const float* xend, int64_t n, const pp
     PP_TRY(check_n(n));
     if (n == 0) return PP_OK;
     if (!xstart || !xend || !img || !p) return PP_EINVAL_PTR;
-    return hip_status(launch_back_tof_sino(xstart, xend, n, g, t, img, p, as_stream(stream)));
+    return hip_status(launch_back_tof_sino(coords(xstart, xend), n, g, t, img, p, as_stream(stream)));
 }
 
 int pp_fwd_tof_lm(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n, const pp_image_t* geom,
@@ -220,7 +230,7 @@ int pp_fwd_tof_lm(const float* xstart, const float* xend, const int16_t* tof_bin
     PP_TRY(check_n(n));
     if (n == 0) return PP_OK;
     if (!xstart || !xend || !tof_bin || !img || !p) return PP_EINVAL_PTR;
-    return hip_status(launch_fwd_tof_lm(xstart, xend, tof_bin, n, g, t, img, p, order, as_stream(stream)));
+    return hip_status(launch_fwd_tof_lm(coords(xstart, xend), tof_bin, n, g, t, img, p, order, as_stream(stream)));
 }
 
 int pp_back_tof_lm(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n, const pp_image_t* geom,
@@ -232,7 +242,7 @@ int pp_back_tof_lm(const float* xstart, const float* xend, const int16_t* tof_bi
     PP_TRY(check_n(n));
     if (n == 0) return PP_OK;
     if (!xstart || !xend || !tof_bin || !img || !p) return PP_EINVAL_PTR;
-    return hip_status(launch_back_tof_lm(xstart, xend, tof_bin, n, g, t, img, p, order, as_stream(stream)));
+    return hip_status(launch_back_tof_lm(coords(xstart, xend), tof_bin, n, g, t, img, p, order, as_stream(stream)));
 }
 
 int pp_count_samples(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n, const pp_image_t* geom,
@@ -244,7 +254,102 @@ int pp_count_samples(const float* xstart, const float* xend, const int16_t* tof_
     PP_TRY(check_n(n));
     if (n == 0) return PP_OK;
     if (!xstart || !xend || !counts) return PP_EINVAL_PTR;
-    return hip_status(launch_count(xstart, xend, tof_bin, n, g, t, counts, as_stream(stream)));
+    return hip_status(launch_count(coords(xstart, xend), tof_bin, n, g, t, counts, as_stream(stream)));
+}
+
+int pp_fwd_crystals(const float* crystal_xyz, int32_t n_crystals, const int32_t* pair, int64_t n,
+                    const pp_image_t* geom, const float* img, float* p, const int32_t* order, void* stream) {
+    GeomK g;
+    RaySrc src;
+    PP_TRY(make_geom(geom, g));
+    PP_TRY(check_n(n));
+    PP_TRY(crystals(crystal_xyz, n_crystals, pair, n, src));
+    if (n == 0) return PP_OK;
+    if (!img || !p) return PP_EINVAL_PTR;
+    return hip_status(launch_fwd(src, n, g, img, p, order, as_stream(stream)));
+}
+
+int pp_back_crystals(const float* crystal_xyz, int32_t n_crystals, const int32_t* pair, int64_t n,
+                     const pp_image_t* geom, float* img, const float* p, const int32_t* order, void* stream) {
+    GeomK g;
+    RaySrc src;
+    PP_TRY(make_geom(geom, g));
+    PP_TRY(check_n(n));
+    PP_TRY(crystals(crystal_xyz, n_crystals, pair, n, src));
+    if (n == 0) return PP_OK;
+    if (!img || !p) return PP_EINVAL_PTR;
+    return hip_status(launch_back(src, n, g, img, p, order, as_stream(stream)));
+}
+
+int pp_fwd_tof_lm_crystals(const float* crystal_xyz, int32_t n_crystals, const int32_t* pair, const int16_t* tof_bin,
+                           int64_t n, const pp_image_t* geom, const pp_tof_t* tof, const float* img, float* p,
+                           const int32_t* order, void* stream) {
+    GeomK g;
+    TofK t;
+    RaySrc src;
+    PP_TRY(make_geom(geom, g));
+    PP_TRY(make_tof(tof, t));
+    PP_TRY(check_n(n));
+    PP_TRY(crystals(crystal_xyz, n_crystals, pair, n, src));
+    if (n == 0) return PP_OK;
+    if (!tof_bin || !img || !p) return PP_EINVAL_PTR;
+    return hip_status(launch_fwd_tof_lm(src, tof_bin, n, g, t, img, p, order, as_stream(stream)));
+}
+
+int pp_back_tof_lm_crystals(const float* crystal_xyz, int32_t n_crystals, const int32_t* pair, const int16_t* tof_bin,
+                            int64_t n, const pp_image_t* geom, const pp_tof_t* tof, float* img, const float* p,
+                            const int32_t* order, void* stream) {
+    GeomK g;
+    TofK t;
+    RaySrc src;
+    PP_TRY(make_geom(geom, g));
+    PP_TRY(make_tof(tof, t));
+    PP_TRY(check_n(n));
+    PP_TRY(crystals(crystal_xyz, n_crystals, pair, n, src));
+    if (n == 0) return PP_OK;
+    if (!tof_bin || !img || !p) return PP_EINVAL_PTR;
+    return hip_status(launch_back_tof_lm(src, tof_bin, n, g, t, img, p, order, as_stream(stream)));
+}
+
+int pp_count_samples_crystals(const float* crystal_xyz, int32_t n_crystals, const int32_t* pair,
+                              const int16_t* tof_bin, int64_t n, const pp_image_t* geom, const pp_tof_t* tof,
+                              int32_t* counts, void* stream) {
+    GeomK g;
+    TofK t{};
+    RaySrc src;
+    PP_TRY(make_geom(geom, g));
+    if (tof_bin) PP_TRY(make_tof(tof, t));
+    PP_TRY(check_n(n));
+    PP_TRY(crystals(crystal_xyz, n_crystals, pair, n, src));
+    if (n == 0) return PP_OK;
+    if (!counts) return PP_EINVAL_PTR;
+    return hip_status(launch_count(src, tof_bin, n, g, t, counts, as_stream(stream)));
+}
+
+int pp_lm_presort_crystals(const float* crystal_xyz, int32_t n_crystals, const int32_t* pair, const int16_t* tof_bin,
+                           int64_t n, const pp_image_t* geom, const pp_tof_t* tof, int32_t n_sub, int32_t* order,
+                           void* workspace, size_t workspace_bytes, void* stream) {
+    GeomK g;
+    TofK t{};
+    RaySrc src;
+    PP_TRY(make_geom(geom, g));
+    if (tof_bin) PP_TRY(make_tof(tof, t));
+    if (n < 0 || n > INT32_MAX || n_sub < 1 || n_sub > 4096) return PP_EINVAL_N;
+    PP_TRY(crystals(crystal_xyz, n_crystals, pair, n, src));
+    if (n == 0) return PP_OK;
+    if (!order || !workspace) return PP_EINVAL_PTR;
+    if (workspace_bytes < presort_workspace_bytes(n)) return PP_EINVAL_N;
+    return hip_status(launch_presort(src, tof_bin, n, g, tof_bin ? t.nb : 1, n_sub, order, workspace, workspace_bytes,
+                                     as_stream(stream)));
+}
+
+int pp_gather_crystal_events(const int32_t* pair, const int16_t* tof_bin, const int32_t* order, int64_t n,
+                             int32_t* pair_out, int16_t* tof_bin_out, void* stream) {
+    if (n < 0 || n > INT32_MAX) return PP_EINVAL_N;
+    if (n == 0) return PP_OK;
+    if (!pair || !order || !pair_out || (tof_bin && !tof_bin_out)) return PP_EINVAL_PTR;
+    if (((reinterpret_cast<uintptr_t>(pair) | reinterpret_cast<uintptr_t>(pair_out)) & 7u) != 0) return PP_EINVAL_PTR;
+    return hip_status(launch_gather_pairs(pair, tof_bin, order, n, pair_out, tof_bin_out, as_stream(stream)));
 }
 
 size_t pp_lm_presort_workspace_bytes(int64_t n) {
@@ -263,7 +368,7 @@ int pp_lm_presort(const float* xstart, const float* xend, const int16_t* tof_bin
     if (n == 0) return PP_OK;
     if (!xstart || !xend || !order || !workspace) return PP_EINVAL_PTR;
     if (workspace_bytes < presort_workspace_bytes(n)) return PP_EINVAL_N;
-    return hip_status(launch_presort(xstart, xend, tof_bin, n, g, tof_bin ? t.nb : 1, n_sub, order, workspace,
+    return hip_status(launch_presort(coords(xstart, xend), tof_bin, n, g, tof_bin ? t.nb : 1, n_sub, order, workspace,
                                      workspace_bytes, as_stream(stream)));
 }
 

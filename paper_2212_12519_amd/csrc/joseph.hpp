@@ -141,6 +141,37 @@ __device__ __forceinline__ bool ray_setup(const float* __restrict__ xs, const fl
     return lo <= hi;
 }
 
+// Where the rays' end points come from: lists of coordinates (xs, xe: [n][3] mm), or pairs of
+// crystal indices (pair: [n] of (start, end)) into a table of crystal positions (xs = the table
+// [nc][3], xe unused).  A crystal index outside [0, nc) makes its ray contribute nothing.
+struct RaySrc {
+    const float* xs;
+    const float* xe;
+    const int2* pair;
+    int nc;
+    __device__ __forceinline__ bool ends(int64_t l, const float*& s, const float*& e) const {
+        if (!pair) {
+            s = xs + 3 * l;
+            e = xe + 3 * l;
+            return true;
+        }
+        const int2 ab = pair[l];
+        if ((unsigned)ab.x >= (unsigned)nc || (unsigned)ab.y >= (unsigned)nc) return false;
+        s = xs + 3 * (int64_t)ab.x;
+        e = xs + 3 * (int64_t)ab.y;
+        return true;
+    }
+    // the rays from position k on
+    __host__ __device__ RaySrc from(int64_t k) const {
+        return pair ? RaySrc{xs, xe, pair + k, nc} : RaySrc{xs + 3 * k, xe + 3 * k, nullptr, 0};
+    }
+};
+
+__device__ __forceinline__ bool ray_setup(const RaySrc& src, int64_t l, const GeomK& g, RayK& r) {
+    const float *s, *e;
+    return src.ends(l, s, e) && ray_setup(s, e, g, r);
+}
+
 // The TOF parameters of one ray.  Without per-ray arrays these are the kernel's; with them
 // ray l has its own width (sigma_l, same n_sigmas) and/or its own centre offset, which is
 // folded into the ray's TOF coordinate (s0 -= shift) so that bin centres stay c0 + b bw.

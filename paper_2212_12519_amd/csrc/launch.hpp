@@ -10,27 +10,30 @@ namespace ppmi {
 
 struct GeomK;
 struct TofK;
+struct RaySrc;
 
-hipError_t launch_fwd(const float* xs, const float* xe, int64_t n, const GeomK& g, const float* img, float* p,
+hipError_t launch_fwd(const RaySrc& src, int64_t n, const GeomK& g, const float* img, float* p,
                       const int32_t* order, hipStream_t s);
-hipError_t launch_back(const float* xs, const float* xe, int64_t n, const GeomK& g, float* img, const float* p,
+hipError_t launch_back(const RaySrc& src, int64_t n, const GeomK& g, float* img, const float* p,
                        const int32_t* order, hipStream_t s);
-hipError_t launch_fwd_tof_sino(const float* xs, const float* xe, int64_t n, const GeomK& g, const TofK& t,
+hipError_t launch_fwd_tof_sino(const RaySrc& src, int64_t n, const GeomK& g, const TofK& t,
                                const float* img, float* p, hipStream_t s);
-hipError_t launch_back_tof_sino(const float* xs, const float* xe, int64_t n, const GeomK& g, const TofK& t,
+hipError_t launch_back_tof_sino(const RaySrc& src, int64_t n, const GeomK& g, const TofK& t,
                                 float* img, const float* p, hipStream_t s);
-hipError_t launch_fwd_tof_lm(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g,
+hipError_t launch_fwd_tof_lm(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g,
                              const TofK& t, const float* img, float* p, const int32_t* order, hipStream_t s);
-hipError_t launch_back_tof_lm(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g,
+hipError_t launch_back_tof_lm(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g,
                               const TofK& t, float* img, const float* p, const int32_t* order, hipStream_t s);
 size_t presort_workspace_bytes(int64_t n);
-hipError_t launch_presort(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g, int nb,
+hipError_t launch_presort(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g, int nb,
                           int n_sub, int32_t* order, void* ws, size_t ws_bytes, hipStream_t s);
 hipError_t launch_gather_events(const float* xs, const float* xe, const int16_t* bins, const int32_t* order, int64_t n,
                                 float* xs_out, float* xe_out, int16_t* bins_out, hipStream_t s);
+hipError_t launch_gather_pairs(const int32_t* pair, const int16_t* bins, const int32_t* order, int64_t n,
+                               int32_t* pair_out, int16_t* bins_out, hipStream_t s);
 hipError_t launch_osem_init(float* x, const float* sens, int64_t n_vox, hipStream_t s);
 
-hipError_t launch_count(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g,
+hipError_t launch_count(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g,
                         const TofK& t, int32_t* counts, hipStream_t s);
 
 int64_t osem_chunks(int64_t n_events, int32_t n_sub);

@@ -31,7 +31,8 @@ constexpr int64_t kOsemChunk = (int64_t)kSheetBlock * kOsemGroups;  // events of
 
 // live: active with steps to run, and (without the resolution model, or with its scratch image)
 __device__ __forceinline__ bool slot_live(const pp_osem_slot_t& s) {
-    return s.active && s.steps_left > 0 && (s.x_fwd == nullptr || s.tmp != nullptr);
+    return s.active && s.steps_left > 0 && (s.x_fwd == nullptr || s.tmp != nullptr) &&
+           (s.crystal_pair == nullptr || (s.crystal_xyz != nullptr && s.n_crystals > 0));
 }
 
 __host__ __device__ inline int64_t slot_chunks(int64_t n_events, int32_t n_sub) {
@@ -49,10 +50,10 @@ struct ModeOsem {
     const int16_t* __restrict__ bins;
     float bg;
     TofK t;
-    __device__ bool setup(int64_t l, const float* xs, const float* xe, const GeomK& g, RayK& r, float& cv,
+    __device__ bool setup(int64_t l, const RaySrc& src, const GeomK& g, RayK& r, float& cv,
                           int& /*aux*/) const {
         const int b = bins[l];
-        if (b < 0 || b >= t.nb || !ray_setup(xs + 3 * l, xe + 3 * l, g, r)) return false;
+        if (b < 0 || b >= t.nb || !ray_setup(src, l, g, r)) return false;
         if (!tof_window_rel(r, t.c0 + b * t.bw, t.lo, t.hi)) return false;
         float fwd = 0.0f;
         for (int k = r.k_lo; k <= r.k_hi; ++k) {
@@ -91,8 +92,10 @@ __global__ void __launch_bounds__(kSheetBlock) k_osem_accumulate(const pp_osem_s
         const int64_t q0 = (c - s.chunk_begin) * kOsemChunk;
         if (q0 >= n_j) continue;
         ModeOsem<Lut> m{s.x_fwd ? s.x_fwd : s.x, s.tof_bin + off_j, s.bg, t};
-        back_runs_chunk(m, s.xstart + 3 * off_j, s.xend + 3 * off_j, n_j, g, s.acc, nullptr, nw_lds, kOsemGroups,
-                        q0, smem);
+        const RaySrc src = s.crystal_pair ? RaySrc{s.crystal_xyz, nullptr, reinterpret_cast<const int2*>(s.crystal_pair),
+                                                   s.n_crystals}
+                                          : RaySrc{s.xstart, s.xend, nullptr, 0};
+        back_runs_chunk(m, src.from(off_j), n_j, g, s.acc, nullptr, nw_lds, kOsemGroups, q0, smem);
     }
 }
 

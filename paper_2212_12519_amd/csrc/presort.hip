@@ -30,15 +30,20 @@ struct KeyGeom {
     float z0, inv_zext;  // axial grid start and 1 / extent
 };
 
-__global__ void __launch_bounds__(256) k_lm_keys(const float* __restrict__ xs, const float* __restrict__ xe,
-                                                 const int16_t* __restrict__ bins, int64_t n, KeyGeom kg, int nb,
-                                                 int n_sub, uint64_t* __restrict__ keys, int32_t* __restrict__ idx) {
+__global__ void __launch_bounds__(256) k_lm_keys(RaySrc src, const int16_t* __restrict__ bins, int64_t n,
+                                                 KeyGeom kg, int nb, int n_sub, uint64_t* __restrict__ keys,
+                                                 int32_t* __restrict__ idx) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     idx[i] = (int32_t)i;
     const uint64_t sub = (uint64_t)(i % n_sub) << 32;
-    const float sx = xs[3 * i], sy = xs[3 * i + 1], sz = xs[3 * i + 2];
-    const float ex = xe[3 * i], ey = xe[3 * i + 1], ez = xe[3 * i + 2];
+    const float *ps, *pe;
+    if (!src.ends(i, ps, pe)) {  // crystal index out of range: no contribution, sorted last
+        keys[i] = sub | 0xffffffffull;
+        return;
+    }
+    const float sx = ps[0], sy = ps[1], sz = ps[2];
+    const float ex = pe[0], ey = pe[1], ez = pe[2];
     if (!(isfinite(sx) && isfinite(sy) && isfinite(sz) && isfinite(ex) && isfinite(ey) && isfinite(ez))) {
         keys[i] = sub | 0xffffffffull;
         return;
@@ -82,7 +87,7 @@ size_t presort_workspace_bytes(int64_t n) {
     return 2 * align256((size_t)n * 8) + align256((size_t)n * 4) + align256(sort_temp_bytes(n));
 }
 
-hipError_t launch_presort(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g, int nb,
+hipError_t launch_presort(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g, int nb,
                           int n_sub, int32_t* order, void* ws, size_t ws_bytes, hipStream_t s) {
     const size_t a8 = align256((size_t)n * 8), a4 = align256((size_t)n * 4);
     char* base = static_cast<char*>(ws);
@@ -98,7 +103,7 @@ hipError_t launch_presort(const float* xs, const float* xe, const int16_t* bins,
     kg.inv_rmax = (float)(1.0 / (0.5 * sqrt(ext0 * ext0 + ext1 * ext1) + 1e-3));
     kg.z0 = (float)(g.o[2] - 0.5 * g.h[2]);
     kg.inv_zext = (float)(1.0 / (g.n[2] * g.h[2]));
-    hipLaunchKernelGGL(k_lm_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, xs, xe, bins, n, kg, nb, n_sub,
+    hipLaunchKernelGGL(k_lm_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, bins, n, kg, nb, n_sub,
                        keys, idx);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -128,6 +133,26 @@ hipError_t launch_gather_events(const float* xs, const float* xe, const int16_t*
                                 float* xs_out, float* xe_out, int16_t* bins_out, hipStream_t s) {
     hipLaunchKernelGGL(k_gather_events, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, xs, xe, bins, order, n,
                        xs_out, xe_out, bins_out);
+    return hipGetLastError();
+}
+
+// out[i] = in[order[i]] for crystal-index events (pairs as int2; bins optional)
+__global__ void __launch_bounds__(256) k_gather_pairs(const int2* __restrict__ pair, const int16_t* __restrict__ bins,
+                                                      const int32_t* __restrict__ order, int64_t n,
+                                                      int2* __restrict__ pair_out, int16_t* __restrict__ bins_out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int64_t o = order[i];
+    const int64_t j = (o >= 0 && o < n) ? o : i;
+    pair_out[i] = pair[j];
+    if (bins) bins_out[i] = bins[j];
+}
+
+hipError_t launch_gather_pairs(const int32_t* pair, const int16_t* bins, const int32_t* order, int64_t n,
+                               int32_t* pair_out, int16_t* bins_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_pairs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       reinterpret_cast<const int2*>(pair), bins, order, n, reinterpret_cast<int2*>(pair_out),
+                       bins_out);
     return hipGetLastError();
 }
 

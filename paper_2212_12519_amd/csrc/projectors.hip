@@ -24,14 +24,14 @@ __device__ __forceinline__ int64_t ray_index(const int32_t* __restrict__ order, 
     return (l >= 0 && l < n) ? l : -1;
 }
 
-__global__ void __launch_bounds__(kBlock) k_fwd(const float* __restrict__ xs, const float* __restrict__ xe,
+__global__ void __launch_bounds__(kBlock) k_fwd(RaySrc src,
                                                 int64_t n, GeomK g, const float* __restrict__ img,
                                                 float* __restrict__ p, const int32_t* __restrict__ order) {
     const int64_t l = ray_index(order, n);
     if (l < 0) return;
     RayK r;
     float acc = 0.0f;
-    if (ray_setup(xs + 3 * l, xe + 3 * l, g, r)) {
+    if (ray_setup(src, l, g, r)) {
         for (int k = r.k_lo; k <= r.k_hi; ++k) acc += stencil_gather(img, r, stencil_at(r, k));
         acc *= r.ell;
     }
@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(kBlock) k_fwd(const float* __restrict__ xs, co
 
 // PerRay: per-ray sigma / centre offset arrays are set (TofRay in joseph.hpp)
 template <bool Lut, bool PerRay>
-__global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(const float* __restrict__ xs, const float* __restrict__ xe,
+__global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(RaySrc src,
                                                        const int16_t* __restrict__ bins, int64_t n, GeomK g,
                                                        TofK t, const float* __restrict__ img,
                                                        float* __restrict__ p, const int32_t* __restrict__ order) {
@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(const float* __restrict__
     float acc = 0.0f;
     RayK r;
     TofRay q;
-    if (b >= 0 && b < t.nb && tof_ray<PerRay>(t, l, q) && ray_setup(xs + 3 * l, xe + 3 * l, g, r)) {
+    if (b >= 0 && b < t.nb && tof_ray<PerRay>(t, l, q) && ray_setup(src, l, g, r)) {
         if (PerRay) r.s0 -= q.shift;
         if (tof_window_rel(r, t.c0 + b * t.bw, q.lo, q.hi)) {
             for (int k = r.k_lo; k <= r.k_hi; ++k) {
@@ -75,7 +75,7 @@ __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(const float* __restrict__
 // coalesced stores at the end.  PerRay: per-ray sigma / centre offset arrays are set.
 
 template <bool PerRay>
-__global__ void k_fwd_tof_sino(const float* __restrict__ xs, const float* __restrict__ xe, int64_t n, GeomK g,
+__global__ void k_fwd_tof_sino(RaySrc src, int64_t n, GeomK g,
                                TofK t, const float* __restrict__ img, float* __restrict__ p) {
     extern __shared__ float lds[];  // [nb][blockDim]
     const int nt = blockDim.x;
@@ -84,7 +84,7 @@ __global__ void k_fwd_tof_sino(const float* __restrict__ xs, const float* __rest
     for (int b = 0; b < t.nb; ++b) lds[b * nt + threadIdx.x] = 0.0f;
     RayK r;
     TofRay q;
-    if (l < n && tof_ray<PerRay>(t, l, q) && ray_setup(xs + 3 * l, xe + 3 * l, g, r)) {
+    if (l < n && tof_ray<PerRay>(t, l, q) && ray_setup(src, l, g, r)) {
         if (PerRay) r.s0 -= q.shift;
         float* mine = lds + threadIdx.x;
         for (int k = r.k_lo; k <= r.k_hi; ++k) {
@@ -120,7 +120,7 @@ __global__ void k_fwd_tof_sino(const float* __restrict__ xs, const float* __rest
 }
 
 template <bool PerRay>
-__global__ void k_back_tof_sino(const float* __restrict__ xs, const float* __restrict__ xe, int64_t n, GeomK g,
+__global__ void k_back_tof_sino(RaySrc src, int64_t n, GeomK g,
                                 TofK t, float* __restrict__ img, const float* __restrict__ p) {
     extern __shared__ float lds[];  // [nb][blockDim]: the block's projection tile, transposed
     const int nt = blockDim.x;
@@ -136,7 +136,7 @@ __global__ void k_back_tof_sino(const float* __restrict__ xs, const float* __res
     __syncthreads();
     RayK r;
     TofRay q;
-    bool ok = l < n && tof_ray<PerRay>(t, l, q) && ray_setup(xs + 3 * l, xe + 3 * l, g, r);
+    bool ok = l < n && tof_ray<PerRay>(t, l, q) && ray_setup(src, l, g, r);
     if (PerRay && ok) r.s0 -= q.shift;
     const float* mine = lds + threadIdx.x;
     if (ok) {
@@ -179,7 +179,7 @@ __global__ void k_back_tof_sino(const float* __restrict__ xs, const float* __res
 // grid; for TOF listmode (bins != nullptr) only samples strictly inside the
 // event's TOF window (non-zero weight).  Same traversal as the projectors.
 
-__global__ void __launch_bounds__(kBlock) k_count(const float* __restrict__ xs, const float* __restrict__ xe,
+__global__ void __launch_bounds__(kBlock) k_count(RaySrc src,
                                                   const int16_t* __restrict__ bins, int64_t n, GeomK g, TofK t,
                                                   int32_t* __restrict__ counts) {
     const int64_t l = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -187,7 +187,7 @@ __global__ void __launch_bounds__(kBlock) k_count(const float* __restrict__ xs, 
     int cnt = 0;
     RayK r;
     TofRay q{};
-    bool ok = ray_setup(xs + 3 * l, xe + 3 * l, g, r);
+    bool ok = ray_setup(src, l, g, r);
     double centre = 0.0;
     if (ok && bins) {
         const int b = bins[l];
@@ -214,15 +214,15 @@ __global__ void __launch_bounds__(kBlock) k_count(const float* __restrict__ xs, 
 
 static unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
-hipError_t launch_fwd(const float* xs, const float* xe, int64_t n, const GeomK& g, const float* img, float* p,
+hipError_t launch_fwd(const RaySrc& src, int64_t n, const GeomK& g, const float* img, float* p,
                       const int32_t* order, hipStream_t s) {
-    hipLaunchKernelGGL(k_fwd, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, xs, xe, n, g, img, p, order);
+    hipLaunchKernelGGL(k_fwd, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, src, n, g, img, p, order);
     return hipGetLastError();
 }
 
 // Back projections of ray lists go through the run/sheet kernel (sheet.hpp).
 template <class Mode>
-static hipError_t launch_runs(const Mode& m, const float* xs, const float* xe, int64_t n, const GeomK& g, float* img,
+static hipError_t launch_runs(const Mode& m, const RaySrc& src, int64_t n, const GeomK& g, float* img,
                               const int32_t* order, hipStream_t s) {
     const int nw = (g.n[2] <= kSheetMaxW) ? g.n[2] : 0;
     const size_t lds = SheetLayout::bytes(nw, g);
@@ -236,69 +236,68 @@ static hipError_t launch_runs(const Mode& m, const float* xs, const float* xe, i
         cus = 256;
     int64_t groups = (n + (int64_t)kSheetBlock * 4 * cus - 1) / ((int64_t)kSheetBlock * 4 * cus);
     groups = groups < 1 ? 1 : (groups > kSheetGroups ? kSheetGroups : groups);
-    hipLaunchKernelGGL(k_back_runs<Mode>, dim3(grid_for(n, kSheetBlock * groups)), dim3(kSheetBlock), lds, s, m, xs,
-                       xe, n, g, img, order, nw, (int)groups);
+    hipLaunchKernelGGL(k_back_runs<Mode>, dim3(grid_for(n, kSheetBlock * groups)), dim3(kSheetBlock), lds, s, m, src, n, g, img, order, nw, (int)groups);
     return hipGetLastError();
 }
 
-hipError_t launch_back(const float* xs, const float* xe, int64_t n, const GeomK& g, float* img, const float* p,
+hipError_t launch_back(const RaySrc& src, int64_t n, const GeomK& g, float* img, const float* p,
                        const int32_t* order, hipStream_t s) {
     ModeNonTof m{p};
-    return launch_runs(m, xs, xe, n, g, img, order, s);
+    return launch_runs(m, src, n, g, img, order, s);
 }
 
-hipError_t launch_fwd_tof_lm(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g,
+hipError_t launch_fwd_tof_lm(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g,
                              const TofK& t, const float* img, float* p, const int32_t* order, hipStream_t s) {
     const bool per = t.sig_ray || t.off_ray;
     auto* k = t.lut ? (per ? k_fwd_tof_lm<true, true> : k_fwd_tof_lm<true, false>)
                     : (per ? k_fwd_tof_lm<false, true> : k_fwd_tof_lm<false, false>);
-    hipLaunchKernelGGL(k, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, xs, xe, bins, n, g, t, img, p, order);
+    hipLaunchKernelGGL(k, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, src, bins, n, g, t, img, p, order);
     return hipGetLastError();
 }
 
-hipError_t launch_back_tof_lm(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g,
+hipError_t launch_back_tof_lm(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g,
                               const TofK& t, float* img, const float* p, const int32_t* order, hipStream_t s) {
     if (t.sig_ray || t.off_ray) {
-        if (t.lut) return launch_runs(ModeTofLm<true, true>{p, bins, t}, xs, xe, n, g, img, order, s);
-        return launch_runs(ModeTofLm<false, true>{p, bins, t}, xs, xe, n, g, img, order, s);
+        if (t.lut) return launch_runs(ModeTofLm<true, true>{p, bins, t}, src, n, g, img, order, s);
+        return launch_runs(ModeTofLm<false, true>{p, bins, t}, src, n, g, img, order, s);
     }
-    if (t.lut) return launch_runs(ModeTofLm<true>{p, bins, t}, xs, xe, n, g, img, order, s);
-    return launch_runs(ModeTofLm<false>{p, bins, t}, xs, xe, n, g, img, order, s);
+    if (t.lut) return launch_runs(ModeTofLm<true>{p, bins, t}, src, n, g, img, order, s);
+    return launch_runs(ModeTofLm<false>{p, bins, t}, src, n, g, img, order, s);
 }
 
 static int sino_block(int nb) { return nb <= 64 ? 256 : 64; }  // LDS tile <= 64 KiB
 
-hipError_t launch_fwd_tof_sino(const float* xs, const float* xe, int64_t n, const GeomK& g, const TofK& t,
+hipError_t launch_fwd_tof_sino(const RaySrc& src, int64_t n, const GeomK& g, const TofK& t,
                                const float* img, float* p, hipStream_t s) {
     const int blk = sino_block(t.nb);
     const size_t lds = (size_t)t.nb * blk * sizeof(float);
     hipLaunchKernelGGL((t.sig_ray || t.off_ray) ? k_fwd_tof_sino<true> : k_fwd_tof_sino<false>, dim3(grid_for(n, blk)),
-                       dim3(blk), lds, s, xs, xe, n, g, t, img, p);
+                       dim3(blk), lds, s, src, n, g, t, img, p);
     return hipGetLastError();
 }
 
-hipError_t launch_back_tof_sino(const float* xs, const float* xe, int64_t n, const GeomK& g, const TofK& t,
+hipError_t launch_back_tof_sino(const RaySrc& src, int64_t n, const GeomK& g, const TofK& t,
                                 float* img, const float* p, hipStream_t s) {
     // the run/sheet kernel carries ray indices in 32 bits
     const bool per = t.sig_ray || t.off_ray;
     if (n < (int64_t(1) << 31)) {
         if (per) {
-            if (t.lut) return launch_runs(ModeTofSino<true, true>{p, t}, xs, xe, n, g, img, nullptr, s);
-            return launch_runs(ModeTofSino<false, true>{p, t}, xs, xe, n, g, img, nullptr, s);
+            if (t.lut) return launch_runs(ModeTofSino<true, true>{p, t}, src, n, g, img, nullptr, s);
+            return launch_runs(ModeTofSino<false, true>{p, t}, src, n, g, img, nullptr, s);
         }
-        if (t.lut) return launch_runs(ModeTofSino<true>{p, t}, xs, xe, n, g, img, nullptr, s);
-        return launch_runs(ModeTofSino<false>{p, t}, xs, xe, n, g, img, nullptr, s);
+        if (t.lut) return launch_runs(ModeTofSino<true>{p, t}, src, n, g, img, nullptr, s);
+        return launch_runs(ModeTofSino<false>{p, t}, src, n, g, img, nullptr, s);
     }
     const int blk = sino_block(t.nb);
     const size_t lds = (size_t)t.nb * blk * sizeof(float);
     hipLaunchKernelGGL(per ? k_back_tof_sino<true> : k_back_tof_sino<false>, dim3(grid_for(n, blk)), dim3(blk), lds, s,
-                       xs, xe, n, g, t, img, p);
+                       src, n, g, t, img, p);
     return hipGetLastError();
 }
 
-hipError_t launch_count(const float* xs, const float* xe, const int16_t* bins, int64_t n, const GeomK& g,
+hipError_t launch_count(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g,
                         const TofK& t, int32_t* counts, hipStream_t s) {
-    hipLaunchKernelGGL(k_count, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, xs, xe, bins, n, g, t, counts);
+    hipLaunchKernelGGL(k_count, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, src, bins, n, g, t, counts);
     return hipGetLastError();
 }
 

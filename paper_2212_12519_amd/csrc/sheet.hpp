@@ -62,10 +62,10 @@ struct SheetLayout {
 struct ModeNonTof {
     static constexpr bool kAux = false;
     const float* __restrict__ p;
-    __device__ bool setup(int64_t l, const float* xs, const float* xe, const GeomK& g, RayK& r, float& cv,
+    __device__ bool setup(int64_t l, const RaySrc& src, const GeomK& g, RayK& r, float& cv,
                           int& /*aux*/) const {
         const float pl = p[l];
-        if (pl == 0.0f || !ray_setup(xs + 3 * l, xe + 3 * l, g, r)) return false;
+        if (pl == 0.0f || !ray_setup(src, l, g, r)) return false;
         cv = r.ell * pl;
         return true;
     }
@@ -80,12 +80,12 @@ struct ModeTofLm {
     const float* __restrict__ p;
     const int16_t* __restrict__ bins;
     TofK t;
-    __device__ bool setup(int64_t l, const float* xs, const float* xe, const GeomK& g, RayK& r, float& cv,
+    __device__ bool setup(int64_t l, const RaySrc& src, const GeomK& g, RayK& r, float& cv,
                           int& aux) const {
         const int b = bins[l];
         const float pl = p[l];
         TofRay q;
-        if (b < 0 || b >= t.nb || pl == 0.0f || !tof_ray<PerRay>(t, l, q) || !ray_setup(xs + 3 * l, xe + 3 * l, g, r))
+        if (b < 0 || b >= t.nb || pl == 0.0f || !tof_ray<PerRay>(t, l, q) || !ray_setup(src, l, g, r))
             return false;
         if (PerRay) r.s0 -= q.shift;
         if (!tof_window_rel(r, t.c0 + b * t.bw, q.lo, q.hi)) return false;
@@ -108,13 +108,13 @@ struct ModeTofSino {
     static constexpr bool kAux = true;
     const float* __restrict__ p;  // [n][n_bins]
     TofK t;
-    __device__ bool setup(int64_t l, const float* xs, const float* xe, const GeomK& g, RayK& r, float& cv,
+    __device__ bool setup(int64_t l, const RaySrc& src, const GeomK& g, RayK& r, float& cv,
                           int& aux) const {
         const float* pr = p + l * t.nb;
         bool any = false;
         for (int b = 0; b < t.nb; ++b) any |= (pr[b] != 0.0f);
         TofRay q;
-        if (!any || !tof_ray<PerRay>(t, l, q) || !ray_setup(xs + 3 * l, xe + 3 * l, g, r)) return false;
+        if (!any || !tof_ray<PerRay>(t, l, q) || !ray_setup(src, l, g, r)) return false;
         if (PerRay) r.s0 -= q.shift;
         cv = r.ell;
         aux = (int)l;
@@ -206,7 +206,7 @@ __device__ __forceinline__ void sheet_flush(float* __restrict__ img, float* col,
 // the column of absolute plane t, so lines need n_p <= 256); it is flushed when a
 // run of another line starts, and at the end.
 template <class Mode>
-__device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, const float* __restrict__ xe, int64_t n,
+__device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
                                 const GeomK& g, float* __restrict__ img, const int32_t* __restrict__ order,
                                 int nw_lds, int groups, int64_t chunk0, double* smem) {
     constexpr int B = kSheetBlock;
@@ -252,7 +252,7 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
         RayK r;
         float cv = 0.0f;
         int ax = 0;
-        const bool ok = l >= 0 && m.setup(l, xs, xe, g, r, cv, ax);
+        const bool ok = l >= 0 && m.setup(l, src, g, r, cv, ax);
         // compact the valid rays to the front of the group (stable order), so that rays
         // without a contribution do not break runs
         const unsigned long long vb = __ballot(ok);
@@ -465,13 +465,12 @@ __device__ void back_runs_chunk(const Mode& m, const float* __restrict__ xs, con
 }
 
 template <class Mode>
-__global__ void __launch_bounds__(kSheetBlock) k_back_runs(Mode m, const float* __restrict__ xs,
-                                                          const float* __restrict__ xe, int64_t n, GeomK g,
+__global__ void __launch_bounds__(kSheetBlock) k_back_runs(Mode m, RaySrc src, int64_t n, GeomK g,
                                                           float* __restrict__ img, const int32_t* __restrict__ order,
                                                           int nw_lds, int groups) {
     extern __shared__ double smem[];
     const int64_t chunk0 = (int64_t)blockIdx.x * groups * kSheetBlock;
-    back_runs_chunk(m, xs, xe, n, g, img, order, nw_lds, groups, chunk0, smem);
+    back_runs_chunk(m, src, n, g, img, order, nw_lds, groups, chunk0, smem);
 }
 
 }  // namespace ppmi

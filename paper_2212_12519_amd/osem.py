@@ -21,7 +21,7 @@ import ctypes
 import torch
 
 from ._lib import COsemSlot, as_geom, as_tof, check, load, ptr, stream_of
-from .projectors import back, fwhm3, gather_events, pp_gauss3d, presort
+from .projectors import back, fwhm3, gather_crystal_events, gather_events, pp_gauss3d, presort, presort_crystals
 
 SLOT_BYTES = ctypes.sizeof(COsemSlot)
 RES_FWHM_MM = 4.5  # the paper's resolution model
@@ -31,6 +31,12 @@ def prepare_frame(xstart, xend, tof_bin, geom, tof, n_sub):
     """Device copies of a frame's events in subset-major order, presorted inside each subset."""
     order = presort(xstart, xend, geom, tof_bin, tof, n_sub=n_sub)
     return gather_events(xstart, xend, tof_bin, order)
+
+
+def prepare_crystal_frame(crystal_xyz, pair, tof_bin, geom, tof, n_sub):
+    """prepare_frame for crystal-index events: (pair, tof_bin) in subset-major, presorted order."""
+    order = presort_crystals(crystal_xyz, pair, geom, tof_bin, tof, n_sub=n_sub)
+    return gather_crystal_events(pair, tof_bin, order)
 
 
 def sensitivity(lor_start, lor_end, geom, chunk=1 << 26, res_fwhm=None):
@@ -60,22 +66,35 @@ class SlotTable:
         self.dev = torch.zeros(self.capacity * SLOT_BYTES, dtype=torch.uint8, device=device)
         self._copied = None
 
-    def set(self, i, xs, xe, tb, x, acc, sens, n_sub, steps, bg, x_fwd=None, tmp=None):
+    def set(self, i, xs, xe, tb, x, acc, sens, n_sub, steps, bg, x_fwd=None, tmp=None, n_events=None):
         """Slot i <- a frame.  x_fwd and tmp (both or neither): the resolution model's G x (set
         before the first step) and its scratch image."""
         if (x_fwd is None) != (tmp is None):
             raise ValueError("x_fwd and tmp go together")
+        self.clear(i)
         s = self.host[i]
-        s.xstart, s.xend, s.tof_bin = xs.data_ptr(), xe.data_ptr(), tb.data_ptr()
+        s.xstart = None if xs is None else xs.data_ptr()
+        s.xend = None if xe is None else xe.data_ptr()
+        s.tof_bin = tb.data_ptr()
         s.x, s.acc, s.sens = x.data_ptr(), acc.data_ptr(), sens.data_ptr()
         s.x_fwd = None if x_fwd is None else x_fwd.data_ptr()
         s.tmp = None if tmp is None else tmp.data_ptr()
-        s.n_events = xs.shape[0]
+        s.n_events = xs.shape[0] if n_events is None else int(n_events)
         s.bg = float(bg)
         s.n_sub = int(n_sub)
         s.subset = 0
         s.steps_left = int(steps)
         s.active = 1
+
+    def set_crystals(self, i, crystal_xyz, pair, tb, x, acc, sens, n_sub, steps, bg, x_fwd=None, tmp=None):
+        """Slot i <- a frame of crystal-index events (pair [n, 2] int32 into crystal_xyz)."""
+        if pair.dtype != torch.int32 or pair.dim() != 2 or pair.shape[1] != 2 or pair.data_ptr() % 8:
+            raise ValueError("pair must be 8-byte aligned int32 [n, 2]")
+        if crystal_xyz.dtype != torch.float32 or crystal_xyz.dim() != 2 or crystal_xyz.shape[1] != 3:
+            raise ValueError("crystal_xyz must be float32 [n_crystals, 3]")
+        self.set(i, None, None, tb, x, acc, sens, n_sub, steps, bg, x_fwd, tmp, n_events=pair.shape[0])
+        s = self.host[i]
+        s.crystal_pair, s.crystal_xyz, s.n_crystals = pair.data_ptr(), crystal_xyz.data_ptr(), crystal_xyz.shape[0]
 
     def clear(self, i):
         ctypes.memset(ctypes.addressof(self.host[i]), 0, SLOT_BYTES)
@@ -141,6 +160,24 @@ def res_buffers(x, geom, res_fwhm):
     x_fwd, tmp = torch.empty_like(x), torch.empty_like(x)
     pp_gauss3d(x, x_fwd, tmp, geom, res_fwhm)
     return x_fwd, tmp
+
+
+def lm_osem_crystals(crystal_xyz, pair, tof_bin, geom, tof, sens, n_iter, n_sub, bg=0.1, x0=None, res_fwhm=None):
+    """lm_osem for crystal-index events (pair [n, 2] int32 into crystal_xyz [n_crystals, 3])."""
+    g = as_geom(geom)
+    pr, tb = prepare_crystal_frame(crystal_xyz, pair, tof_bin, g, tof, n_sub)
+    x = init_image(sens) if x0 is None else x0.clone()
+    acc = torch.zeros_like(sens)
+    x_fwd = tmp = None
+    if res_fwhm is not None:
+        x_fwd, tmp = res_buffers(x, g, res_fwhm)
+    table = SlotTable(1, pair.device)
+    table.set_crystals(0, crystal_xyz, pr, tb, x, acc, sens, n_sub, n_iter * n_sub, bg, x_fwd, tmp)
+    table.upload()
+    osem_steps(table, g, tof, n_iter * n_sub, res_fwhm)
+    torch.cuda.current_stream(x.device).synchronize()
+    del pr, tb
+    return x
 
 
 def lm_osem(xstart, xend, tof_bin, geom, tof, sens, n_iter, n_sub, bg=0.1, x0=None, res_fwhm=None):

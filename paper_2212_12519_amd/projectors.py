@@ -11,7 +11,9 @@ import math
 
 import torch
 
-from ._lib import TofParams, _bins, _dev, _img, _order, _rays, as_geom, as_tof, check, load, ptr, stream_of
+from ._lib import (TofParams, _bins, _crystal_events, _dev, _img, _order, _rays, as_geom, as_tof, check, load, ptr,
+                   stream_of)
+
 
 def pp_fwd(xstart, xend, geom, img, p, order=None):
     """Non-TOF forward projection into p[n] (overwritten). Sec. 2.1 of the paper.
@@ -258,3 +260,143 @@ def back_tof_lm(xstart, xend, tof_bin, geom, tof, p, img=None, order=None):
     if img is None:
         img = torch.zeros(g.dim, dtype=torch.float32, device=xstart.device)
     return pp_back_tof_lm(xstart, xend, tof_bin, g, tof, img, p, order)
+
+
+# ----------------------------------------------------- crystal-index events
+#
+# Events given as (start crystal, end crystal) index pairs into a table of crystal positions;
+# each entry point computes exactly what its coordinate counterpart computes for
+# crystal_xyz[pair[:, 0]], crystal_xyz[pair[:, 1]].
+
+def pp_fwd_crystals(crystal_xyz, pair, geom, img, p, order=None):
+    g = as_geom(geom)
+    _dev(crystal_xyz, pair, img, p, order)
+    n, nc = _crystal_events(crystal_xyz, pair)
+    _img(img, g)
+    _order(order, n)
+    if p.dtype != torch.float32 or p.numel() != n:
+        raise ValueError("p must be float32 [n]")
+    check(load().pp_fwd_crystals(ptr(crystal_xyz), nc, ptr(pair), n, g.c(), ptr(img), ptr(p), ptr(order),
+                                 stream_of(p)))
+    return p
+
+
+def pp_back_crystals(crystal_xyz, pair, geom, img, p, order=None):
+    g = as_geom(geom)
+    _dev(crystal_xyz, pair, img, p, order)
+    n, nc = _crystal_events(crystal_xyz, pair)
+    _img(img, g)
+    _order(order, n)
+    if p.dtype != torch.float32 or p.numel() != n:
+        raise ValueError("p must be float32 [n]")
+    check(load().pp_back_crystals(ptr(crystal_xyz), nc, ptr(pair), n, g.c(), ptr(img), ptr(p), ptr(order),
+                                  stream_of(img)))
+    return img
+
+
+def pp_fwd_tof_lm_crystals(crystal_xyz, pair, tof_bin, geom, tof, img, p, order=None):
+    g, t = as_geom(geom), as_tof(tof)
+    _dev(crystal_xyz, pair, tof_bin, img, p, order, t.sigma_per_ray, t.offset_per_ray)
+    n, nc = _crystal_events(crystal_xyz, pair)
+    _bins(tof_bin, n)
+    _img(img, g)
+    _order(order, n)
+    if p.dtype != torch.float32 or p.numel() != n:
+        raise ValueError("p must be float32 [n]")
+    check(load().pp_fwd_tof_lm_crystals(ptr(crystal_xyz), nc, ptr(pair), ptr(tof_bin), n, g.c(), t.c(n), ptr(img),
+                                        ptr(p), ptr(order), stream_of(p)))
+    return p
+
+
+def pp_back_tof_lm_crystals(crystal_xyz, pair, tof_bin, geom, tof, img, p, order=None):
+    g, t = as_geom(geom), as_tof(tof)
+    _dev(crystal_xyz, pair, tof_bin, img, p, order, t.sigma_per_ray, t.offset_per_ray)
+    n, nc = _crystal_events(crystal_xyz, pair)
+    _bins(tof_bin, n)
+    _img(img, g)
+    _order(order, n)
+    if p.dtype != torch.float32 or p.numel() != n:
+        raise ValueError("p must be float32 [n]")
+    check(load().pp_back_tof_lm_crystals(ptr(crystal_xyz), nc, ptr(pair), ptr(tof_bin), n, g.c(), t.c(n), ptr(img),
+                                         ptr(p), ptr(order), stream_of(img)))
+    return img
+
+
+def pp_lm_presort_crystals(crystal_xyz, pair, tof_bin, geom, tof, order, workspace, n_sub=1):
+    """pp_lm_presort for crystal-index events (same key, same order)."""
+    g = as_geom(geom)
+    _dev(crystal_xyz, pair, tof_bin, order, workspace)
+    n, nc = _crystal_events(crystal_xyz, pair)
+    _order(order, n)
+    tc = None
+    if tof_bin is not None:
+        _bins(tof_bin, n)
+        tc = as_tof(tof).c(n)
+    check(load().pp_lm_presort_crystals(ptr(crystal_xyz), nc, ptr(pair), ptr(tof_bin), n, g.c(), tc, int(n_sub),
+                                        ptr(order), ptr(workspace), workspace.numel() * workspace.element_size(),
+                                        stream_of(order)))
+    return order
+
+
+def presort_crystals(crystal_xyz, pair, geom, tof_bin=None, tof=None, n_sub=1):
+    order = torch.empty(pair.shape[0], dtype=torch.int32, device=pair.device)
+    if pair.shape[0] == 0:
+        return order
+    return pp_lm_presort_crystals(crystal_xyz, pair, tof_bin, geom, tof, order,
+                                  presort_workspace(pair.shape[0], pair.device), n_sub)
+
+
+def count_samples_crystals(crystal_xyz, pair, geom, tof_bin=None, tof=None):
+    g = as_geom(geom)
+    _dev(crystal_xyz, pair, tof_bin)
+    n, nc = _crystal_events(crystal_xyz, pair)
+    counts = torch.empty(n, dtype=torch.int32, device=pair.device)
+    tc = None
+    if tof_bin is not None:
+        _bins(tof_bin, n)
+        t = as_tof(tof)
+        _dev(pair, t.sigma_per_ray, t.offset_per_ray)
+        tc = t.c(n)
+    check(load().pp_count_samples_crystals(ptr(crystal_xyz), nc, ptr(pair), ptr(tof_bin), n, g.c(), tc, ptr(counts),
+                                           stream_of(counts)))
+    return counts
+
+
+def gather_crystal_events(pair, tof_bin, order):
+    """(pair[order], tof_bin[order]) as new tensors (tof_bin may be None)."""
+    _dev(pair, tof_bin, order)
+    if pair.dtype != torch.int32 or pair.dim() != 2 or pair.shape[1] != 2:
+        raise ValueError("pair must be int32 [n, 2]")
+    n = pair.shape[0]
+    _order(order, n)
+    if tof_bin is not None:
+        _bins(tof_bin, n)
+    pair_out = torch.empty_like(pair)
+    tb_out = None if tof_bin is None else torch.empty_like(tof_bin)
+    check(load().pp_gather_crystal_events(ptr(pair), ptr(tof_bin), ptr(order), n, ptr(pair_out), ptr(tb_out),
+                                          stream_of(pair_out)))
+    return pair_out, tb_out
+
+
+def fwd_crystals(crystal_xyz, pair, geom, img, order=None):
+    p = torch.empty(pair.shape[0], dtype=torch.float32, device=pair.device)
+    return pp_fwd_crystals(crystal_xyz, pair, geom, img, p, order)
+
+
+def back_crystals(crystal_xyz, pair, geom, p, img=None, order=None):
+    g = as_geom(geom)
+    if img is None:
+        img = torch.zeros(g.dim, dtype=torch.float32, device=pair.device)
+    return pp_back_crystals(crystal_xyz, pair, g, img, p, order)
+
+
+def fwd_tof_lm_crystals(crystal_xyz, pair, tof_bin, geom, tof, img, order=None):
+    p = torch.empty(pair.shape[0], dtype=torch.float32, device=pair.device)
+    return pp_fwd_tof_lm_crystals(crystal_xyz, pair, tof_bin, geom, tof, img, p, order)
+
+
+def back_tof_lm_crystals(crystal_xyz, pair, tof_bin, geom, tof, p, img=None, order=None):
+    g = as_geom(geom)
+    if img is None:
+        img = torch.zeros(g.dim, dtype=torch.float32, device=pair.device)
+    return pp_back_tof_lm_crystals(crystal_xyz, pair, tof_bin, g, tof, img, p, order)

@@ -38,8 +38,11 @@ def _rng(seed, device):
 def generate_tof_lm_events(scanner: CylinderScanner, n_rad: int, max_rd: int, grid: ImageGrid,
                            image: torch.Tensor, n_events: int, seed: int, tof_bin_width: float,
                            tof_sigma: float, n_tof_bins: int, device="cpu", chunk=None,
-                           return_points=False):
-    """Returns (xstart float32 [n,3], xend float32 [n,3], tof_bin int16 [n]) on ``device``."""
+                           return_points=False, return_crystals=False):
+    """Returns (xstart float32 [n,3], xend float32 [n,3], tof_bin int16 [n]) on ``device``; with
+    return_points also the emission points (float64 [n,3]), with return_crystals also the
+    crystal indices of the end points (int32 [n,2], index ring * n_crystals + crystal into
+    ``scanner.crystal_table()``, whose rows are bit-identical to xstart / xend)."""
     device = torch.device(device)
     g = _rng(seed, device)
     w = image.to(device=device, dtype=torch.float64).reshape(-1)
@@ -110,6 +113,8 @@ def generate_tof_lm_events(scanner: CylinderScanner, n_rad: int, max_rd: int, gr
         piece = [xs[take].to(torch.float32), xe[take].to(torch.float32), tb[take].to(torch.int16)]
         if return_points:
             piece.append(p[take])
+        if return_crystals:
+            piece.append(torch.stack([ri[take] * N + ci[take], rj[take] * N + cj[take]], 1).to(torch.int32))
         outs.append(piece)
         n_have += take.numel()
     res = [torch.cat([o[k] for o in outs]).contiguous() for k in range(len(outs[0]))]

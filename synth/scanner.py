@@ -59,6 +59,12 @@ class CylinderScanner:
         z = (ring.to(torch.float64) - 0.5 * (self.n_rings - 1)) * self.ring_pitch
         return torch.stack([self.radius * torch.cos(phi), self.radius * torch.sin(phi), z], dim=-1)
 
+    def crystal_table(self, device="cpu") -> torch.Tensor:
+        """float32 [n_rings * n_crystals, 3]: row ring * n_crystals + crystal is that crystal's centre."""
+        ring = torch.arange(self.n_rings).repeat_interleave(self.n_crystals)
+        crystal = torch.arange(self.n_crystals).repeat(self.n_rings)
+        return self.crystal_xyz(ring, crystal).to(torch.float32).contiguous().to(device)
+
     def sinogram_shape(self, n_rad: int, max_rd: int):
         return (n_rad, self.n_crystals // 2, int(sinogram_planes(self.n_rings, max_rd).shape[0]))
 

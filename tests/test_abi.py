@@ -29,7 +29,7 @@ def test_exports_every_declared_symbol(lib):
     assert len(names) >= 12, names
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.pp_abi_version() == 4
+    assert lib.pp_abi_version() == 5
 
 
 def _geom(dim=(4, 4, 4), vs=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0)):
@@ -87,6 +87,21 @@ def test_error_codes(lib):
         assert lib.pp_lm_osem_accumulate(DUMMY, 3, g, t, None) == PP_EINVAL_TOF
         assert lib.pp_fwd_tof_lm(DUMMY, DUMMY, DUMMY, 0, g, t, DUMMY, DUMMY, None, None) == PP_OK
     assert lib.pp_fwd_tof_lm(DUMMY, DUMMY, None, 5, g, _tof(), DUMMY, DUMMY, None, None) == PP_EINVAL_PTR
+    # crystal-index events: table size, pointers, 8-byte alignment of the pairs
+    assert lib.pp_fwd_crystals(DUMMY, 0, DUMMY, 5, g, DUMMY2, DUMMY3, None, None) == PP_EINVAL_N
+    assert lib.pp_fwd_crystals(None, 10, DUMMY, 5, g, DUMMY2, DUMMY3, None, None) == PP_EINVAL_PTR
+    assert lib.pp_back_crystals(DUMMY, 10, None, 5, g, DUMMY2, DUMMY3, None, None) == PP_EINVAL_PTR
+    assert lib.pp_back_crystals(DUMMY, 10, ctypes.c_void_p(20), 5, g, DUMMY2, DUMMY3, None, None) == PP_EINVAL_PTR
+    assert lib.pp_fwd_crystals(DUMMY, 10, DUMMY, 0, g, DUMMY2, DUMMY3, None, None) == PP_OK
+    assert lib.pp_fwd_tof_lm_crystals(DUMMY, 10, DUMMY, None, 5, g, _tof(), DUMMY2, DUMMY3, None, None) == \
+        PP_EINVAL_PTR
+    assert lib.pp_back_tof_lm_crystals(DUMMY, 10, DUMMY, DUMMY, 5, g, _tof(nb=0), DUMMY2, DUMMY3, None, None) == \
+        PP_EINVAL_TOF
+    assert lib.pp_count_samples_crystals(DUMMY, -1, DUMMY, None, 5, g, None, DUMMY2, None) == PP_EINVAL_N
+    assert lib.pp_lm_presort_crystals(DUMMY, 10, DUMMY, None, 1000, g, None, 1, DUMMY2, DUMMY3, 1, None) == \
+        PP_EINVAL_N  # workspace too small
+    assert lib.pp_gather_crystal_events(DUMMY, None, DUMMY2, 10, ctypes.c_void_p(36), None, None) == PP_EINVAL_PTR
+    assert lib.pp_gather_crystal_events(DUMMY, DUMMY, DUMMY2, 10, DUMMY3, None, None) == PP_EINVAL_PTR
     assert lib.pp_fwd_tof_lm(DUMMY, DUMMY, DUMMY, 5, g, None, DUMMY, DUMMY, None, None) == PP_EINVAL_PTR
     assert lib.pp_lm_osem_accumulate(DUMMY, -1, g, _tof(), None) == PP_EINVAL_N
     assert lib.pp_lm_osem_accumulate(DUMMY, 0, g, _tof(), None) == PP_OK

@@ -1,0 +1,137 @@
+"""Crystal-index listmode events (index-based LOR geometry): events as (start, end) crystal
+index pairs into a table of crystal positions.  Each entry point must compute what its
+coordinate counterpart computes for the table rows the pairs select -- the forward projection
+bit-identically (same float32 end points, same arithmetic), the presort order identically, the
+back projection up to the order of float atomic adds -- and match the FP64 oracle run on those
+coordinates.  Pairs with an index outside the table contribute nothing."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from helpers import geom_of, rel_l2, tof_of
+from synth import configs as C
+from synth import generate_tof_lm_events
+
+pytestmark = pytest.mark.gpu
+FWD_TOL, BACK_TOL, ADJ_TOL, OSEM_TOL = 1e-5, 1e-4, 1e-5, 1e-4
+
+
+def np64(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def small(gpu):
+    img = C.phantom_small()
+    t = C.TOF_CLIN
+    xs, xe, bins, pair = generate_tof_lm_events(C.SCANNER_SMALL, C.SINO_SMALL.n_rad, C.SINO_SMALL.max_rd,
+                                                C.GRID_SMALL, img, 50_003, seed=111, tof_bin_width=t.bin_width,
+                                                tof_sigma=t.sigma, n_tof_bins=t.n_bins, return_crystals=True)
+    table = C.SCANNER_SMALL.crystal_table()
+    assert torch.equal(table[pair[:, 0].long()], xs) and torch.equal(table[pair[:, 1].long()], xe)
+    # a few events with an index outside the table
+    nc = table.shape[0]
+    pair[3, 0], pair[7, 1], pair[11, 0], pair[13, 1] = -1, nc, 2**31 - 1, -(2**31)
+    g = geom_of(C.GRID_SMALL)
+    G = gpu.ImageGeom(g["dim"], g["voxsize"], g["origin"])
+    T = gpu.TofParams(t.bin_width, t.sigma, t.n_sigmas, t.n_bins)
+    return xs, xe, bins, pair, table, img, g, G, T, tof_of(t)
+
+
+BAD = [3, 7, 11, 13]
+
+
+def test_crystal_listmode_equals_coordinates_and_oracle(gpu, small):
+    xs, xe, bins, pair, table, img, g, G, T, tof = small
+    d = torch.device("cuda")
+    ok = torch.ones(xs.shape[0], dtype=torch.bool)
+    ok[BAD] = False
+    tab_d, pair_d, b_d, img_d = table.to(d), pair.to(d), bins.to(d), img.to(d)
+    p = gpu.fwd_tof_lm_crystals(tab_d, pair_d, b_d, G, T, img_d)
+    pc = gpu.fwd_tof_lm(xs.to(d), xe.to(d), b_d, G, T, img_d)
+    assert torch.equal(p[ok.to(d)], pc[ok.to(d)])  # same rays, same arithmetic: bit-identical
+    assert not torch.any(p[BAD])
+    ref = oracle.fwd_tof_lm(xs.numpy(), xe.numpy(), g["origin"], g["voxsize"], g["dim"], tof, bins.numpy(),
+                            img.numpy().astype(np.float64))
+    ref[BAD] = 0.0
+    assert rel_l2(np64(p), ref) <= FWD_TOL
+    y = torch.rand(xs.shape[0], generator=torch.Generator().manual_seed(112))
+    y_ok = torch.where(ok, y, torch.zeros_like(y))
+    bk = gpu.back_tof_lm_crystals(tab_d, pair_d, b_d, G, T, y.to(d))
+    bref = oracle.back_tof_lm(xs.numpy(), xe.numpy(), g["origin"], g["voxsize"], g["dim"], tof, bins.numpy(),
+                              y_ok.numpy().astype(np.float64))
+    assert rel_l2(np64(bk), bref) <= BACK_TOL
+    lhs, rhs = float(np.dot(np64(p), y.numpy())), float(np.sum(np64(bk) * img.numpy()))
+    assert abs(lhs - rhs) <= ADJ_TOL * abs(lhs)
+    # presort: the same key from the same float32 end points, so the same order (for valid events)
+    order = gpu.presort_crystals(tab_d, pair_d, G, b_d, T)
+    order_c = gpu.presort(xs.to(d), xe.to(d), G, b_d, T)
+    n_ok = int(ok.sum())
+    o, oc = order.cpu(), order_c.cpu()
+    assert set(o[n_ok:].tolist()) == set(BAD)  # invalid pairs sort last
+    assert torch.equal(o[:n_ok], oc[ok[oc.long()]])
+    bk2 = gpu.back_tof_lm_crystals(tab_d, pair_d, b_d, G, T, y.to(d), order=order)
+    assert rel_l2(np64(bk2), bref) <= BACK_TOL
+    p2 = gpu.fwd_tof_lm_crystals(tab_d, pair_d, b_d, G, T, img_d, order=order)
+    assert torch.equal(p2, p)
+    cnt = gpu.count_samples_crystals(tab_d, pair_d, G, b_d, T)
+    cnt_c = gpu.count_samples(xs.to(d), xe.to(d), G, b_d, T)
+    assert torch.equal(cnt[ok.to(d)], cnt_c[ok.to(d)]) and not torch.any(cnt[BAD])
+
+
+def test_crystal_nontof_equals_coordinates(gpu, small):
+    xs, xe, bins, pair, table, img, g, G, T, tof = small
+    d = torch.device("cuda")
+    ok = torch.ones(xs.shape[0], dtype=torch.bool)
+    ok[BAD] = False
+    tab_d, pair_d, img_d = table.to(d), pair.to(d), img.to(d)
+    p = gpu.fwd_crystals(tab_d, pair_d, G, img_d)
+    pc = gpu.fwd(xs.to(d), xe.to(d), G, img_d)
+    assert torch.equal(p[ok.to(d)], pc[ok.to(d)]) and not torch.any(p[BAD])
+    y = torch.rand(xs.shape[0], generator=torch.Generator().manual_seed(113)).to(d)
+    bk = gpu.back_crystals(tab_d, pair_d, G, y)
+    bkc = gpu.back(xs[ok].to(d), xe[ok].to(d), G, y[ok.to(d)])
+    assert rel_l2(np64(bk), np64(bkc)) <= 1e-6
+
+
+def test_crystal_osem_matches_oracle(gpu, small):
+    from paper_2212_12519_amd import osem
+
+    xs, xe, bins, pair, table, img, g, G, T, tof = small
+    d = torch.device("cuda")
+    good = torch.ones(xs.shape[0], dtype=torch.bool)
+    good[BAD] = False
+    xs, xe, bins, pair = xs[good], xe[good], bins[good], pair[good].contiguous()
+    lxs, lxe = C.SINO_SMALL.lors()
+    sens = osem.sensitivity(lxs.to(d), lxe.to(d), G)
+    x = osem.lm_osem_crystals(table.to(d), pair.to(d), bins.to(d), G, T, sens, n_iter=2, n_sub=4, bg=0.1)
+    xc = osem.lm_osem(xs.to(d), xe.to(d), bins.to(d), G, T, sens, n_iter=2, n_sub=4, bg=0.1)
+    assert rel_l2(np64(x), np64(xc)) <= 1e-5
+    sens_ref = oracle.back(lxs.numpy(), lxe.numpy(), g["origin"], g["voxsize"], g["dim"], np.ones(lxs.shape[0]))
+    x_ref = oracle.lm_osem(xs.numpy(), xe.numpy(), bins.numpy(), g["origin"], g["voxsize"], g["dim"], tof,
+                           sens_ref, 0.1, 2, 4, (sens_ref > 0).astype(np.float64))
+    assert rel_l2(np64(x), x_ref) <= OSEM_TOL
+
+
+def test_crystal_clinical_equals_coordinates(gpu):
+    """4M clinical events at full size in the launch configuration of the benchmark (presorted):
+    crystal-index forward bit-identical to the coordinate forward, back projection equal up to
+    the order of atomic adds, the presort order identical."""
+    d = torch.device("cuda")
+    t = C.TOF_CLIN
+    img = C.phantom_clin(device=d)
+    xs, xe, bins, pair = generate_tof_lm_events(C.SCANNER_CLIN, C.SINO_CLIN.n_rad, C.SINO_CLIN.max_rd, C.GRID_CLIN,
+                                                img, 4_000_000, seed=114, tof_bin_width=t.bin_width,
+                                                tof_sigma=t.sigma, n_tof_bins=t.n_bins, device=d,
+                                                return_crystals=True)
+    table = C.SCANNER_CLIN.crystal_table(device=d)
+    G = gpu.ImageGeom(C.GRID_CLIN.dim, C.GRID_CLIN.voxsize, C.GRID_CLIN.origin)
+    T = gpu.TofParams(t.bin_width, t.sigma, t.n_sigmas, t.n_bins)
+    order = gpu.presort_crystals(table, pair, G, bins, T)
+    assert torch.equal(order, gpu.presort(xs, xe, G, bins, T))
+    p = gpu.fwd_tof_lm_crystals(table, pair, bins, G, T, img, order=order)
+    assert torch.equal(p, gpu.fwd_tof_lm(xs, xe, bins, G, T, img, order=order))
+    bk = gpu.back_tof_lm_crystals(table, pair, bins, G, T, p, order=order)
+    bkc = gpu.back_tof_lm(xs, xe, bins, G, T, p, order=order)
+    assert rel_l2(np64(bk), np64(bkc)) <= 1e-6
