@@ -150,12 +150,21 @@ __device__ __forceinline__ double bcast(double v, int src) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// col[j][k] += a, col[j + 1][k] += b for the in-range entries (thread-private column k), by
-// read-modify-write: LDS float atomics run at ~0.2 T adds/s on this GPU against ~2.7 T/s
-// for read-modify-write of thread-private words.
-__device__ __forceinline__ void col_add(float* col, int j, int k, float a, float b, int nw, int cs) {
-    if ((unsigned)j < (unsigned)nw && a != 0.0f) col[j * cs + k] += a;
-    if ((unsigned)(j + 1) < (unsigned)nw && b != 0.0f) col[(j + 1) * cs + k] += b;
+// The column entries (j, j + 1) of thread-private column k: col_get reads them (0 outside the
+// grid), col_put stores pa + a, pb + b back.  The sheet loop reads the pair when z moves to it
+// and writes it back when z moves on, so the read's latency overlaps the work in between instead
+// of stalling a read-modify-write (LDS float atomics run at ~0.2 T adds/s on this GPU against
+// ~2.7 T/s for read-modify-write of thread-private words).  A read issued after the write-back
+// of an overlapping pair sees it: one wave's LDS accesses complete in order.
+__device__ __forceinline__ void col_get(const float* col, int j, int k, int nw, int cs, float& pa, float& pb) {
+    pa = ((unsigned)j < (unsigned)nw) ? col[j * cs + k] : 0.0f;
+    pb = ((unsigned)(j + 1) < (unsigned)nw) ? col[(j + 1) * cs + k] : 0.0f;
+}
+
+__device__ __forceinline__ void col_put(float* col, int j, int k, float pa, float a, float pb, float b, int nw,
+                                        int cs) {
+    if ((unsigned)j < (unsigned)nw && a != 0.0f) col[j * cs + k] = pa + a;
+    if ((unsigned)(j + 1) < (unsigned)nw && b != 0.0f) col[(j + 1) * cs + k] = pb + b;
 }
 
 // Flush the sheet of line (p, U0, dU) with contiguous atomics and clear it: only the planes
@@ -389,6 +398,7 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
             const bool kin = k <= sh_kmax;
             int jc = kNoEntry;
             float accA = 0.0f, accB = 0.0f;
+            float preA = 0.0f, preB = 0.0f;  // column values of the pair jc, read when z moved to it
             for (int b0 = h; b0 < h + len; b0 += 64) {
                 const int nb = min(64, h + len - b0);
                 const int q = b0 + min(lane, nb - 1);
@@ -444,8 +454,9 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
 #pragma unroll
                         for (int u = 0; u < kSheetUnroll; ++u) {
                             if (vv[u] != 0.0f && j0v[u] != jc) {
-                                col_add(col, jc, k, accA, accB, nw, cs);
+                                col_put(col, jc, k, preA, accA, preB, accB, nw, cs);
                                 jc = j0v[u];
+                                col_get(col, jc, k, nw, cs, preA, preB);
                                 accA = 0.0f;
                                 accB = 0.0f;
                             }
@@ -455,7 +466,7 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
                     }
                 }
             }
-            col_add(col, jc, k, accA, accB, nw, cs);
+            col_put(col, jc, k, preA, accA, preB, accB, nw, cs);
             touched = touched || jc != kNoEntry;  // jc may be an out-of-grid entry after writes
             __syncthreads();
         }
