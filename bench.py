@@ -190,7 +190,7 @@ def lm_leg(args, pp, C, dev):
         lambda: pp.pp_fill(bimg, 0.0), args.steps, args.warmup)
     # the same projector pair in the events' own (unsorted) order (skipped when profiling the step)
     t_fwd_u = t_back_u = float("nan")
-    crys = {}
+    crys, per_ray = {}, {}
     if args.only is None:
         _, t_fwd_u, t_back_u = timed_pairs(lambda: pp.pp_fwd_tof_lm(xs, xe, bins, G, T, img, p),
                                            lambda: pp.pp_back_tof_lm(xs, xe, bins, G, T, bimg, p),
@@ -204,6 +204,19 @@ def lm_leg(args, pp, C, dev):
             lambda: pp.pp_fill(bimg, 0.0), 3, 1)
         crys = {"t_presort_ms": cs, "t_fwd_ms": cf, "t_back_ms": cb, "events_per_s": n_ev / (wall_c / 3)}
         log(f"TOF-LM crystal-index events: presort {cs:.2f} ms, fwd {cf:.2f} ms, back {cb:.2f} ms")
+        # the same projector pair with a sigma and a centre offset per event (presorted order)
+        from synth import tof_per_ray_params
+
+        sig, off = tof_per_ray_params(n_ev, tofs.sigma, seed=C.SEED_EVENTS + 1000, device=dev)
+        TP = pp.TofParams(tofs.bin_width, tofs.sigma, tofs.n_sigmas, tofs.n_bins, sigma_per_ray=sig,
+                          offset_per_ray=off)
+        pp.pp_lm_presort(xs, xe, bins, G, T, order, sort_ws)
+        _, pf, pb = timed_pairs(lambda: pp.pp_fwd_tof_lm(xs, xe, bins, G, TP, img, p, order),
+                                lambda: pp.pp_back_tof_lm(xs, xe, bins, G, TP, bimg, p, order),
+                                lambda: pp.pp_fill(bimg, 0.0), 3, 1)
+        per_ray = {"t_fwd_ms": pf, "t_back_ms": pb}
+        log(f"TOF-LM per-event sigma and offset: fwd {pf:.2f} ms, back {pb:.2f} ms")
+        del sig, off, TP
     log(f"TOF-LM: presort {t_sort:.2f} ms, fwd {t_fwd:.2f} ms, back {t_back:.2f} ms, wall "
         f"{1e3 * wall / args.steps:.2f} ms/step; unsorted order: fwd {t_fwd_u:.2f} ms back {t_back_u:.2f} ms; "
         f"{n_samples / n_ev:.1f} samples/event")
@@ -217,9 +230,31 @@ def lm_leg(args, pp, C, dev):
         "samples_per_event": n_samples / n_ev, "alg_bytes_per_launch": alg_bytes,
         "dominant": dom_name, "achieved_gbs": achieved,
         "fwd_alg_gbs": alg_bytes / (t_fwd * 1e-3) / 1e9, "back_alg_gbs": alg_bytes / (t_back * 1e-3) / 1e9,
-        "crystal_index_events": crys,
+        "crystal_index_events": crys, "per_event_tof_params": per_ray,
     }
     return res, (xs, xe, bins, img, G, T)
+
+
+def resmodel_leg(args, pp, C, dev):
+    """The resolution model's separable Gaussian (pp_gauss3d, 4.5 mm FWHM) on the clinical grid and
+    the 128 x 128 x 64 serving grid: 3 passes, each reading and writing the image once (8 B per
+    voxel per pass of algorithmic HBM traffic)."""
+    import torch
+
+    from paper_2212_12519_amd.osem import RES_FWHM_MM
+
+    out = {}
+    for name, grid in (("clinical_215x215x71", C.GRID_CLIN), ("serving_128x128x64", C.GRID_DL)):
+        G = pp.ImageGeom(grid.dim, grid.voxsize, grid.origin)
+        src = torch.rand(grid.dim, generator=torch.Generator().manual_seed(5)).to(dev)
+        dst, tmp = torch.empty_like(src), torch.empty_like(src)
+        fwhm = (RES_FWHM_MM,) * 3
+        _, t, _ = timed_pairs(lambda: pp.pp_gauss3d(src, dst, tmp, G, fwhm), lambda: None, lambda: None, 20, 3)
+        alg = 3 * 8 * src.numel()
+        out[name] = {"t_ms": t, "alg_bytes": alg, "alg_gbs": alg / (t * 1e-3) / 1e9,
+                     "hbm_frac": alg / (t * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        log(f"resolution model {name}: {t * 1e3:.1f} us, {alg / (t * 1e-3) / 1e9:.0f} GB/s")
+    return out
 
 
 def cpu_leg(args, lm_inputs, C):
@@ -325,6 +360,8 @@ def main():
     if args.only == "sino":
         print(json.dumps(extra))
         return
+    if args.only is None:
+        extra["resolution_model"] = resmodel_leg(args, pp, C, dev)
     if args.only in (None, "serve") and not args.no_serve:
         from paper_2212_12519_amd import serve
 

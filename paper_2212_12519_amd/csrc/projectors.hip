@@ -40,29 +40,44 @@ __global__ void __launch_bounds__(kBlock) k_fwd(RaySrc src,
 
 // ------------------------------------------------------- TOF listmode ----
 
-// PerRay: per-ray sigma / centre offset arrays are set (TofRay in joseph.hpp)
+// PerRay: per-ray sigma / centre offset arrays are set (TofRay in joseph.hpp).  Presorted
+// events of one wave share their TOF bin, so their plane windows nearly coincide and the lanes
+// of a wave gather from the same planes at each step; with per-ray parameters the windows start
+// at different planes, so the loop runs over absolute planes instead (wave-synchronous: all
+// lanes at plane k, each active inside its own window), keeping the gathers of a step coherent.
 template <bool Lut, bool PerRay>
 __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(RaySrc src,
                                                        const int16_t* __restrict__ bins, int64_t n, GeomK g,
                                                        TofK t, const float* __restrict__ img,
                                                        float* __restrict__ p, const int32_t* __restrict__ order) {
+    constexpr bool kWaveSync = PerRay;
     const int64_t l = ray_index(order, n);
-    if (l < 0) return;
-    const int b = bins[l];
+    const int b = l >= 0 ? bins[l] : -1;
     float acc = 0.0f;
     RayK r;
     TofRay q;
-    if (b >= 0 && b < t.nb && tof_ray<PerRay>(t, l, q) && ray_setup(src, l, g, r)) {
+    bool on = b >= 0 && b < t.nb && tof_ray<PerRay>(t, l, q) && ray_setup(src, l, g, r);
+    if (on) {
         if (PerRay) r.s0 -= q.shift;
-        if (tof_window_rel(r, t.c0 + b * t.bw, q.lo, q.hi)) {
-            for (int k = r.k_lo; k <= r.k_hi; ++k) {
+        on = tof_window_rel(r, t.c0 + b * t.bw, q.lo, q.hi);
+    }
+    if (kWaveSync) {  // every lane of the wave reaches this point
+        const int lo = on ? r.k_lo : (1 << 30), hi = on ? r.k_hi : -(1 << 30);
+        const int k0 = wave_min(lo), k1 = wave_max(hi);
+        for (int k = k0; k <= k1; ++k) {
+            if (k >= lo && k <= hi) {
                 const float w = tof_weight<Lut>(fma((double)k, r.ds, r.s0), t, q.inv);
                 acc += w * stencil_gather(img, r, stencil_at(r, k));
             }
-            acc *= r.ell;
+        }
+    } else if (on) {
+        for (int k = r.k_lo; k <= r.k_hi; ++k) {
+            const float w = tof_weight<Lut>(fma((double)k, r.ds, r.s0), t, q.inv);
+            acc += w * stencil_gather(img, r, stencil_at(r, k));
         }
     }
-    p[l] = acc;
+    if (on) acc *= r.ell;
+    if (l >= 0) p[l] = acc;
 }
 
 // ------------------------------------------------------- TOF sinogram ----
