@@ -50,7 +50,9 @@ struct SheetLayout {
         const int np = g.n[0] > g.n[1] ? g.n[0] : g.n[1];
         return (np < kSheetBlock ? np : kSheetBlock) + 1;
     }
-    static size_t bytes(int nw, const GeomK& g) { return ray_bytes() + (size_t)nw * col_stride(g) * 4; }
+    // nw rows of the sheet plus one spare row that absorbs the out-of-grid entries of a z pair
+    // (216-entry rows on the clinical grid: 81,760 bytes, two workgroups per CU)
+    static size_t bytes(int nw, const GeomK& g) { return ray_bytes() + (size_t)(nw + 1) * col_stride(g) * 4; }
 };
 
 // Per-ray value hooks:
@@ -150,21 +152,25 @@ __device__ __forceinline__ double bcast(double v, int src) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// The column entries (j, j + 1) of thread-private column k: col_get reads them (0 outside the
-// grid), col_put stores pa + a, pb + b back.  The sheet loop reads the pair when z moves to it
-// and writes it back when z moves on, so the read's latency overlaps the work in between instead
-// of stalling a read-modify-write (LDS float atomics run at ~0.2 T adds/s on this GPU against
-// ~2.7 T/s for read-modify-write of thread-private words).  A read issued after the write-back
-// of an overlapping pair sees it: one wave's LDS accesses complete in order.
+// The column entries (j, j + 1) of thread-private column k: col_get reads them, col_put stores
+// pa + a, pb + b back.  The sheet loop reads the pair when z moves to it and writes it back when
+// z moves on, so the read's latency overlaps the work in between instead of stalling a
+// read-modify-write (LDS float atomics run at ~0.2 T adds/s on this GPU against ~2.7 T/s for
+// read-modify-write of thread-private words).  A read issued after the write-back of an
+// overlapping pair sees it: one wave's LDS accesses complete in order.  Entries outside the grid
+// (j = -1, j + 1 = nw, or no entry yet) go to the spare row nw, which is never flushed, so both
+// calls are four plain LDS accesses with no branch.
+__device__ __forceinline__ int col_row(int j, int nw) { return ((unsigned)j < (unsigned)nw) ? j : nw; }
+
 __device__ __forceinline__ void col_get(const float* col, int j, int k, int nw, int cs, float& pa, float& pb) {
-    pa = ((unsigned)j < (unsigned)nw) ? col[j * cs + k] : 0.0f;
-    pb = ((unsigned)(j + 1) < (unsigned)nw) ? col[(j + 1) * cs + k] : 0.0f;
+    pa = col[col_row(j, nw) * cs + k];
+    pb = col[col_row(j + 1, nw) * cs + k];
 }
 
 __device__ __forceinline__ void col_put(float* col, int j, int k, float pa, float a, float pb, float b, int nw,
                                         int cs) {
-    if ((unsigned)j < (unsigned)nw && a != 0.0f) col[j * cs + k] = pa + a;
-    if ((unsigned)(j + 1) < (unsigned)nw && b != 0.0f) col[(j + 1) * cs + k] = pb + b;
+    col[col_row(j, nw) * cs + k] = pa + a;
+    col[col_row(j + 1, nw) * cs + k] = pb + b;
 }
 
 // Flush the sheet of line (p, U0, dU) with contiguous atomics and clear it: only the planes
