@@ -160,17 +160,20 @@ __device__ __forceinline__ double bcast(double v, int src) {
 // overlapping pair sees it: one wave's LDS accesses complete in order.  Entries outside the grid
 // (j = -1, j + 1 = nw, or no entry yet) go to the spare row nw, which is never flushed, so both
 // calls are four plain LDS accesses with no branch.
+// The LDS indices of the pair are kept from the read to the write-back (ia, ib).
 __device__ __forceinline__ int col_row(int j, int nw) { return ((unsigned)j < (unsigned)nw) ? j : nw; }
 
-__device__ __forceinline__ void col_get(const float* col, int j, int k, int nw, int cs, float& pa, float& pb) {
-    pa = col[col_row(j, nw) * cs + k];
-    pb = col[col_row(j + 1, nw) * cs + k];
+__device__ __forceinline__ void col_get(const float* col, int j, int k, int nw, int cs, int& ia, int& ib, float& pa,
+                                        float& pb) {
+    ia = (int)__umul24((unsigned)col_row(j, nw), (unsigned)cs) + k;  // rows and strides < 2^24
+    ib = (int)__umul24((unsigned)col_row(j + 1, nw), (unsigned)cs) + k;
+    pa = col[ia];
+    pb = col[ib];
 }
 
-__device__ __forceinline__ void col_put(float* col, int j, int k, float pa, float a, float pb, float b, int nw,
-                                        int cs) {
-    col[col_row(j, nw) * cs + k] = pa + a;
-    col[col_row(j + 1, nw) * cs + k] = pb + b;
+__device__ __forceinline__ void col_put(float* col, int ia, int ib, float pa, float a, float pb, float b) {
+    col[ia] = pa + a;
+    col[ib] = pb + b;
 }
 
 // Flush the sheet of line (p, U0, dU) with contiguous atomics and clear it: only the planes
@@ -405,6 +408,8 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
             int jc = kNoEntry;
             float accA = 0.0f, accB = 0.0f;
             float preA = 0.0f, preB = 0.0f;  // column values of the pair jc, read when z moved to it
+            int ia = (int)__umul24((unsigned)nw, (unsigned)cs) + k, ib = ia;  // its LDS indices (spare row;
+                                                                              // used only while kin)
             for (int b0 = h; b0 < h + len; b0 += 64) {
                 const int nb = min(64, h + len - b0);
                 const int q = b0 + min(lane, nb - 1);
@@ -460,9 +465,9 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
 #pragma unroll
                         for (int u = 0; u < kSheetUnroll; ++u) {
                             if (vv[u] != 0.0f && j0v[u] != jc) {
-                                col_put(col, jc, k, preA, accA, preB, accB, nw, cs);
+                                col_put(col, ia, ib, preA, accA, preB, accB);
                                 jc = j0v[u];
-                                col_get(col, jc, k, nw, cs, preA, preB);
+                                col_get(col, jc, k, nw, cs, ia, ib, preA, preB);
                                 accA = 0.0f;
                                 accB = 0.0f;
                             }
@@ -472,7 +477,8 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
                     }
                 }
             }
-            col_put(col, jc, k, preA, accA, preB, accB, nw, cs);
+            // threads past the line's last plane (k >= cs possible) never leave the initial state
+            if (kin) col_put(col, ia, ib, preA, accA, preB, accB);
             touched = touched || jc != kNoEntry;  // jc may be an out-of-grid entry after writes
             __syncthreads();
         }
