@@ -75,10 +75,14 @@ static int key_bits(int n_sub) {
     return b;
 }
 
+// temporary storage of the radix sort (a size query: no launch); 0 if the query fails, which
+// makes the sort itself report the error
 static size_t sort_temp_bytes(int64_t n) {
     size_t bytes = 0;
-    hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr,
-                                       (const int32_t*)nullptr, (int32_t*)nullptr, (int)n, 0, 64, (hipStream_t)0);
+    if (hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                                           (const int32_t*)nullptr, (int32_t*)nullptr, (int)n, 0, 64,
+                                           (hipStream_t)0) != hipSuccess)
+        return 0;
     return bytes;
 }
 
