@@ -35,7 +35,6 @@ constexpr int kSheetBlock = 256;
 constexpr int kRunMin = 2;
 constexpr int kSheetMaxW = 128;  // largest axis-2 size with an LDS sheet
 constexpr int kSheetGroups = 8;  // groups of 256 rays per workgroup (a sheet persists across them)
-constexpr int kSheetUnroll = 1;  // rays evaluated together in the sheet loop
 constexpr int kNoEntry = -(1 << 30);  // "no z entry cached": no ray's floor(W) comes near it
 
 // LDS layout of k_back_runs (bytes): per-ray arrays, then the column buffer.
@@ -143,14 +142,6 @@ struct ModeTofSino {
         return c * cv;
     }
 };
-
-// Broadcast lane `src` (wave-uniform) of a double to the whole wave through scalar registers.
-__device__ __forceinline__ double bcast(double v, int src) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
 
 // The column entries (j, j + 1) of thread-private column k: col_get reads them, col_put stores
 // pa + a, pb + b back.  The sheet loop reads the pair when z moves to it and writes it back when
@@ -397,11 +388,10 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
                 sh_dU = dU[h];
                 sh_kmax = g.n[sh_p] - 1;
             }
-            // thread tid accumulates the column of absolute plane k = tid.  Each wave loads 64 of
-            // the run's rays with one vector LDS read and broadcasts them lane by lane (readlane);
-            // kSheetUnroll rays are evaluated branch-free per step (one measured best: the loop
-            // waits on the z-change write-backs, not on arithmetic), and the current pair of z
-            // entries stays in registers until z changes.
+            // thread tid accumulates the column of absolute plane k = tid.  Each wave walks the run's
+            // rays whose plane window meets its 64 planes, one ray per step (evaluating 2 or 4 rays
+            // per step measured slower), and the current pair of z entries stays in registers until
+            // z changes.
             const int k = tid;
             const int len = cnt[h];
             const bool kin = k <= sh_kmax;
@@ -412,69 +402,53 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
                                                                               // used only while kin)
             for (int b0 = h; b0 < h + len; b0 += 64) {
                 const int nb = min(64, h + len - b0);
-                const int q = b0 + min(lane, nb - 1);
-                const double qW0 = W0[q], qdW = dW[q], qs0 = s0[q], qds = ds[q];
-                const int qcv = __float_as_int(cvs[q]);
-                const int qax = aux[q];
-                const int qlh = lohi[q];
+                const int qlh = lohi[b0 + min(lane, nb - 1)];
                 // rays whose plane window meets this wave's 64 planes (wave-uniform bit mask)
                 const int kw0 = wave * 64, kw1 = min(kw0 + 63, sh_kmax);
                 unsigned long long todo =
                     __ballot(lane < nb && (qlh & 0xffff) <= kw1 && (qlh >> 16) >= kw0);
-                while (todo) {
-                    int ru[kSheetUnroll], nu_ = 0;
-#pragma unroll
-                    for (int u = 0; u < kSheetUnroll; ++u) {
-                        if (todo) {
-                            ru[u] = __ffsll((long long)todo) - 1;
-                            todo &= todo - 1ull;
-                            ++nu_;
-                        } else {
-                            ru[u] = ru[0];
-                        }
+                if (!todo) continue;
+                // Each ray's parameters are read from LDS at a wave-uniform address (a broadcast,
+                // no bank conflict), one ray ahead of its evaluation so that the read latency
+                // overlaps the current ray's arithmetic.
+                int e = b0 + __ffsll((long long)todo) - 1;
+                todo &= todo - 1ull;
+                double cW0 = W0[e], cdW = dW[e], cs0 = s0[e], cds = ds[e];
+                float ccv = cvs[e];
+                int cax = aux[e], clh = lohi[e];
+                while (true) {
+                    const bool more = todo != 0ull;
+                    const int en = more ? b0 + __ffsll((long long)todo) - 1 : e;
+                    todo &= todo - 1ull;
+                    const double nW0 = W0[en], ndW = dW[en], ns0 = s0[en], nds = ds[en];
+                    const float ncv = cvs[en];
+                    const int nax = aux[en], nlh = lohi[en];
+                    const bool act = kin && k >= (clh & 0xffff) && k <= (clh >> 16);
+                    const double W = fma((double)k, cdW, cW0);
+                    const double fj = floor(W);
+                    const int j0 = (int)fj;
+                    const float fw = (float)(W - fj);
+                    const float v0 = m.sample(fma((double)k, cds, cs0), ccv, Mode::kAux ? cax : 0);
+                    const float v = act ? v0 : 0.0f;
+                    // the pair of z entries stays in registers until z changes
+                    if (v != 0.0f && j0 != jc) {
+                        col_put(col, ia, ib, preA, accA, preB, accB);
+                        jc = j0;
+                        col_get(col, jc, k, nw, cs, ia, ib, preA, preB);
+                        accA = 0.0f;
+                        accB = 0.0f;
                     }
-                    // evaluate all rays of the batch first (straight-line code, no branches)
-                    int j0v[kSheetUnroll];
-                    float fwv[kSheetUnroll], vv[kSheetUnroll];
-#pragma unroll
-                    for (int u = 0; u < kSheetUnroll; ++u) {
-                        const int rlh = __builtin_amdgcn_readlane(qlh, ru[u]);
-                        const bool act = kin && u < nu_ && k >= (rlh & 0xffff) && k <= (rlh >> 16);
-                        const double W = fma((double)k, bcast(qdW, ru[u]), bcast(qW0, ru[u]));
-                        const double fj = floor(W);
-                        j0v[u] = (int)fj;
-                        fwv[u] = (float)(W - fj);
-                        const float v = m.sample(fma((double)k, bcast(qds, ru[u]), bcast(qs0, ru[u])),
-                                                 __int_as_float(__builtin_amdgcn_readlane(qcv, ru[u])),
-                                                 Mode::kAux ? __builtin_amdgcn_readlane(qax, ru[u]) : 0);
-                        vv[u] = act ? v : 0.0f;
-                    }
-                    // then accumulate: the pair of z entries stays in registers until z changes.
-                    // The common case (no contributing ray of the batch leaves entry jc) is tested
-                    // on all rays at once, so the evaluations above stay in one basic block.
-                    bool same = true;
-#pragma unroll
-                    for (int u = 0; u < kSheetUnroll; ++u) same &= (vv[u] == 0.0f) | (j0v[u] == jc);
-                    if (same) {
-#pragma unroll
-                        for (int u = 0; u < kSheetUnroll; ++u) {
-                            accA = fmaf(1.0f - fwv[u], vv[u], accA);
-                            accB = fmaf(fwv[u], vv[u], accB);
-                        }
-                    } else {
-#pragma unroll
-                        for (int u = 0; u < kSheetUnroll; ++u) {
-                            if (vv[u] != 0.0f && j0v[u] != jc) {
-                                col_put(col, ia, ib, preA, accA, preB, accB);
-                                jc = j0v[u];
-                                col_get(col, jc, k, nw, cs, ia, ib, preA, preB);
-                                accA = 0.0f;
-                                accB = 0.0f;
-                            }
-                            accA = fmaf(1.0f - fwv[u], vv[u], accA);
-                            accB = fmaf(fwv[u], vv[u], accB);
-                        }
-                    }
+                    accA = fmaf(1.0f - fw, v, accA);
+                    accB = fmaf(fw, v, accB);
+                    if (!more) break;
+                    e = en;
+                    cW0 = nW0;
+                    cdW = ndW;
+                    cs0 = ns0;
+                    cds = nds;
+                    ccv = ncv;
+                    cax = nax;
+                    clh = nlh;
                 }
             }
             // threads past the line's last plane (k >= cs possible) never leave the initial state
