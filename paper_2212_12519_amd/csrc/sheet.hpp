@@ -410,25 +410,27 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
                 if (!todo) continue;
                 // Each ray's parameters are read from LDS at a wave-uniform address (a broadcast,
                 // no bank conflict), one ray ahead of its evaluation so that the read latency
-                // overlaps the current ray's arithmetic.
-                int e = b0 + __ffsll((long long)todo) - 1;
-                todo &= todo - 1ull;
-                double cW0 = W0[e], cdW = dW[e], cs0 = s0[e], cds = ds[e];
-                float ccv = cvs[e];
-                int cax = aux[e], clh = lohi[e];
-                while (true) {
-                    const bool more = todo != 0ull;
-                    const int en = more ? b0 + __ffsll((long long)todo) - 1 : e;
+                // overlaps the current ray's arithmetic; two records alternate (no copies).
+                struct Rec {
+                    double W0, dW, s0, ds;
+                    float cv;
+                    int ax, lh;
+                };
+                auto load = [&](int e) {
+                    return Rec{W0[e], dW[e], s0[e], ds[e], cvs[e], aux[e], lohi[e]};
+                };
+                auto next = [&](int fallback) {
+                    const int en = todo ? b0 + __ffsll((long long)todo) - 1 : fallback;
                     todo &= todo - 1ull;
-                    const double nW0 = W0[en], ndW = dW[en], ns0 = s0[en], nds = ds[en];
-                    const float ncv = cvs[en];
-                    const int nax = aux[en], nlh = lohi[en];
-                    const bool act = kin && k >= (clh & 0xffff) && k <= (clh >> 16);
-                    const double W = fma((double)k, cdW, cW0);
+                    return en;
+                };
+                auto step = [&](const Rec& c) {
+                    const bool act = kin && k >= (c.lh & 0xffff) && k <= (c.lh >> 16);
+                    const double W = fma((double)k, c.dW, c.W0);
                     const double fj = floor(W);
                     const int j0 = (int)fj;
                     const float fw = (float)(W - fj);
-                    const float v0 = m.sample(fma((double)k, cds, cs0), ccv, Mode::kAux ? cax : 0);
+                    const float v0 = m.sample(fma((double)k, c.ds, c.s0), c.cv, Mode::kAux ? c.ax : 0);
                     const float v = act ? v0 : 0.0f;
                     // the pair of z entries stays in registers until z changes
                     if (v != 0.0f && j0 != jc) {
@@ -440,15 +442,20 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
                     }
                     accA = fmaf(1.0f - fw, v, accA);
                     accB = fmaf(fw, v, accB);
+                };
+                int e = next(0);
+                Rec ra = load(e);
+                while (true) {
+                    bool more = todo != 0ull;
+                    e = next(e);
+                    const Rec rb = load(e);
+                    step(ra);
                     if (!more) break;
-                    e = en;
-                    cW0 = nW0;
-                    cdW = ndW;
-                    cs0 = ns0;
-                    cds = nds;
-                    ccv = ncv;
-                    cax = nax;
-                    clh = nlh;
+                    more = todo != 0ull;
+                    e = next(e);
+                    ra = load(e);
+                    step(rb);
+                    if (!more) break;
                 }
             }
             // threads past the line's last plane (k >= cs possible) never leave the initial state
