@@ -330,7 +330,7 @@ __device__ __forceinline__ float erf_hastings(float x) {
 // 1 / (sqrt(2) sigma): the clip is taken on the scaled argument (at +-n_sigmas / sqrt 2), so a
 // ray with its own sigma needs nothing but its own inv
 __device__ __forceinline__ float tof_erf(float x, float inv, const TofK& t) {
-    return erf_hastings(fminf(fmaxf(x * inv, -t.cmax), t.cmax));
+    return erf_hastings(__builtin_amdgcn_fmed3f(x * inv, -t.cmax, t.cmax));
 }
 
 
@@ -344,14 +344,20 @@ __device__ __forceinline__ float tof_lut(double x, const TofK& t) {
     return fmaf(f, b - a, a);
 }
 
-// weight of a bin for a plane sample at signed distance x (mm) from the bin centre:
-// G(x + bw/2) - G(x - bw/2) with inv = 1 / (sqrt(2) sigma) (Lut = false), or the tabulated
-// kernel (Lut = true)
+// Weight of a bin for a plane sample at signed distance x (mm) from the bin centre, up to the
+// factor kTofScale<Lut>: for the Gaussian (inv = 1 / (sqrt(2) sigma)) 2 w(x) = 2 (G(x + bw/2) -
+// G(x - bw/2)), the difference of the two clipped erf, for a table w(x).  Every caller folds
+// kTofScale into its per-ray constant (ell, or ell times the ray's value); a power-of-two factor
+// commutes with float rounding, so the weights are applied exactly as if scaled per sample.
 template <bool Lut>
-__device__ __forceinline__ float tof_weight(double x, const TofK& t, float inv) {
+constexpr float kTofScale = Lut ? 1.0f : 0.5f;
+
+template <bool Lut>
+__device__ __forceinline__ float tof_weight_unscaled(double x, const TofK& t, float inv) {
     if (Lut) return tof_lut(x, t);
-    const float xf = (float)x;
-    return 0.5f * (tof_erf(xf + t.hbw, inv, t) - tof_erf(xf - t.hbw, inv, t));
+    const float xf = (float)x, h = t.hbw * inv;
+    return erf_hastings(__builtin_amdgcn_fmed3f(fmaf(xf, inv, h), -t.cmax, t.cmax)) -
+           erf_hastings(__builtin_amdgcn_fmed3f(fmaf(xf, inv, -h), -t.cmax, t.cmax));
 }
 
 // TOF bins whose support [lo_x, hi_x] (relative to the bin centre) contains a sample at TOF

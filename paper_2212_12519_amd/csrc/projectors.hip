@@ -66,17 +66,17 @@ __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(RaySrc src,
         const int k0 = wave_min(lo), k1 = wave_max(hi);
         for (int k = k0; k <= k1; ++k) {
             if (k >= lo && k <= hi) {
-                const float w = tof_weight<Lut>(fma((double)k, r.ds, r.s0), t, q.inv);
+                const float w = tof_weight_unscaled<Lut>(fma((double)k, r.ds, r.s0), t, q.inv);
                 acc += w * stencil_gather(img, r, stencil_at(r, k));
             }
         }
     } else if (on) {
         for (int k = r.k_lo; k <= r.k_hi; ++k) {
-            const float w = tof_weight<Lut>(fma((double)k, r.ds, r.s0), t, q.inv);
+            const float w = tof_weight_unscaled<Lut>(fma((double)k, r.ds, r.s0), t, q.inv);
             acc += w * stencil_gather(img, r, stencil_at(r, k));
         }
     }
-    if (on) acc *= r.ell;
+    if (on) acc *= r.ell * kTofScale<Lut>;
     if (l >= 0) p[l] = acc;
 }
 

@@ -90,12 +90,12 @@ struct ModeTofLm {
             return false;
         if (PerRay) r.s0 -= q.shift;
         if (!tof_window_rel(r, t.c0 + b * t.bw, q.lo, q.hi)) return false;
-        cv = r.ell * pl;
+        cv = r.ell * pl * kTofScale<Lut>;
         if (PerRay) aux = __float_as_int(q.inv);
         return true;
     }
     __device__ float sample(double x, float cv, int aux) const {
-        return tof_weight<Lut>(x, t, PerRay ? __int_as_float(aux) : t.inv_sqrt2_sig) * cv;
+        return tof_weight_unscaled<Lut>(x, t, PerRay ? __int_as_float(aux) : t.inv_sqrt2_sig) * cv;
     }
 };
 
