@@ -65,8 +65,8 @@ int make_tof(const pp_tof_t* ti, TofK& t) {
         t.inv_bw = 1.0 / t.bw;
         t.c0 = -0.5 * (double)(ti->n_bins - 1) * t.bw + offset;
         t.hbw = (float)(0.5 * t.bw);
-        t.inv_sqrt2_sig = 1.0f;
-        t.cmax = 1.0f;
+        t.u_per_mm = 1.0f;
+        t.u_max = 1.0f;
         t.nsig = 1.0f;
         t.nb = ti->n_bins;
         t.lo = x0;
@@ -84,10 +84,11 @@ int make_tof(const pp_tof_t* ti, TofK& t) {
     t.inv_bw = 1.0 / bw;
     t.c0 = -0.5 * (double)(ti->n_bins - 1) * bw + offset;
     t.hbw = (float)(0.5 * bw);
-    t.cmax = (float)(ns / std::sqrt(2.0));
+    const double erf_c = std::sqrt(1.0 / std::log(2.0));  // sqrt(log2 e), kErfC
+    t.u_max = (float)(erf_c * ns / std::sqrt(2.0));
     t.nsig = ti->n_sigmas;
     t.win = ns * sig + 0.5 * bw;
-    t.inv_sqrt2_sig = (float)(1.0 / (std::sqrt(2.0) * sig));
+    t.u_per_mm = (float)(erf_c / (std::sqrt(2.0) * sig));
     t.nb = ti->n_bins;
     t.lo = -t.win;
     t.hi = t.win;

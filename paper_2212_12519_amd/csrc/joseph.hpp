@@ -36,13 +36,15 @@ struct TofK {
     int lut_n;
     float lut_inv_dx;
     float hbw;            // bw / 2, mm
-    float inv_sqrt2_sig;  // 1 / (sqrt(2) sigma)
-    float cmax;           // n_sigmas / sqrt(2): the truncation in units of the erf argument
+    float u_per_mm;       // kErfC / (sqrt(2) sigma): the scaled erf argument (erf_scaled) per mm
+    float u_max;          // kErfC n_sigmas / sqrt(2): the truncation in units of that argument
     float nsig;           // n_sigmas
     int nb;               // bins
     const float* sig_ray; // sigma of each ray (mm), or nullptr: every ray has sigma
     const float* off_ray; // centre offset of each ray (mm), or nullptr: c0 holds the offset
 };
+
+constexpr float kErfC = 1.2011224087864498f;  // sqrt(log2(e)): scale of the erf argument (erf_scaled)
 
 // Resolution-model blur taps per axis: w[a][i + r[a]] for |i| <= r[a].
 constexpr int kGaussMaxR = 31;
@@ -178,12 +180,14 @@ __device__ __forceinline__ bool ray_setup(const RaySrc& src, int64_t l, const Ge
 struct TofRay {
     double shift;   // the ray's centre offset (0 without per-ray offsets: c0 holds it)
     double lo, hi;  // support of a bin's weight relative to its centre
-    float inv;      // 1 / (sqrt(2) sigma_l)
+    float inv;      // kErfC / (sqrt(2) sigma_l), the erf argument per mm
 };
 
-// 1 / (sqrt(2) sigma) of a per-ray sigma (sigma below 1e-30 mm taken as 1e-30 mm, a kernel far
+// kErfC / (sqrt(2) sigma) of a per-ray sigma (sigma below 1e-30 mm taken as 1e-30 mm, a kernel far
 // narrower than any voxel, so that the product never overflows)
-__device__ __forceinline__ float tof_inv_sigma(float sigma) { return 1.0f / (1.41421356f * fmaxf(sigma, 1e-30f)); }
+__device__ __forceinline__ float tof_inv_sigma(float sigma) {
+    return kErfC / (1.41421356f * fmaxf(sigma, 1e-30f));
+}
 
 // Parameters of ray l; false if its per-ray entries are unusable (sigma not a positive
 // finite number, offset not finite): the ray contributes nothing.
@@ -192,7 +196,7 @@ __device__ __forceinline__ bool tof_ray(const TofK& t, int64_t l, TofRay& q) {
     q.shift = 0.0;
     q.lo = t.lo;
     q.hi = t.hi;
-    q.inv = t.inv_sqrt2_sig;
+    q.inv = t.u_per_mm;
     if (!PerRay) return true;
     if (t.sig_ray) {
         const float sg = t.sig_ray[l];
@@ -315,22 +319,25 @@ __device__ __forceinline__ void wave_stencil_scatter(float* __restrict__ img, bo
 // 6e-7 when evaluated in float32 (the cancellation in 1 - t P e near u = 0).  Branch-free,
 // so the plane loops keep several rays' dependency chains interleaved (a library erf
 // with a branch per range serialises them), and about a third of the instructions.
-__device__ __forceinline__ float erf_hastings(float x) {
-    const float u = fabsf(x);
-    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, u, 1.0f));
+// erf_scaled takes v = kErfC u, kErfC = sqrt(log2 e), so that exp(-u^2) = exp2(-v^2) costs one
+// multiply; the callers fold kErfC into the factor that forms the argument.
+
+__device__ __forceinline__ float erf_scaled(float v) {
+    const float a = fabsf(v);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f / kErfC, a, 1.0f));
     float P = fmaf(1.061405429f, t, -1.453152027f);
     P = fmaf(P, t, 1.421413741f);
     P = fmaf(P, t, -0.284496736f);
     P = fmaf(P, t, 0.254829592f);
-    const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * u * u);  // exp(-u^2)
-    return copysignf(fmaf(-(t * P), e, 1.0f), x);
+    const float e = __builtin_amdgcn_exp2f(-(a * a));  // exp(-u^2)
+    return copysignf(fmaf(-(t * P), e, 1.0f), v);
 }
 
 // erf(clip(x, -n_sigmas sigma, n_sigmas sigma) / (sqrt(2) sigma)), x in mm, with inv =
-// 1 / (sqrt(2) sigma): the clip is taken on the scaled argument (at +-n_sigmas / sqrt 2), so a
-// ray with its own sigma needs nothing but its own inv
+// kErfC / (sqrt(2) sigma): the clip is taken on the scaled argument (at +-u_max), so a ray with
+// its own sigma needs nothing but its own inv
 __device__ __forceinline__ float tof_erf(float x, float inv, const TofK& t) {
-    return erf_hastings(__builtin_amdgcn_fmed3f(x * inv, -t.cmax, t.cmax));
+    return erf_scaled(__builtin_amdgcn_fmed3f(x * inv, -t.u_max, t.u_max));
 }
 
 
@@ -345,7 +352,7 @@ __device__ __forceinline__ float tof_lut(double x, const TofK& t) {
 }
 
 // Weight of a bin for a plane sample at signed distance x (mm) from the bin centre, up to the
-// factor kTofScale<Lut>: for the Gaussian (inv = 1 / (sqrt(2) sigma)) 2 w(x) = 2 (G(x + bw/2) -
+// factor kTofScale<Lut>: for the Gaussian (inv = kErfC / (sqrt(2) sigma)) 2 w(x) = 2 (G(x + bw/2) -
 // G(x - bw/2)), the difference of the two clipped erf, for a table w(x).  Every caller folds
 // kTofScale into its per-ray constant (ell, or ell times the ray's value); a power-of-two factor
 // commutes with float rounding, so the weights are applied exactly as if scaled per sample.
@@ -356,8 +363,8 @@ template <bool Lut>
 __device__ __forceinline__ float tof_weight_unscaled(double x, const TofK& t, float inv) {
     if (Lut) return tof_lut(x, t);
     const float xf = (float)x, h = t.hbw * inv;
-    return erf_hastings(__builtin_amdgcn_fmed3f(fmaf(xf, inv, h), -t.cmax, t.cmax)) -
-           erf_hastings(__builtin_amdgcn_fmed3f(fmaf(xf, inv, -h), -t.cmax, t.cmax));
+    return erf_scaled(__builtin_amdgcn_fmed3f(fmaf(xf, inv, h), -t.u_max, t.u_max)) -
+           erf_scaled(__builtin_amdgcn_fmed3f(fmaf(xf, inv, -h), -t.u_max, t.u_max));
 }
 
 // TOF bins whose support [lo_x, hi_x] (relative to the bin centre) contains a sample at TOF

@@ -57,7 +57,7 @@ struct ModeOsem {
         if (!tof_window_rel(r, t.c0 + b * t.bw, t.lo, t.hi)) return false;
         float fwd = 0.0f;
         for (int k = r.k_lo; k <= r.k_hi; ++k) {
-            const float w = tof_weight_unscaled<Lut>(fma((double)k, r.ds, r.s0), t, t.inv_sqrt2_sig);
+            const float w = tof_weight_unscaled<Lut>(fma((double)k, r.ds, r.s0), t, t.u_per_mm);
             fwd += w * stencil_gather(x, r, stencil_at(r, k));
         }
         const float ybar = r.ell * kTofScale<Lut> * fwd + bg;
@@ -66,7 +66,7 @@ struct ModeOsem {
         return true;
     }
     __device__ float sample(double x, float cv, int /*aux*/) const {
-        return tof_weight_unscaled<Lut>(x, t, t.inv_sqrt2_sig) * cv;
+        return tof_weight_unscaled<Lut>(x, t, t.u_per_mm) * cv;
     }
 };
 

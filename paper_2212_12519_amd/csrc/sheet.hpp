@@ -74,7 +74,7 @@ struct ModeNonTof {
 };
 
 // Listmode TOF.  With per-ray TOF parameters (PerRay) the ray's offset is folded into its TOF
-// coordinate at setup and aux carries the bits of its 1 / (sqrt(2) sigma).
+// coordinate at setup and aux carries the bits of its erf argument per mm (TofRay::inv).
 template <bool Lut, bool PerRay = false>
 struct ModeTofLm {
     static constexpr bool kAux = PerRay;
@@ -95,7 +95,7 @@ struct ModeTofLm {
         return true;
     }
     __device__ float sample(double x, float cv, int aux) const {
-        return tof_weight_unscaled<Lut>(x, t, PerRay ? __int_as_float(aux) : t.inv_sqrt2_sig) * cv;
+        return tof_weight_unscaled<Lut>(x, t, PerRay ? __int_as_float(aux) : t.u_per_mm) * cv;
     }
 };
 
