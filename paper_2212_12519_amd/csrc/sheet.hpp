@@ -168,32 +168,40 @@ __device__ __forceinline__ void col_put(float* col, int ia, int ib, float pa, fl
 }
 
 // Flush the sheet of line (p, U0, dU) with contiguous atomics and clear it: only the planes
-// whose thread accumulated something (touched), listed in tl[], and with the (plane, z)
-// entries spread over all threads (consecutive threads take consecutive z of a plane).
-// Every thread of the workgroup calls it; the caller synchronises before and after.
+// whose thread accumulated something (touched), listed in tl[], only the z entries between the
+// lowest and the highest any of them wrote ([zlo, zhi] of each thread, united over the
+// workgroup), and with the (plane, z) entries spread over all threads (consecutive threads take
+// consecutive z of a plane).  Every thread of the workgroup calls it; the caller synchronises
+// before and after.
 __device__ __forceinline__ void sheet_flush(float* __restrict__ img, float* col, const GeomK& g, int p, double U0,
-                                            double dU, bool touched, int nw, int cs, int* tl, int* tcount) {
+                                            double dU, bool touched, int zlo, int zhi, int nw, int cs, int* tl,
+                                            int* tcount) {
     constexpr int B = kSheetBlock;
     const int tid = threadIdx.x, lane = (int)__lane_id(), wave = tid >> 6;
     const unsigned long long bal = __ballot(touched);
-    if (lane == 0) tcount[wave] = __popcll(bal);
+    // per wave: touched count (bits 0-7), lowest z (bits 8-15), highest z (bits 16-23); nw <= 128
+    const int wlo = wave_min(touched ? max(zlo, 0) : 255), whi = wave_max(touched ? min(zhi, nw - 1) : 0);
+    if (lane == 0) tcount[wave] = __popcll(bal) | (wlo << 8) | (whi << 16);
     __syncthreads();
-    int off = 0, nt = 0;
+    int off = 0, nt = 0, z0 = 255, z1 = 0;
     for (int w = 0; w < B / 64; ++w) {
         const int c = tcount[w];
-        off += (w < wave) ? c : 0;
-        nt += c;
+        off += (w < wave) ? (c & 0xff) : 0;
+        nt += c & 0xff;
+        z0 = min(z0, (c >> 8) & 0xff);
+        z1 = max(z1, (c >> 16) & 0xff);
     }
     if (touched) tl[off + __popcll(bal & ((1ull << lane) - 1ull))] = tid;
     __syncthreads();
     const int su = (p == 0) ? g.stride[1] : g.stride[0];
     const int sp = g.stride[p];
     const int nu = (p == 0) ? g.n[1] : g.n[0];
-    const int total = nt * nw;
-    const float inv_nw = 1.0f / (float)nw;
+    const int nz = max(z1 - z0 + 1, 0);
+    const int total = nt * nz;
+    const float inv_nz = 1.0f / (float)max(nz, 1);
     for (int e = tid; e < total; e += B) {
-        // e / nw: (e + 1/2) / nw stays >= 1/(2 nw) away from an integer, far above float error
-        const int pi = (int)(((float)e + 0.5f) * inv_nw), j = e - pi * nw;
+        // e / nz: (e + 1/2) / nz stays >= 1/(2 nz) away from an integer, far above float error
+        const int pi = (int)(((float)e + 0.5f) * inv_nz), j = z0 + e - pi * nz;
         const int k = tl[pi];
         float* cp = col + j * cs + k;
         const float v = *cp;
@@ -248,6 +256,7 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
         for (int q = tid; q < nw * cs; q += B) col[q] = 0.0f;
     // current sheet (block-uniform copies in registers, updated after barriers)
     bool sh_on = false, touched = false;  // touched: this thread's plane holds sheet values
+    int zlo = INT_MAX, zhi = INT_MIN;      // z entries it wrote since the last flush (pairs jc, jc + 1)
     int sh_p = -1, sh_kmax = -1;
     double sh_U0 = 0.0, sh_dU = 0.0;
     for (int grp = 0; grp < groups; ++grp) {
@@ -376,8 +385,10 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
             const int h = list[li];
             const bool same_line = sh_on && pax[h] == sh_p && U0[h] == sh_U0 && dU[h] == sh_dU;
             if (sh_on && !same_line) {
-                sheet_flush(img, col, g, sh_p, sh_U0, sh_dU, touched, nw, cs, tl, masks);
+                sheet_flush(img, col, g, sh_p, sh_U0, sh_dU, touched, zlo, zhi, nw, cs, tl, masks);
                 touched = false;
+                zlo = INT_MAX;
+                zhi = INT_MIN;
                 __syncthreads();
                 sh_on = false;
             }
@@ -436,6 +447,8 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
                     if (v != 0.0f && j0 != jc) {
                         col_put(col, ia, ib, preA, accA, preB, accB);
                         jc = j0;
+                        zlo = min(zlo, jc);
+                        zhi = max(zhi, jc + 1);
                         col_get(col, jc, k, nw, cs, ia, ib, preA, preB);
                         accA = 0.0f;
                         accB = 0.0f;
@@ -464,7 +477,7 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
             __syncthreads();
         }
     }
-    if (sh_on) sheet_flush(img, col, g, sh_p, sh_U0, sh_dU, touched, nw, cs, tl, masks);
+    if (sh_on) sheet_flush(img, col, g, sh_p, sh_U0, sh_dU, touched, zlo, zhi, nw, cs, tl, masks);
     __syncthreads();  // the LDS may be reused by the caller
 }
 
