@@ -24,7 +24,7 @@
  *   Coordinates: float32, array of structures [n][3] = (x, y, z) in mm.
  *   Image: float32, C order [dim[0]][dim[1]][dim[2]] (axis 2 fastest); the
  *     centre of voxel (i, j, k) is origin + (i, j, k) * voxsize.  Voxels
- *     outside the grid read as zero.  dim[0]*dim[1]*dim[2] <= 2^30.
+ *     outside the grid read as zero.  dim[0]*dim[1]*dim[2] < 2^30.
  *   Principal axis: argmax_a |end_a - start_a| in mm (float32 differences,
  *     first axis on ties).  The ray is the segment start -> end: plane k is
  *     visited iff its ray parameter t in [0, 1].
@@ -67,7 +67,7 @@ extern "C" {
 enum pp_status {
     PP_OK = 0,
     PP_EINVAL_PTR = 1,  /* a required pointer is NULL */
-    PP_EINVAL_GEOM = 2, /* dim <= 0, voxel count > 2^30, voxsize <= 0 or non-finite, origin non-finite */
+    PP_EINVAL_GEOM = 2, /* dim <= 0, voxel count >= 2^30, voxsize <= 0 or non-finite, origin non-finite */
     PP_EINVAL_TOF = 3,  /* n_bins not in [1, 256], bin_width/sigma/n_sigmas <= 0 or non-finite, bad table,
                          * per-ray sigma with a table, per-ray parameters where unsupported */
     PP_EINVAL_N = 4,    /* negative count, or a count/slot argument out of range */

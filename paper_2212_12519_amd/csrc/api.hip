@@ -33,7 +33,7 @@ int make_geom(const pp_image_t* gi, GeomK& g) {
     for (int a = 0; a < 3; ++a) {
         if (gi->dim[a] <= 0 || !(gi->voxsize[a] > 0.0f)) return PP_EINVAL_GEOM;
         nv *= gi->dim[a];
-        if (nv > (int64_t(1) << 30)) return PP_EINVAL_GEOM;
+        if (nv >= (int64_t(1) << 30)) return PP_EINVAL_GEOM;  // byte offsets of the image fit 32 bits
     }
     for (int a = 0; a < 3; ++a) {
         g.o[a] = gi->origin[a];

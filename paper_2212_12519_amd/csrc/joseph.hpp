@@ -252,12 +252,30 @@ __device__ __forceinline__ Stencil stencil_at(const RayK& r, int k) {
     return st;
 }
 
+// The image as a raw buffer: loads take 32-bit byte offsets, and an offset at or beyond the
+// image's end reads 0 (the hardware range check).  Neighbours outside the grid are given the
+// offset 0xFFFFFFFF, so the zero padding of the stencil costs a select instead of a branch per
+// neighbour.  Byte offsets fit 32 bits: grids hold fewer than 2^30 voxels.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t img_buffer(const float* img, const GeomK& g) {
+    const unsigned bytes = (unsigned)g.n[0] * (unsigned)g.n[1] * (unsigned)g.n[2] * 4u;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(img), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ float img_load(__amdgpu_buffer_rsrc_t ib, bool ok, int idx) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ib, ok ? (unsigned)idx * 4u : 0xFFFFFFFFu, 0, 0));
+}
+
 // bilinear interpolation with zero padding
-__device__ __forceinline__ float stencil_gather(const float* __restrict__ img, const RayK& r, const Stencil& st) {
-    const float v00 = (st.i0ok && st.j0ok) ? img[st.base] : 0.0f;
-    const float v01 = (st.i0ok && st.j1ok) ? img[st.base + r.sw] : 0.0f;
-    const float v10 = (st.i1ok && st.j0ok) ? img[st.base + r.su] : 0.0f;
-    const float v11 = (st.i1ok && st.j1ok) ? img[st.base + r.su + r.sw] : 0.0f;
+__device__ __forceinline__ float stencil_gather(__amdgpu_buffer_rsrc_t ib, const RayK& r, const Stencil& st) {
+    // the neighbours' indices as additions to the base (an empty asm keeps the compiler from
+    // turning them back into products, which are quarter-rate instructions)
+    int base = st.base;
+    asm volatile("" : "+v"(base));
+    const int b01 = base + r.sw, b10 = base + r.su;
+    const float v00 = img_load(ib, st.i0ok && st.j0ok, base);
+    const float v01 = img_load(ib, st.i0ok && st.j1ok, b01);
+    const float v10 = img_load(ib, st.i1ok && st.j0ok, b10);
+    const float v11 = img_load(ib, st.i1ok && st.j1ok, b10 + r.sw);
     const float gu = 1.0f - st.fu, gw = 1.0f - st.fw;
     return gu * (gw * v00 + st.fw * v01) + st.fu * (gw * v10 + st.fw * v11);
 }

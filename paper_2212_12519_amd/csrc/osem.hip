@@ -55,10 +55,11 @@ struct ModeOsem {
         const int b = bins[l];
         if (b < 0 || b >= t.nb || !ray_setup(src, l, g, r)) return false;
         if (!tof_window_rel(r, t.c0 + b * t.bw, t.lo, t.hi)) return false;
+        const __amdgpu_buffer_rsrc_t ib = img_buffer(x, g);
         float fwd = 0.0f;
         for (int k = r.k_lo; k <= r.k_hi; ++k) {
             const float w = tof_weight_unscaled<Lut>(fma((double)k, r.ds, r.s0), t, t.u_per_mm);
-            fwd += w * stencil_gather(x, r, stencil_at(r, k));
+            fwd += w * stencil_gather(ib, r, stencil_at(r, k));
         }
         const float ybar = r.ell * kTofScale<Lut> * fwd + bg;
         if (!(ybar > 0.0f)) return false;

@@ -29,10 +29,11 @@ __global__ void __launch_bounds__(kBlock) k_fwd(RaySrc src,
                                                 float* __restrict__ p, const int32_t* __restrict__ order) {
     const int64_t l = ray_index(order, n);
     if (l < 0) return;
+    const __amdgpu_buffer_rsrc_t ib = img_buffer(img, g);
     RayK r;
     float acc = 0.0f;
     if (ray_setup(src, l, g, r)) {
-        for (int k = r.k_lo; k <= r.k_hi; ++k) acc += stencil_gather(img, r, stencil_at(r, k));
+        for (int k = r.k_lo; k <= r.k_hi; ++k) acc += stencil_gather(ib, r, stencil_at(r, k));
         acc *= r.ell;
     }
     p[l] = acc;
@@ -51,6 +52,7 @@ __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(RaySrc src,
                                                        TofK t, const float* __restrict__ img,
                                                        float* __restrict__ p, const int32_t* __restrict__ order) {
     constexpr bool kWaveSync = PerRay;
+    const __amdgpu_buffer_rsrc_t ib = img_buffer(img, g);
     const int64_t l = ray_index(order, n);
     const int b = l >= 0 ? bins[l] : -1;
     float acc = 0.0f;
@@ -67,13 +69,13 @@ __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(RaySrc src,
         for (int k = k0; k <= k1; ++k) {
             if (k >= lo && k <= hi) {
                 const float w = tof_weight_unscaled<Lut>(fma((double)k, r.ds, r.s0), t, q.inv);
-                acc += w * stencil_gather(img, r, stencil_at(r, k));
+                acc += w * stencil_gather(ib, r, stencil_at(r, k));
             }
         }
     } else if (on) {
         for (int k = r.k_lo; k <= r.k_hi; ++k) {
             const float w = tof_weight_unscaled<Lut>(fma((double)k, r.ds, r.s0), t, q.inv);
-            acc += w * stencil_gather(img, r, stencil_at(r, k));
+            acc += w * stencil_gather(ib, r, stencil_at(r, k));
         }
     }
     if (on) acc *= r.ell * kTofScale<Lut>;
@@ -97,13 +99,14 @@ __global__ void k_fwd_tof_sino(RaySrc src, int64_t n, GeomK g,
     const int64_t l0 = (int64_t)blockIdx.x * nt;
     const int64_t l = l0 + threadIdx.x;
     for (int b = 0; b < t.nb; ++b) lds[b * nt + threadIdx.x] = 0.0f;
+    const __amdgpu_buffer_rsrc_t ib = img_buffer(img, g);
     RayK r;
     TofRay q;
     if (l < n && tof_ray<PerRay>(t, l, q) && ray_setup(src, l, g, r)) {
         if (PerRay) r.s0 -= q.shift;
         float* mine = lds + threadIdx.x;
         for (int k = r.k_lo; k <= r.k_hi; ++k) {
-            const float v = stencil_gather(img, r, stencil_at(r, k));
+            const float v = stencil_gather(ib, r, stencil_at(r, k));
             if (v == 0.0f) continue;
             const double s = fma((double)k, r.ds, r.s0);
             int b_lo, b_hi;

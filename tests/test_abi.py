@@ -60,7 +60,7 @@ def test_error_codes(lib):
     assert lib.pp_fwd(DUMMY, DUMMY, 5, None, DUMMY, DUMMY, None, None) == PP_EINVAL_PTR
     for bad in (_geom(dim=(0, 4, 4)), _geom(vs=(1.0, 0.0, 1.0)), _geom(vs=(1.0, -2.0, 1.0)),
                 _geom(vs=(float("nan"), 1.0, 1.0)), _geom(origin=(float("inf"), 0.0, 0.0)),
-                _geom(dim=(2048, 2048, 512))):
+                _geom(dim=(2048, 2048, 512)), _geom(dim=(1024, 1024, 1024))):
         assert lib.pp_fwd(DUMMY, DUMMY, 5, bad, DUMMY, DUMMY, None, None) == PP_EINVAL_GEOM
         assert lib.pp_back(DUMMY, DUMMY, 5, bad, DUMMY, DUMMY, None, None) == PP_EINVAL_GEOM
     from paper_2212_12519_amd._lib import CTof
