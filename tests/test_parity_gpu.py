@@ -186,6 +186,32 @@ def test_degenerate_inputs(gpu):
     assert not torch.any(z)
 
 
+def test_largest_grid_far_corner(gpu):
+    """The largest grid the library takes (1023 x 1024 x 1024 voxels, just under 2^30; a 4.3 GB image):
+    axis-aligned rays through voxel centres of the far corner's row, column and line in an image of
+    ones give exactly n_p h_p (pin 1) -- the forward gathers there use byte offsets near 2^32 -- and
+    the back projection of ones along the last line puts h_p into the very last voxel."""
+    dim, vs, origin = (1023, 1024, 1024), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0)
+    G = gpu.ImageGeom(dim, vs, origin)
+    dev = torch.device("cuda")
+    img = torch.ones(dim, device=dev)
+    a, b, c = (d - 1 for d in dim)
+    xs = torch.tensor([[-5, b, c], [a, -5, c], [a, b, -5], [-5, 512, 511]], dtype=torch.float32, device=dev)
+    xe = torch.tensor([[dim[0] + 5, b, c], [a, dim[1] + 5, c], [a, b, dim[2] + 5], [dim[0] + 5, 512, 511]],
+                      dtype=torch.float32, device=dev)
+    p = gpu.fwd(xs, xe, G, img)
+    assert p.tolist() == [float(dim[0]), float(dim[1]), float(dim[2]), float(dim[0])]
+    T = gpu.TofParams(2.0, 1000.0, 3.0, 1)  # one bin much wider than the rays: weights near erf(1/(2 sqrt 2 1000))
+    pt = gpu.fwd_tof_sino(xs, xe, G, T, img)
+    assert torch.all(pt[:, 0] > 0)
+    del img
+    bk = torch.zeros(dim, device=dev)
+    gpu.back(xs[2:3].contiguous(), xe[2:3].contiguous(), G, torch.ones(1, device=dev), bk)
+    torch.cuda.synchronize()
+    assert float(bk[a, b, c]) == 1.0 and float(bk[a, b, 0]) == 1.0
+    assert float(bk.sum(dtype=torch.float64)) == float(dim[2])
+
+
 # -------------------------------------------------- clinical sizes, sampled
 
 @pytest.fixture(scope="module")
