@@ -474,7 +474,8 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
             // threads past the line's last plane (k >= cs possible) never leave the initial state
             if (kin) col_put(col, ia, ib, preA, accA, preB, accB);
             touched = touched || jc != kNoEntry;  // jc may be an out-of-grid entry after writes
-            __syncthreads();
+            // no barrier between runs: a run writes only the thread's own column; other threads read
+            // the columns only in a flush, whose first barrier follows every wave's last write here
         }
     }
     if (sh_on) sheet_flush(img, col, g, sh_p, sh_U0, sh_dU, touched, zlo, zhi, nw, cs, tl, masks);
