@@ -280,17 +280,9 @@ __device__ __forceinline__ float stencil_gather(__amdgpu_buffer_rsrc_t ib, const
     return gu * (gw * v00 + st.fw * v01) + st.fu * (gw * v10 + st.fw * v11);
 }
 
-// transpose of stencil_gather: img[...] += weight * c (hardware float atomics)
-__device__ __forceinline__ void stencil_scatter(float* __restrict__ img, const RayK& r, const Stencil& st, float c) {
-    const float gu = 1.0f - st.fu, gw = 1.0f - st.fw;
-    if (st.i0ok && st.j0ok) unsafeAtomicAdd(img + st.base, gu * gw * c);
-    if (st.i0ok && st.j1ok) unsafeAtomicAdd(img + st.base + r.sw, gu * st.fw * c);
-    if (st.i1ok && st.j0ok) unsafeAtomicAdd(img + st.base + r.su, st.fu * gw * c);
-    if (st.i1ok && st.j1ok) unsafeAtomicAdd(img + st.base + r.su + r.sw, st.fu * st.fw * c);
-}
-
-// Wave-cooperative version of stencil_scatter; every lane of the wave must
-// call it (inactive lanes with active == false).  Float atomics that hit the
+// Transpose of stencil_gather for the direct path: img[...] += weight * c with hardware float
+// atomics, wave-cooperative; every lane of the wave must call it (inactive lanes with
+// active == false).  Float atomics that hit the
 // same address within one instruction are serialised by the memory system,
 // which is exactly what nearly coincident rays of a wave produce.  Lanes are
 // therefore grouped into runs of equal stencil (same base voxel and principal

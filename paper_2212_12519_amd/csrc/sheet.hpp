@@ -15,16 +15,16 @@
 // each thread becomes a plane k: it walks the run's rays and accumulates the
 // W-interpolated values into its own LDS column (thread-private addresses: no
 // atomics, no bank conflicts; the current pair of z entries is kept in
-// registers and written back by read-modify-write when z changes), then the
-// waves flush the sheet with contiguous, duplicate-free atomics -- one memory
-// request per ~16 values instead of one per value.  The column stride is the
-// grid's longest line + 1, so that two workgroups fit a CU's LDS on clinical
-// grids: the loop is latency-bound and needs the second workgroup's waves.  The
+// registers, its column values read when z moves to it and written back when z
+// moves on), then the waves flush the sheet with contiguous, duplicate-free
+// atomics -- one memory request per ~16 values instead of one per value.  The
+// column stride is the grid's longest line + 1, so that two workgroups fit a
+// CU's LDS on clinical grids: the loop needs the second workgroup's waves.  The
 // u-weights (1 - fu, fu) are shared by the run and applied at the flush.  Rays
 // in short runs (or with p == 2, or grids whose axis 2 exceeds the LDS column)
-// take the direct wave-synchronous,
-// run-combined scatter.  The arithmetic per (ray, plane) sample is the same
-// as in the direct path; only the order of float additions differs.
+// take the direct wave-synchronous, run-combined scatter.  The arithmetic per
+// (ray, plane) sample is the same as in the direct path; only the order of
+// float additions differs.
 #pragma once
 
 #include "joseph.hpp"
