@@ -62,7 +62,7 @@
 extern "C" {
 #endif
 
-#define PP_ABI_VERSION 5
+#define PP_ABI_VERSION 6
 
 enum pp_status {
     PP_OK = 0,
@@ -101,7 +101,7 @@ typedef struct pp_image {
  * sigma is not a positive finite number, or whose offset is not finite, contributes nothing
  * (data, not an error; a sigma below 1e-30 mm is taken as 1e-30 mm).  A table kernel takes
  * offset_per_ray but not sigma_per_ray (PP_EINVAL_TOF).  Accepted by the projectors and
- * pp_count_samples; pp_lm_osem_accumulate returns PP_EINVAL_TOF when either is set. */
+ * pp_count_samples; pp_lm_osem_subset_batched returns PP_EINVAL_TOF when either is set. */
 typedef struct pp_tof {
     float bin_width;     /* mm, > 0 */
     float sigma;         /* mm, > 0 (FWHM / 2.355) */
@@ -131,7 +131,10 @@ int pp_back(const float* xstart, const float* xend, int64_t n_lors, const pp_ima
             const float* p, const int32_t* order, void* stream);
 
 /* TOF sinogram forward projection (Sec. 2.1, 2.2): all n_bins of every ray in
- * one traversal.  p: [n_lors][n_bins] (bin fastest), overwritten. */
+ * one traversal.  p: [n_lors][n_bins] (bin fastest), overwritten.
+ * Both TOF sinogram calls take n_lors < 2^31 (else PP_EINVAL_N); larger LOR
+ * sets are projected in chunks of consecutive LORs (xstart + 3 c, xend + 3 c,
+ * p + c n_bins), back projections accumulating into the same image. */
 int pp_fwd_tof_sino(const float* xstart, const float* xend, int64_t n_lors, const pp_image_t* geom,
                     const pp_tof_t* tof, const float* img, float* p, void* stream);
 
@@ -182,6 +185,23 @@ int pp_gather_events(const float* xstart, const float* xend, const int16_t* tof_
 int pp_count_samples(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n,
                      const pp_image_t* geom, const pp_tof_t* tof, int32_t* counts, void* stream);
 
+/* The Gaussian kernel of `tof` (sigma, n_sigmas, bin_width; its lut and
+ * per-ray fields are ignored) as a table for pp_tof_t.lut: the bin weight
+ * w(x) = G(x + bin_width/2) - G(x - bin_width/2) of Sec. 2.1 (G truncated at
+ * n_sigmas as in Sec. 2.6) over its support [-win, win], win = n_sigmas
+ * sigma + bin_width/2, at x_i = -win + i dx, i in [0, n), with
+ * n = ceil(2 win / dx_max) + 1 and dx = 2 win / (n - 1) (the largest spacing
+ * <= dx_max whose last entry lands on +win).  Evaluated in float64 on the
+ * device, stored as float32.
+ *   lut:      DEVICE float32 [capacity], or NULL to query the size only;
+ *   n_out, x0_out, dx_out: HOST outputs n, -win, dx (each may be NULL);
+ *             pass x0_out / dx_out as pp_tof_t.lut_x0 / lut_dx.
+ * Errors: PP_EINVAL_TOF (sigma, n_sigmas or bin_width not positive-finite),
+ * PP_EINVAL_N (dx_max not positive-finite, n > 2^24, or capacity < n with
+ * lut set). */
+int pp_tof_gaussian_table(const pp_tof_t* tof, float dx_max, float* lut, int32_t capacity, int32_t* n_out,
+                          float* x0_out, float* dx_out, void* stream);
+
 /* ------------------------------------------------------------------------
  * Crystal-index events (index-based LOR geometry).  A scanner identifies a
  * listmode event by the two crystals that detected it; the entry points
@@ -224,31 +244,34 @@ int pp_gather_crystal_events(const int32_t* pair, const int16_t* tof_bin, const 
  * Batched listmode TOF OSEM (the paper's listmode OSEM of Sec. 2.6, run for
  * many short frames at once).  One "step" of a frame is one ordered-subset
  * update with subset j = {events e : e mod n_sub == j}:
- *     acc  = sum_{e in subset j} a_e / (a_e . x' + bg)     (pp_lm_osem_accumulate)
+ *     acc  = sum_{e in subset j} a_e / (a_e . x' + bg)     (pp_lm_osem_subset_batched)
  *     x_v <- x_v * acc'_v / (sens_v / n_sub) if sens_v > 0, else 0;  acc <- 0
- *                                                           (pp_lm_osem_update)
+ *                                                           (pp_osem_update_batched)
  * An event whose expectation a_e . x' + bg is not positive contributes nothing.
  * Without the resolution model (x_fwd == NULL) x' = x and acc' = acc.  With it
  * (x_fwd and tmp set) the system model is the projector after the Gaussian
  * blur G of pp_gauss3d (the paper's OSEM includes such an image-based model):
  * x' = x_fwd = G x, acc' = G acc, and sens must be G applied to the back
  * projection of ones; before the first step x_fwd must hold G x
- * (pp_gauss3d(x, x_fwd, tmp, ...)).  pp_lm_osem_update keeps x_fwd = G x.
+ * (pp_gauss3d(x, x_fwd, tmp, ...)).  pp_osem_update_batched keeps x_fwd = G x.
  * Event storage of a frame is SUBSET-MAJOR: subset j occupies the contiguous
  * range [off_j, off_j + n_j), n_j = n / n_sub + (j < n mod n_sub),
  * off_j = j (n / n_sub) + min(j, n mod n_sub), in any order inside the range
  * (pp_lm_presort with n_sub, then pp_gather_events, produces exactly this).
  * The slot table lives in DEVICE memory and is read by the kernels at run
  * time, so one captured graph of steps serves any mix of frames: the host
- * rewrites slots between replays.  pp_lm_osem_update advances `subset`
+ * rewrites slots between replays.  pp_osem_update_batched advances `subset`
  * ((subset + 1) mod n_sub) and decrements `steps_left` of every slot it
  * updates; slots with active == 0 or steps_left <= 0 are skipped by both
- * calls.  All frames of one call share the image grid and TOF parameters.
+ * calls, and so are malformed slots (n_sub < 1, subset outside [0, n_sub),
+ * n_events < 0), which the library cannot reject on the host because the
+ * table is device memory.  All frames of one call share the image grid and TOF parameters.
  * Each frame owns its x, acc (zero before its first step) and events, so a
  * frame's result does not depend on the other frames of the batch (up to
  * the order of atomic adds).
  * ------------------------------------------------------------------------ */
-typedef struct pp_osem_slot {
+/* One frame of the batch (a "slot" of the table). */
+typedef struct pp_frame_desc {
     const float* xstart;     /* [n_events][3] (unused with crystal_pair) */
     const float* xend;       /* [n_events][3] (unused with crystal_pair) */
     const int16_t* tof_bin;  /* [n_events] */
@@ -269,7 +292,7 @@ typedef struct pp_osem_slot {
     const int32_t* crystal_pair; /* [n_events][2] crystal-index events (8-byte aligned), or NULL */
     const float* crystal_xyz;    /* [n_crystals][3] crystal table, used with crystal_pair (a slot with
                                   * crystal_pair but no table or n_crystals < 1 is skipped by every call) */
-} pp_osem_slot_t;
+} pp_frame_desc_t;
 
 /* Work chunks a slot needs per step (events of the largest subset / 1024,
  * rounded up).  The host sets chunk_begin of slot s to the sum over slots
@@ -279,16 +302,16 @@ int64_t pp_osem_chunks(int64_t n_events, int32_t n_sub);
 /* Fused forward -> 1/(ybar) -> back projection of the current subset of
  * every live slot into its acc.  d_slots: DEVICE array of n_slots entries.
  * tof: one kernel for all slots (per-ray parameters: PP_EINVAL_TOF). */
-int pp_lm_osem_accumulate(const pp_osem_slot_t* d_slots, int32_t n_slots, const pp_image_t* geom,
-                          const pp_tof_t* tof, void* stream);
+int pp_lm_osem_subset_batched(const pp_frame_desc_t* d_slots, int32_t n_slots, const pp_image_t* geom,
+                              const pp_tof_t* tof, void* stream);
 
 /* Multiplicative image update of every live slot, then acc <- 0, subset
  * advanced, steps_left decremented.  geom: the slots' common image grid.
  * res_fwhm: host array of 3 FWHM values in mm (per image axis) of the
  * resolution model, applied to the slots that have x_fwd set; NULL = FWHM 0
  * (G = identity).  Errors: PP_EINVAL_RES as for pp_gauss3d. */
-int pp_lm_osem_update(pp_osem_slot_t* d_slots, int32_t n_slots, const pp_image_t* geom, const float* res_fwhm,
-                      void* stream);
+int pp_osem_update_batched(pp_frame_desc_t* d_slots, int32_t n_slots, const pp_image_t* geom,
+                           const float* res_fwhm, void* stream);
 
 /* OSEM start image: x_v = 1 where sens_v > 0, else 0. */
 int pp_osem_init(float* x, const float* sens, int64_t n_vox, void* stream);

@@ -58,6 +58,7 @@ def _load():
     lib.orc_count_samples.restype = I64
     lib.orc_lm_osem.argtypes = [P, P, P, I64, P, P, P] + tof + [P, ctypes.c_double, I32, I32, P, P]
     lib.orc_gauss3d.argtypes = [P, P, P, P, P]
+    lib.orc_tof_kernel.argtypes = [P, I64, F, F, F, P, I32, ctypes.c_double, ctypes.c_double, P]
     lib.orc_max_threads.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -211,6 +212,16 @@ def count_samples(xstart, xend, origin, voxsize, dim, tof=None, bins=None, per_r
     tot = lib.orc_count_samples(_ptr(xs), _ptr(xe), xs.shape[0], _ptr(o), _ptr(h), _ptr(d), *ta,
                                 _ptr(b) if b is not None else None, _ptr(pr) if pr is not None else None)
     return (int(tot), pr) if per_ray else int(tot)
+
+
+def tof_kernel(x, tof):
+    """The TOF bin weight w(x) of one bin centred at 0 (Gaussian or table of `tof`), float64."""
+    lib = _load()
+    xx = np.ascontiguousarray(np.asarray(x, dtype=np.float64).ravel())
+    ta = _tofargs(tof)
+    out = np.empty_like(xx)
+    lib.orc_tof_kernel(_ptr(xx), xx.size, ta[0], ta[1], ta[2], ta[5], ta[6], ta[7], ta[8], _ptr(out))
+    return out
 
 
 def _fwhm3(fwhm):

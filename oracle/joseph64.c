@@ -455,6 +455,14 @@ int64_t orc_count_samples(const float* xs, const float* xe, int64_t n, const flo
     return total;
 }
 
+/* The TOF bin weight w(x) of a single bin centred at x = 0 (Gaussian or table), at n points:
+ * the function every TOF projection evaluates at each plane sample. */
+void orc_tof_kernel(const double* x, int64_t n, float bin_width, float sigma, float n_sigmas, const float* lut,
+                    int32_t lut_n, double lut_x0, double lut_dx, double* w) {
+    tof64 tf = mktof(bin_width, sigma, n_sigmas, 0.0f, 1, lut, lut_n, lut_x0, lut_dx, NULL, NULL);
+    for (int64_t i = 0; i < n; ++i) w[i] = tof_weight(x[i], 0, &tf);
+}
+
 /* Image-based resolution model (the Gaussian blur the paper's listmode OSEM
  * reconstructions include, Sec. 2.6): a shift-invariant 3D Gaussian of the
  * given FWHM per axis (mm), applied as a discrete convolution on the voxel

@@ -161,8 +161,8 @@ def load():
         "pp_lm_presort": [P, P, P, I64, G, T, I32, P, P, ctypes.c_size_t, P],
         "pp_gather_events": [P, P, P, P, I64, P, P, P, P],
         "pp_osem_init": [P, P, I64, P],
-        "pp_lm_osem_accumulate": [P, I32, G, T, P],
-        "pp_lm_osem_update": [P, I32, G, P, P],
+        "pp_lm_osem_subset_batched": [P, I32, G, T, P],
+        "pp_osem_update_batched": [P, I32, G, P, P],
         "pp_gauss3d": [P, P, P, G, P, P],
         "pp_fill": [P, I64, ctypes.c_float, P],
         "pp_count_samples": [P, P, P, I64, G, T, P, P],
@@ -173,6 +173,8 @@ def load():
         "pp_lm_presort_crystals": [P, I32, P, P, I64, G, T, I32, P, P, ctypes.c_size_t, P],
         "pp_count_samples_crystals": [P, I32, P, P, I64, G, T, P, P],
         "pp_gather_crystal_events": [P, P, P, I64, P, P, P],
+        "pp_tof_gaussian_table": [T, ctypes.c_float, P, I32, ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_float),
+                                  ctypes.POINTER(ctypes.c_float), P],
     }
     for name, argt in sig.items():
         f = getattr(lib, name)

@@ -12,7 +12,7 @@
 using namespace ppmi;
 
 static_assert(sizeof(pp_tof_t) == 64, "pp_tof_t layout");
-static_assert(sizeof(pp_osem_slot_t) == 120, "pp_osem_slot_t layout");
+static_assert(sizeof(pp_frame_desc_t) == 120, "pp_frame_desc_t layout");
 
 namespace {
 
@@ -132,6 +132,9 @@ constexpr int64_t kMaxRays = ((int64_t(1) << 31) - 1) * 64;
 
 int check_n(int64_t n) { return (n < 0 || n > kMaxRays) ? PP_EINVAL_N : PP_OK; }
 
+// TOF sinogram calls: the sheet back projection carries ray indices in 32 bits
+int check_n_sino(int64_t n) { return (n < 0 || n >= (int64_t(1) << 31)) ? PP_EINVAL_N : PP_OK; }
+
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 RaySrc coords(const float* xs, const float* xe) { return RaySrc{xs, xe, nullptr, 0}; }
@@ -204,7 +207,7 @@ int pp_fwd_tof_sino(const float* xstart, const float* xend, int64_t n, const pp_
     TofK t;
     PP_TRY(make_geom(geom, g));
     PP_TRY(make_tof(tof, t));
-    PP_TRY(check_n(n));
+    PP_TRY(check_n_sino(n));
     if (n == 0) return PP_OK;
     if (!xstart || !xend || !img || !p) return PP_EINVAL_PTR;
     return hip_status(launch_fwd_tof_sino(coords(xstart, xend), n, g, t, img, p, as_stream(stream)));
@@ -216,7 +219,7 @@ int pp_back_tof_sino(const float* xstart, const float* xend, int64_t n, const pp
     TofK t;
     PP_TRY(make_geom(geom, g));
     PP_TRY(make_tof(tof, t));
-    PP_TRY(check_n(n));
+    PP_TRY(check_n_sino(n));
     if (n == 0) return PP_OK;
     if (!xstart || !xend || !img || !p) return PP_EINVAL_PTR;
     return hip_status(launch_back_tof_sino(coords(xstart, xend), n, g, t, img, p, as_stream(stream)));
@@ -256,6 +259,28 @@ int pp_count_samples(const float* xstart, const float* xend, const int16_t* tof_
     if (n == 0) return PP_OK;
     if (!xstart || !xend || !counts) return PP_EINVAL_PTR;
     return hip_status(launch_count(coords(xstart, xend), tof_bin, n, g, t, counts, as_stream(stream)));
+}
+
+int pp_tof_gaussian_table(const pp_tof_t* tof, float dx_max, float* lut, int32_t capacity, int32_t* n_out,
+                          float* x0_out, float* dx_out, void* stream) {
+    if (!tof) return PP_EINVAL_PTR;
+    const double bw = tof->bin_width, sig = tof->sigma, ns = tof->n_sigmas;
+    if (!(std::isfinite(bw) && bw > 0.0 && std::isfinite(sig) && sig > 0.0 && std::isfinite(ns) && ns > 0.0))
+        return PP_EINVAL_TOF;
+    if (!(std::isfinite(dx_max) && dx_max > 0.0f)) return PP_EINVAL_N;
+    const double win = ns * sig + 0.5 * bw;
+    const double cells = std::ceil(2.0 * win / (double)dx_max);
+    if (!(cells + 1.0 <= (double)(1 << 24))) return PP_EINVAL_N;
+    const int n = (int)cells + 1;
+    // the nodes are placed where the projectors will interpolate them: at the float32 origin and
+    // spacing that pp_tof_t carries
+    const float x0 = (float)(-win), dx = (float)(2.0 * win / (double)(n - 1));
+    if (n_out) *n_out = n;
+    if (x0_out) *x0_out = x0;
+    if (dx_out) *dx_out = dx;
+    if (!lut) return PP_OK;
+    if (capacity < n) return PP_EINVAL_N;
+    return hip_status(launch_tof_gauss_table(lut, n, (double)x0, (double)dx, bw, sig, ns, as_stream(stream)));
 }
 
 int pp_fwd_crystals(const float* crystal_xyz, int32_t n_crystals, const int32_t* pair, int64_t n,
@@ -391,7 +416,7 @@ int pp_osem_init(float* x, const float* sens, int64_t n_vox, void* stream) {
 
 int64_t pp_osem_chunks(int64_t n_events, int32_t n_sub) { return osem_chunks(n_events, n_sub); }
 
-int pp_lm_osem_accumulate(const pp_osem_slot_t* d_slots, int32_t n_slots, const pp_image_t* geom,
+int pp_lm_osem_subset_batched(const pp_frame_desc_t* d_slots, int32_t n_slots, const pp_image_t* geom,
                           const pp_tof_t* tof, void* stream) {
     GeomK g;
     TofK t;
@@ -404,7 +429,7 @@ int pp_lm_osem_accumulate(const pp_osem_slot_t* d_slots, int32_t n_slots, const 
     return hip_status(launch_osem_accumulate(d_slots, n_slots, g, t, device_cus(), as_stream(stream)));
 }
 
-int pp_lm_osem_update(pp_osem_slot_t* d_slots, int32_t n_slots, const pp_image_t* geom, const float* res_fwhm,
+int pp_osem_update_batched(pp_frame_desc_t* d_slots, int32_t n_slots, const pp_image_t* geom, const float* res_fwhm,
                       void* stream) {
     GeomK g;
     GaussK k;

@@ -75,16 +75,17 @@ enum BlurOp {
     kOpZero = 2     // dst = blur(src) and acc = 0
 };
 
-__device__ __forceinline__ float* slot_field(const pp_osem_slot_t& s, int f) {
+__device__ __forceinline__ float* slot_field(const pp_frame_desc_t& s, int f) {
     return f == kFieldX ? s.x : f == kFieldXFwd ? s.x_fwd : f == kFieldAcc ? s.acc : s.tmp;
 }
 
-__device__ __forceinline__ bool slot_res_live(const pp_osem_slot_t& s) {
-    return s.active && s.steps_left > 0 && s.x_fwd != nullptr && s.tmp != nullptr;
+__device__ __forceinline__ bool slot_res_live(const pp_frame_desc_t& s) {
+    return s.active && s.steps_left > 0 && s.n_sub >= 1 && s.subset >= 0 && s.subset < s.n_sub &&
+           s.n_events >= 0 && s.x_fwd != nullptr && s.tmp != nullptr;
 }
 
 template <int Axis, int Op>
-__global__ void __launch_bounds__(kBlurBlock) k_osem_blur(const pp_osem_slot_t* __restrict__ slots, int n_slots,
+__global__ void __launch_bounds__(kBlurBlock) k_osem_blur(const pp_frame_desc_t* __restrict__ slots, int n_slots,
                                                           int64_t n_vox, GaussK k, GridDims d, int src_f,
                                                           int dst_f) {
     const int64_t total = (int64_t)n_slots * n_vox;
@@ -92,7 +93,7 @@ __global__ void __launch_bounds__(kBlurBlock) k_osem_blur(const pp_osem_slot_t* 
     for (int64_t i = (int64_t)blockIdx.x * kBlurBlock + threadIdx.x; i < total; i += stride) {
         const int si = (int)(i / n_vox);
         const int64_t v = i - (int64_t)si * n_vox;
-        const pp_osem_slot_t& s = slots[si];
+        const pp_frame_desc_t& s = slots[si];
         if (!slot_res_live(s)) continue;
         const float b = blur_at<Axis>(slot_field(s, src_f), v, k, d);
         if (Op == kOpUpdate) {
@@ -124,7 +125,7 @@ hipError_t launch_gauss3d(const float* src, float* dst, float* tmp, const GeomK&
     return hipGetLastError();
 }
 
-hipError_t launch_osem_res_update(pp_osem_slot_t* slots, int n_slots, const GeomK& g, const GaussK& k, int cus,
+hipError_t launch_osem_res_update(pp_frame_desc_t* slots, int n_slots, const GeomK& g, const GaussK& k, int cus,
                                   hipStream_t s) {
     const int64_t nv = (int64_t)g.n[0] * g.n[1] * g.n[2];
     const GridDims d = dims_of(g);

@@ -20,6 +20,8 @@ hipError_t launch_fwd_tof_sino(const RaySrc& src, int64_t n, const GeomK& g, con
                                const float* img, float* p, hipStream_t s);
 hipError_t launch_back_tof_sino(const RaySrc& src, int64_t n, const GeomK& g, const TofK& t,
                                 float* img, const float* p, hipStream_t s);
+hipError_t launch_tof_gauss_table(float* lut, int n, double x0, double dx, double bw, double sigma, double n_sigmas,
+                                  hipStream_t s);
 hipError_t launch_fwd_tof_lm(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g,
                              const TofK& t, const float* img, float* p, const int32_t* order, hipStream_t s);
 hipError_t launch_back_tof_lm(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g,
@@ -37,16 +39,16 @@ hipError_t launch_count(const RaySrc& src, const int16_t* bins, int64_t n, const
                         const TofK& t, int32_t* counts, hipStream_t s);
 
 int64_t osem_chunks(int64_t n_events, int32_t n_sub);
-hipError_t launch_osem_accumulate(const pp_osem_slot_t* slots, int n_slots, const GeomK& g, const TofK& t, int cus,
+hipError_t launch_osem_accumulate(const pp_frame_desc_t* slots, int n_slots, const GeomK& g, const TofK& t, int cus,
                                   hipStream_t s);
-hipError_t launch_osem_update(pp_osem_slot_t* slots, int n_slots, int64_t n_vox, int n_blocks, hipStream_t s);
-hipError_t launch_osem_advance(pp_osem_slot_t* slots, int n_slots, hipStream_t s);
+hipError_t launch_osem_update(pp_frame_desc_t* slots, int n_slots, int64_t n_vox, int n_blocks, hipStream_t s);
+hipError_t launch_osem_advance(pp_frame_desc_t* slots, int n_slots, hipStream_t s);
 hipError_t launch_fill(float* dst, int64_t n, float value, hipStream_t s);
 
 struct GaussK;
 hipError_t launch_gauss3d(const float* src, float* dst, float* tmp, const GeomK& g, const GaussK& k, int cus,
                           hipStream_t s);
-hipError_t launch_osem_res_update(pp_osem_slot_t* slots, int n_slots, const GeomK& g, const GaussK& k, int cus,
+hipError_t launch_osem_res_update(pp_frame_desc_t* slots, int n_slots, const GeomK& g, const GaussK& k, int cus,
                                   hipStream_t s);
 
 }  // namespace ppmi

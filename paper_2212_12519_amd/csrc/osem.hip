@@ -29,9 +29,12 @@ constexpr int kOsemBlock = 256;
 constexpr int kOsemGroups = 4;
 constexpr int64_t kOsemChunk = (int64_t)kSheetBlock * kOsemGroups;  // events of one work chunk
 
-// live: active with steps to run, and (without the resolution model, or with its scratch image)
-__device__ __forceinline__ bool slot_live(const pp_osem_slot_t& s) {
-    return s.active && s.steps_left > 0 && (s.x_fwd == nullptr || s.tmp != nullptr) &&
+// live: active with steps to run, a well-formed subset state (n_sub >= 1, 0 <= subset < n_sub,
+// n_events >= 0: anything else would place the subset's range outside the events), and (without
+// the resolution model, or with its scratch image) (coordinates, or a usable crystal table)
+__device__ __forceinline__ bool slot_live(const pp_frame_desc_t& s) {
+    return s.active && s.steps_left > 0 && s.n_sub >= 1 && s.subset >= 0 && s.subset < s.n_sub &&
+           s.n_events >= 0 && (s.x_fwd == nullptr || s.tmp != nullptr) &&
            (s.crystal_pair == nullptr || (s.crystal_xyz != nullptr && s.n_crystals > 0));
 }
 
@@ -72,10 +75,10 @@ struct ModeOsem {
 };
 
 template <bool Lut>
-__global__ void __launch_bounds__(kSheetBlock) k_osem_accumulate(const pp_osem_slot_t* __restrict__ slots,
+__global__ void __launch_bounds__(kSheetBlock) k_osem_accumulate(const pp_frame_desc_t* __restrict__ slots,
                                                                  int n_slots, GeomK g, TofK t, int nw_lds) {
     extern __shared__ double smem[];
-    const pp_osem_slot_t& last = slots[n_slots - 1];
+    const pp_frame_desc_t& last = slots[n_slots - 1];
     const int64_t total = last.chunk_begin + (last.active ? slot_chunks(last.n_events, last.n_sub) : 0);
     for (int64_t c = blockIdx.x; c < total; c += gridDim.x) {
         // largest slot index whose first chunk is <= c (block-uniform)
@@ -84,14 +87,14 @@ __global__ void __launch_bounds__(kSheetBlock) k_osem_accumulate(const pp_osem_s
             const int mid = (lo_s + hi_s + 1) >> 1;
             if (slots[mid].chunk_begin <= c) lo_s = mid; else hi_s = mid - 1;
         }
-        const pp_osem_slot_t& s = slots[lo_s];
+        const pp_frame_desc_t& s = slots[lo_s];
         if (!slot_live(s)) continue;  // block-uniform
         const int64_t n = s.n_events, ns = s.n_sub, j = s.subset;
         const int64_t base_n = n / ns, rem = n - base_n * ns;
         const int64_t n_j = base_n + (j < rem ? 1 : 0);
         const int64_t off_j = j * base_n + (j < rem ? j : rem);
         const int64_t q0 = (c - s.chunk_begin) * kOsemChunk;
-        if (q0 >= n_j) continue;
+        if (q0 < 0 || q0 >= n_j) continue;  // chunk offsets not from pp_osem_chunks: nothing to do
         ModeOsem<Lut> m{s.x_fwd ? s.x_fwd : s.x, s.tof_bin + off_j, s.bg, t};
         const RaySrc src = s.crystal_pair ? RaySrc{s.crystal_xyz, nullptr, reinterpret_cast<const int2*>(s.crystal_pair),
                                                    s.n_crystals}
@@ -100,14 +103,14 @@ __global__ void __launch_bounds__(kSheetBlock) k_osem_accumulate(const pp_osem_s
     }
 }
 
-__global__ void __launch_bounds__(kOsemBlock) k_osem_update(const pp_osem_slot_t* __restrict__ slots, int n_slots,
+__global__ void __launch_bounds__(kOsemBlock) k_osem_update(const pp_frame_desc_t* __restrict__ slots, int n_slots,
                                                             int64_t n_vox) {
     const int64_t total = (int64_t)n_slots * n_vox;
     const int64_t stride = (int64_t)gridDim.x * kOsemBlock;
     for (int64_t i = (int64_t)blockIdx.x * kOsemBlock + threadIdx.x; i < total; i += stride) {
         const int si = (int)(i / n_vox);
         const int64_t v = i - (int64_t)si * n_vox;
-        const pp_osem_slot_t& s = slots[si];
+        const pp_frame_desc_t& s = slots[si];
         if (!slot_live(s) || s.x_fwd != nullptr) continue;  // resolution-model slots: blur.hip
         const float sv = s.sens[v];
         const float a = s.acc[v];
@@ -116,9 +119,9 @@ __global__ void __launch_bounds__(kOsemBlock) k_osem_update(const pp_osem_slot_t
     }
 }
 
-__global__ void k_osem_advance(pp_osem_slot_t* slots, int n_slots) {
+__global__ void k_osem_advance(pp_frame_desc_t* slots, int n_slots) {
     for (int i = threadIdx.x; i < n_slots; i += blockDim.x) {
-        pp_osem_slot_t& s = slots[i];
+        pp_frame_desc_t& s = slots[i];
         if (!slot_live(s)) continue;
         s.subset = (s.subset + 1) % s.n_sub;
         s.steps_left -= 1;
@@ -139,7 +142,7 @@ __global__ void k_fill(float* __restrict__ dst, int64_t n, float value) {
 int64_t osem_chunks(int64_t n_events, int32_t n_sub) { return slot_chunks(n_events, n_sub); }
 
 template <bool Lut>
-static hipError_t launch_accumulate(const pp_osem_slot_t* slots, int n_slots, const GeomK& g, const TofK& t, int cus,
+static hipError_t launch_accumulate(const pp_frame_desc_t* slots, int n_slots, const GeomK& g, const TofK& t, int cus,
                                    hipStream_t s) {
     const int nw = (g.n[2] <= kSheetMaxW) ? g.n[2] : 0;
     const size_t lds = SheetLayout::bytes(nw, g);
@@ -156,18 +159,18 @@ static hipError_t launch_accumulate(const pp_osem_slot_t* slots, int n_slots, co
     return hipGetLastError();
 }
 
-hipError_t launch_osem_accumulate(const pp_osem_slot_t* slots, int n_slots, const GeomK& g, const TofK& t, int cus,
+hipError_t launch_osem_accumulate(const pp_frame_desc_t* slots, int n_slots, const GeomK& g, const TofK& t, int cus,
                                   hipStream_t s) {
     return t.lut ? launch_accumulate<true>(slots, n_slots, g, t, cus, s)
                  : launch_accumulate<false>(slots, n_slots, g, t, cus, s);
 }
 
-hipError_t launch_osem_update(pp_osem_slot_t* slots, int n_slots, int64_t n_vox, int n_blocks, hipStream_t s) {
+hipError_t launch_osem_update(pp_frame_desc_t* slots, int n_slots, int64_t n_vox, int n_blocks, hipStream_t s) {
     hipLaunchKernelGGL(k_osem_update, dim3(n_blocks), dim3(kOsemBlock), 0, s, slots, n_slots, n_vox);
     return hipGetLastError();
 }
 
-hipError_t launch_osem_advance(pp_osem_slot_t* slots, int n_slots, hipStream_t s) {
+hipError_t launch_osem_advance(pp_frame_desc_t* slots, int n_slots, hipStream_t s) {
     hipLaunchKernelGGL(k_osem_advance, dim3(1), dim3(256), 0, s, slots, n_slots);
     return hipGetLastError();
 }

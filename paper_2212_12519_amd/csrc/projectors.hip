@@ -137,60 +137,6 @@ __global__ void k_fwd_tof_sino(RaySrc src, int64_t n, GeomK g,
     }
 }
 
-template <bool PerRay>
-__global__ void k_back_tof_sino(RaySrc src, int64_t n, GeomK g,
-                                TofK t, float* __restrict__ img, const float* __restrict__ p) {
-    extern __shared__ float lds[];  // [nb][blockDim]: the block's projection tile, transposed
-    const int nt = blockDim.x;
-    const int64_t l0 = (int64_t)blockIdx.x * nt;
-    const int64_t l = l0 + threadIdx.x;
-    const int64_t nrays = (n - l0 < nt) ? (n - l0) : nt;
-    const int64_t total = nrays * t.nb;
-    const float* in = p + l0 * t.nb;
-    for (int64_t i = threadIdx.x; i < total; i += nt) {
-        const int ray = (int)(i / t.nb), b = (int)(i - (int64_t)ray * t.nb);
-        lds[b * nt + ray] = in[i];
-    }
-    __syncthreads();
-    RayK r;
-    TofRay q;
-    bool ok = l < n && tof_ray<PerRay>(t, l, q) && ray_setup(src, l, g, r);
-    if (PerRay && ok) r.s0 -= q.shift;
-    const float* mine = lds + threadIdx.x;
-    if (ok) {
-        bool any = false;
-        for (int b = 0; b < t.nb; ++b) any |= (mine[b * nt] != 0.0f);
-        ok = any;
-    }
-    // wave-synchronous plane loop with run-combined atomics (see k_back_tof_lm)
-    const int lo = ok ? r.k_lo : (1 << 30), hi = ok ? r.k_hi : -(1 << 30);
-    const int k0 = wave_min(lo), k1 = wave_max(hi);
-    for (int k = k0; k <= k1; ++k) {
-        const bool act = k >= lo && k <= hi;
-        Stencil st{};
-        float c = 0.0f;
-        if (act) {
-            const double s = fma((double)k, r.ds, r.s0);
-            int b_lo, b_hi;
-            tof_bin_range(s, t, q.lo, q.hi, b_lo, b_hi);
-            if (t.lut) {
-                for (int b = b_lo; b <= b_hi; ++b) c += tof_lut(s - (t.c0 + b * t.bw), t) * mine[b * nt];
-            } else {
-                const float x_hi0 = (float)(s - (t.c0 + b_lo * t.bw) + 0.5 * t.bw), bwf = (float)t.bw;
-                float e_hi = tof_erf(x_hi0, q.inv, t);
-                for (int b = b_lo; b <= b_hi; ++b) {
-                    const float e_lo = tof_erf(x_hi0 - (float)(b - b_lo + 1) * bwf, q.inv, t);
-                    c += 0.5f * (e_hi - e_lo) * mine[b * nt];
-                    e_hi = e_lo;
-                }
-            }
-            c *= r.ell;
-            st = stencil_at(r, k);
-        }
-        wave_stencil_scatter(img, act && c != 0.0f, r, st, c);
-    }
-}
-
 // ------------------------------------------------------- work counter ----
 //
 // Plane samples per ray whose 2x2 stencil has at least one voxel inside the
@@ -296,20 +242,30 @@ hipError_t launch_fwd_tof_sino(const RaySrc& src, int64_t n, const GeomK& g, con
 
 hipError_t launch_back_tof_sino(const RaySrc& src, int64_t n, const GeomK& g, const TofK& t,
                                 float* img, const float* p, hipStream_t s) {
-    // the run/sheet kernel carries ray indices in 32 bits
-    const bool per = t.sig_ray || t.off_ray;
-    if (n < (int64_t(1) << 31)) {
-        if (per) {
-            if (t.lut) return launch_runs(ModeTofSino<true, true>{p, t}, src, n, g, img, nullptr, s);
-            return launch_runs(ModeTofSino<false, true>{p, t}, src, n, g, img, nullptr, s);
-        }
-        if (t.lut) return launch_runs(ModeTofSino<true>{p, t}, src, n, g, img, nullptr, s);
-        return launch_runs(ModeTofSino<false>{p, t}, src, n, g, img, nullptr, s);
+    // the run/sheet kernel carries ray indices in 32 bits: the C ABI takes n < 2^31
+    if (t.sig_ray || t.off_ray) {
+        if (t.lut) return launch_runs(ModeTofSino<true, true>{p, t}, src, n, g, img, nullptr, s);
+        return launch_runs(ModeTofSino<false, true>{p, t}, src, n, g, img, nullptr, s);
     }
-    const int blk = sino_block(t.nb);
-    const size_t lds = (size_t)t.nb * blk * sizeof(float);
-    hipLaunchKernelGGL(per ? k_back_tof_sino<true> : k_back_tof_sino<false>, dim3(grid_for(n, blk)), dim3(blk), lds, s,
-                       src, n, g, t, img, p);
+    if (t.lut) return launch_runs(ModeTofSino<true>{p, t}, src, n, g, img, nullptr, s);
+    return launch_runs(ModeTofSino<false>{p, t}, src, n, g, img, nullptr, s);
+}
+
+// The Gaussian bin weight w(x) = (erf(clip(x + bw/2) / (sqrt2 sigma)) - erf(clip(x - bw/2) /
+// (sqrt2 sigma))) / 2, clip at +-trunc, at x_i = x0 + i dx, in float64 (the device library's erf).
+__global__ void __launch_bounds__(kBlock) k_tof_gauss_table(float* __restrict__ lut, int n, double x0, double dx,
+                                                           double hbw, double trunc, double inv_s2) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double x = fma((double)i, dx, x0);
+    const double a = fmin(fmax(x + hbw, -trunc), trunc), b = fmin(fmax(x - hbw, -trunc), trunc);
+    lut[i] = (float)(0.5 * (erf(a * inv_s2) - erf(b * inv_s2)));
+}
+
+hipError_t launch_tof_gauss_table(float* lut, int n, double x0, double dx, double bw, double sigma, double n_sigmas,
+                                  hipStream_t s) {
+    hipLaunchKernelGGL(k_tof_gauss_table, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, lut, n, x0, dx, 0.5 * bw,
+                       n_sigmas * sigma, 1.0 / (sqrt(2.0) * sigma));
     return hipGetLastError();
 }
 

@@ -179,8 +179,12 @@ __device__ __forceinline__ void sheet_flush(float* __restrict__ img, float* col,
     constexpr int B = kSheetBlock;
     const int tid = threadIdx.x, lane = (int)__lane_id(), wave = tid >> 6;
     const unsigned long long bal = __ballot(touched);
-    // per wave: touched count (bits 0-7), lowest z (bits 8-15), highest z (bits 16-23); nw <= 128
-    const int wlo = wave_min(touched ? max(zlo, 0) : 255), whi = wave_max(touched ? min(zhi, nw - 1) : 0);
+    // per wave: touched count (bits 0-7), lowest z (bits 8-15), highest z (bits 16-23); nw <= 128.
+    // Both ends are clamped to [0, nw - 1] per lane: a thread whose writes all went to out-of-grid
+    // entries (a pair below z = 0 at the conservative end plane of a window, or above nw - 1) has
+    // zhi < 0 or zlo >= nw, and an unclamped negative value would sign-extend into the packed word.
+    const int wlo = wave_min(touched ? min(max(zlo, 0), nw - 1) : 255);
+    const int whi = wave_max(touched ? max(min(zhi, nw - 1), 0) : 0);
     if (lane == 0) tcount[wave] = __popcll(bal) | (wlo << 8) | (whi << 16);
     __syncthreads();
     int off = 0, nt = 0, z0 = 255, z1 = 0;

@@ -2,7 +2,7 @@
 
 The paper runs listmode OSEM with all operations on the GPU (Sec. 2.6); here
 one subset update of any number of frames sharing an image grid is two
-kernel launches (pp_lm_osem_accumulate, pp_lm_osem_update) driven by a slot
+kernel launches (pp_lm_osem_subset_batched, pp_osem_update_batched) driven by a slot
 table in device memory, so a sequence of steps can be captured once into a
 HIP graph and replayed for any mix of frames.
 
@@ -57,7 +57,7 @@ def sensitivity(lor_start, lor_end, geom, chunk=1 << 26, res_fwhm=None):
 
 
 class SlotTable:
-    """Host mirror + device copy of a pp_osem_slot_t array for one image grid."""
+    """Host mirror + device copy of a pp_frame_desc_t array for one image grid."""
 
     def __init__(self, capacity, device):
         self.capacity = int(capacity)
@@ -71,6 +71,11 @@ class SlotTable:
         before the first step) and its scratch image."""
         if (x_fwd is None) != (tmp is None):
             raise ValueError("x_fwd and tmp go together")
+        if not 0 <= int(i) < self.capacity:
+            raise IndexError(f"slot {i} outside the table of {self.capacity}")
+        n_ev = xs.shape[0] if n_events is None else int(n_events)
+        if int(n_sub) < 1 or n_ev < 0 or int(steps) < 0:
+            raise ValueError("a slot needs n_sub >= 1, n_events >= 0 and steps >= 0")
         self.clear(i)
         s = self.host[i]
         s.xstart = None if xs is None else xs.data_ptr()
@@ -79,7 +84,7 @@ class SlotTable:
         s.x, s.acc, s.sens = x.data_ptr(), acc.data_ptr(), sens.data_ptr()
         s.x_fwd = None if x_fwd is None else x_fwd.data_ptr()
         s.tmp = None if tmp is None else tmp.data_ptr()
-        s.n_events = xs.shape[0] if n_events is None else int(n_events)
+        s.n_events = n_ev
         s.bg = float(bg)
         s.n_sub = int(n_sub)
         s.subset = 0
@@ -134,8 +139,8 @@ def osem_steps(table: SlotTable, geom, tof, n_steps=1, res_fwhm=None):
     fw = None if res_fwhm is None else fwhm3(res_fwhm)
     st = stream_of(table.dev)
     for _ in range(n_steps):
-        check(lib.pp_lm_osem_accumulate(ptr(table.dev), table.capacity, gc, tc, st))
-        check(lib.pp_lm_osem_update(ptr(table.dev), table.capacity, gc, fw, st))
+        check(lib.pp_lm_osem_subset_batched(ptr(table.dev), table.capacity, gc, tc, st))
+        check(lib.pp_osem_update_batched(ptr(table.dev), table.capacity, gc, fw, st))
 
 
 def capture_steps(table: SlotTable, geom, tof, n_steps=1, res_fwhm=None):

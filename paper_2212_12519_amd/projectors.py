@@ -7,7 +7,6 @@ allocate the output with torch and call the ``pp_*`` function.
 from __future__ import annotations
 
 import ctypes
-import math
 
 import torch
 
@@ -155,23 +154,32 @@ def pp_fill(dst, value):
     return dst
 
 
+def pp_tof_gaussian_table(tof, dx_max, lut=None):
+    """(n, x0, dx) of the table of the Gaussian bin weight of `tof` at spacing <= dx_max mm;
+    with `lut` (float32 CUDA tensor of >= n entries) the library also fills it."""
+    t = as_tof(tof)
+    base = TofParams(t.bin_width, t.sigma, t.n_sigmas, t.n_bins, t.center_offset)
+    n, x0, step = ctypes.c_int32(), ctypes.c_float(), ctypes.c_float()
+    if lut is not None:
+        _dev(lut)
+        if lut.dtype != torch.float32:
+            raise ValueError("lut must be float32")
+    check(load().pp_tof_gaussian_table(base.c(), float(dx_max), ptr(lut), 0 if lut is None else lut.numel(),
+                                       ctypes.byref(n), ctypes.byref(x0), ctypes.byref(step),
+                                       None if lut is None else stream_of(lut)))
+    return n.value, x0.value, step.value
+
+
 def gaussian_tof_table(tof, dx, device="cuda"):
     """TofParams whose kernel is the table of its own Gaussian bin weight
     w(x) = G(x + bw/2) - G(x - bw/2) over its support [-win, win], win = n_sigmas sigma + bw/2,
-    at the largest spacing <= `dx` mm that puts the last entry exactly on +win (evaluated in
-    float64 on the host)."""
+    at the largest spacing <= `dx` mm that puts the last entry on +win (pp_tof_gaussian_table:
+    evaluated by the library on the device)."""
     t = as_tof(tof)
-    win = t.n_sigmas * t.sigma + 0.5 * t.bin_width
-    n = int(math.ceil(2.0 * win / dx)) + 1
-    dx = 2.0 * win / (n - 1)
-    x = -win + dx * torch.arange(n, dtype=torch.float64)
-    tr = t.n_sigmas * t.sigma
-
-    def G(u):
-        return 0.5 * torch.special.erf(torch.clamp(u, -tr, tr) / (math.sqrt(2.0) * t.sigma))
-
-    w = (G(x + 0.5 * t.bin_width) - G(x - 0.5 * t.bin_width)).to(torch.float32).to(device)
-    return TofParams(t.bin_width, t.sigma, t.n_sigmas, t.n_bins, t.center_offset, w, -win, dx)
+    n, _, _ = pp_tof_gaussian_table(t, dx)
+    w = torch.empty(n, dtype=torch.float32, device=device)
+    _, x0, step = pp_tof_gaussian_table(t, dx, w)
+    return TofParams(t.bin_width, t.sigma, t.n_sigmas, t.n_bins, t.center_offset, w, x0, step)
 
 
 def fwhm3(fwhm):

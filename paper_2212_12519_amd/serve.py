@@ -5,9 +5,10 @@ short frames (Sec. 1), and OSEM should keep every operation on the GPU
 (Sec. 2.6, Sec. 4).  Requests (a frame's events, an image grid, iterations x
 subsets) arrive over time.  The server
 
-* admits queued requests FIFO whenever a slot of their grid's table is free
-  and the frame fits the HBM budget (events in subset-major presorted order,
-  image, accumulator);
+* admits queued requests whenever a slot of their grid's table is free and
+  the frame fits the HBM budget (events in subset-major presorted order,
+  image, accumulator), first-come first-served within each grid: a request
+  waiting for its grid's slots does not hold up requests of another grid;
 * advances every admitted frame by one OSEM subset update per step, all
   frames of a grid in one fused launch pair -- frames at different
   iterations / subsets coexist, new frames join between steps, finished
@@ -134,6 +135,17 @@ class OsemServer:
         self.in_use += nbytes
         return True
 
+    def _admit_queue(self, queue, now):
+        """Admits what fits, in arrival order within each grid; returns the requests left waiting.
+        Once a request of a grid has to wait, later requests of that grid wait behind it."""
+        waiting, blocked = deque(), set()
+        for req in queue:
+            g = as_geom(req.grid)
+            if g in blocked or not self._admit(req, now):
+                blocked.add(g)
+                waiting.append(req)
+        return waiting
+
     def _step(self, st):
         if st.dirty:
             st.table.upload()
@@ -157,8 +169,7 @@ class OsemServer:
             now = clock() - t0
             while pending and pending[0].arrival <= now:
                 queue.append(pending.popleft())
-            while queue and self._admit(queue[0], now):
-                queue.popleft()
+            queue = self._admit_queue(queue, now)
             live = [st for st in self.grids.values() if st.live]
             if not live:
                 if pending:

@@ -2,6 +2,7 @@
 include/ppmi.h declares, and rejects bad arguments with the documented codes before
 touching the GPU."""
 import ctypes
+import math
 import os
 import re
 
@@ -29,7 +30,12 @@ def test_exports_every_declared_symbol(lib):
     assert len(names) >= 12, names
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.pp_abi_version() == 5
+    assert lib.pp_abi_version() == 6
+    # the entry points the boundary is specified with: the six projectors, the batched OSEM pair
+    for n in ("pp_fwd", "pp_back", "pp_fwd_tof_sino", "pp_back_tof_sino", "pp_fwd_tof_lm", "pp_back_tof_lm",
+              "pp_lm_osem_subset_batched", "pp_osem_update_batched", "pp_strerror", "pp_abi_version",
+              "pp_tof_gaussian_table"):
+        assert n in names, n
 
 
 def _geom(dim=(4, 4, 4), vs=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0)):
@@ -84,7 +90,7 @@ def test_error_codes(lib):
     for field in ("sigma_per_ray", "offset_per_ray"):
         t = _tof()
         setattr(t, field, DUMMY2.value)
-        assert lib.pp_lm_osem_accumulate(DUMMY, 3, g, t, None) == PP_EINVAL_TOF
+        assert lib.pp_lm_osem_subset_batched(DUMMY, 3, g, t, None) == PP_EINVAL_TOF
         assert lib.pp_fwd_tof_lm(DUMMY, DUMMY, DUMMY, 0, g, t, DUMMY, DUMMY, None, None) == PP_OK
     assert lib.pp_fwd_tof_lm(DUMMY, DUMMY, None, 5, g, _tof(), DUMMY, DUMMY, None, None) == PP_EINVAL_PTR
     # crystal-index events: table size, pointers, 8-byte alignment of the pairs
@@ -103,15 +109,15 @@ def test_error_codes(lib):
     assert lib.pp_gather_crystal_events(DUMMY, None, DUMMY2, 10, ctypes.c_void_p(36), None, None) == PP_EINVAL_PTR
     assert lib.pp_gather_crystal_events(DUMMY, DUMMY, DUMMY2, 10, DUMMY3, None, None) == PP_EINVAL_PTR
     assert lib.pp_fwd_tof_lm(DUMMY, DUMMY, DUMMY, 5, g, None, DUMMY, DUMMY, None, None) == PP_EINVAL_PTR
-    assert lib.pp_lm_osem_accumulate(DUMMY, -1, g, _tof(), None) == PP_EINVAL_N
-    assert lib.pp_lm_osem_accumulate(DUMMY, 0, g, _tof(), None) == PP_OK
-    assert lib.pp_lm_osem_update(DUMMY, -1, g, None, None) == PP_EINVAL_N
-    assert lib.pp_lm_osem_update(None, 3, g, None, None) == PP_EINVAL_PTR
-    assert lib.pp_lm_osem_update(DUMMY, 3, None, None, None) == PP_EINVAL_PTR
-    assert lib.pp_lm_osem_update(DUMMY, 3, _geom(dim=(0, 4, 4)), None, None) == PP_EINVAL_GEOM
+    assert lib.pp_lm_osem_subset_batched(DUMMY, -1, g, _tof(), None) == PP_EINVAL_N
+    assert lib.pp_lm_osem_subset_batched(DUMMY, 0, g, _tof(), None) == PP_OK
+    assert lib.pp_osem_update_batched(DUMMY, -1, g, None, None) == PP_EINVAL_N
+    assert lib.pp_osem_update_batched(None, 3, g, None, None) == PP_EINVAL_PTR
+    assert lib.pp_osem_update_batched(DUMMY, 3, None, None, None) == PP_EINVAL_PTR
+    assert lib.pp_osem_update_batched(DUMMY, 3, _geom(dim=(0, 4, 4)), None, None) == PP_EINVAL_GEOM
     f3 = ctypes.c_float * 3
     for bad in (f3(-1.0, 4.5, 4.5), f3(float("nan"), 4.5, 4.5), f3(4.5, float("inf"), 4.5), f3(4.5, 4.5, 1e4)):
-        assert lib.pp_lm_osem_update(DUMMY, 3, g, bad, None) == PP_EINVAL_RES
+        assert lib.pp_osem_update_batched(DUMMY, 3, g, bad, None) == PP_EINVAL_RES
         assert lib.pp_gauss3d(DUMMY, DUMMY2, DUMMY3, g, bad, None) == PP_EINVAL_RES
     # resolution model: pointers, aliasing, widths at the radius limit (31 voxels)
     ok = f3(4.5, 4.5, 4.5)
@@ -121,8 +127,8 @@ def test_error_codes(lib):
     assert lib.pp_gauss3d(DUMMY, DUMMY2, ctypes.c_void_p((1 << 20) + 4), g, ok, None) == PP_EINVAL_PTR  # tmp overlaps dst
     sig_max = 31.49 / 4.0  # radius floor(4 s + 1/2) = 31 voxels at 1 mm
     assert lib.pp_gauss3d(DUMMY, DUMMY2, DUMMY3, _geom(dim=(0, 4, 4)), ok, None) == PP_EINVAL_GEOM
-    assert lib.pp_lm_osem_update(DUMMY, 0, g, f3(*(3 * [sig_max * 2.3548])), None) == PP_OK
-    assert lib.pp_lm_osem_update(DUMMY, 0, g, f3(*(3 * [32.0 / 4.0 * 2.3549])), None) == PP_EINVAL_RES
+    assert lib.pp_osem_update_batched(DUMMY, 0, g, f3(*(3 * [sig_max * 2.3548])), None) == PP_OK
+    assert lib.pp_osem_update_batched(DUMMY, 0, g, f3(*(3 * [32.0 / 4.0 * 2.3549])), None) == PP_EINVAL_RES
     assert lib.pp_fill(None, 10, ctypes.c_float(0.0), None) == PP_EINVAL_PTR
     assert lib.pp_fill(None, -1, ctypes.c_float(0.0), None) == PP_EINVAL_N
     ws = lib.pp_lm_presort_workspace_bytes(1000)
@@ -137,6 +143,31 @@ def test_error_codes(lib):
     assert lib.pp_osem_init(None, None, 10, None) == PP_EINVAL_PTR
     for c in range(6):
         assert lib.pp_strerror(c)
+    # TOF sinogram calls take fewer than 2^31 rays (larger sets go in chunks)
+    big = 1 << 31
+    assert lib.pp_fwd_tof_sino(DUMMY, DUMMY, big, g, _tof(), DUMMY2, DUMMY3, None) == PP_EINVAL_N
+    assert lib.pp_back_tof_sino(DUMMY, DUMMY, big, g, _tof(), DUMMY2, DUMMY3, None) == PP_EINVAL_N
+    assert lib.pp_back_tof_sino(DUMMY, DUMMY, big - 1, g, _tof(nb=0), DUMMY2, DUMMY3, None) == PP_EINVAL_TOF
+
+
+def test_tof_gaussian_table_host(lib):
+    """pp_tof_gaussian_table: size query (no device memory touched) and its error codes."""
+    from paper_2212_12519_amd._lib import PP_EINVAL_N, PP_EINVAL_PTR, PP_EINVAL_TOF, PP_OK
+
+    n, x0, dx = ctypes.c_int32(), ctypes.c_float(), ctypes.c_float()
+    t = _tof(bw=28.0, sig=58.5 / 2.355, ns=3.0, nb=29)
+    assert lib.pp_tof_gaussian_table(t, 0.05, None, 0, ctypes.byref(n), ctypes.byref(x0), ctypes.byref(dx),
+                                     None) == PP_OK
+    win = 3.0 * float(ctypes.c_float(58.5 / 2.355).value) + 14.0
+    assert n.value == math.ceil(2 * win / float(ctypes.c_float(0.05).value)) + 1
+    assert x0.value == pytest.approx(-win, rel=1e-7) and dx.value <= 0.05
+    assert x0.value + (n.value - 1) * dx.value == pytest.approx(win, rel=1e-6)
+    assert lib.pp_tof_gaussian_table(None, 0.05, None, 0, None, None, None, None) == PP_EINVAL_PTR
+    for bad in (_tof(sig=0.0), _tof(ns=-1.0), _tof(bw=float("nan"))):
+        assert lib.pp_tof_gaussian_table(bad, 0.05, None, 0, None, None, None, None) == PP_EINVAL_TOF
+    for dxm in (0.0, -1.0, float("inf"), 1e-6):  # 1e-6 mm: more than 2^24 entries
+        assert lib.pp_tof_gaussian_table(t, dxm, None, 0, None, None, None, None) == PP_EINVAL_N
+    assert lib.pp_tof_gaussian_table(t, 0.05, DUMMY, n.value - 1, None, None, None, None) == PP_EINVAL_N
 
 
 def test_osem_chunks(lib):

@@ -697,3 +697,66 @@ def test_per_ray_sigma_bin_sum_and_adjoint():
                 offset_per_ray=np.full(n, 1.5, np.float32))
     assert np.array_equal(oracle.fwd_tof_sino(xs, xe, origin, vs, dim, same, x),
                           oracle.fwd_tof_sino(xs, xe, origin, vs, dim, tofd(4.0, 3.0, 3.0, 41, 1.5), x))
+
+
+def test_lut_work_counter():
+    """The work counter with a tabulated kernel: a sample counts iff its stencil touches the grid
+    and its signed distance x from the event's bin centre lies strictly inside the table's range
+    (x0, x0 + (n - 1) dx) -- also with a per-ray centre offset (written out per plane here, the
+    bin centre from the ray's own offset).  The table values play no part (a zero entry still
+    counts).  Catches a closed range, a table origin taken from the wrong side of the bin centre,
+    or an offset ignored in the count."""
+    dim, vs, origin = GRIDS[0]
+    rng = np.random.default_rng(19)
+    n = 60
+    xs, xe = random_rays(rng, n, origin, vs, dim, inside_frac=0.2)
+    x0, dx, n_lut = -3.7, 0.45, 15  # asymmetric: (x0, x0 + 14 dx) = (-3.7, 2.6)
+    lut = np.zeros(n_lut, dtype=np.float32)
+    lut[3:9] = 1.0
+    bins = rng.integers(-1, 8, size=n).astype(np.int16)  # -1 and 7: outside the 7 bins
+    for with_offset in (False, True):
+        off = rng.normal(0.0, 1.5, size=n).astype(np.float32) if with_offset else None
+        tof = dict(tofd(bin_width=2.0, sigma=1.0, n_sigmas=2.5, n_bins=7), lut=lut, lut_x0=x0, lut_dx=dx)
+        if with_offset:
+            tof["offset_per_ray"] = off
+        tot, per = oracle.count_samples(xs, xe, origin, vs, dim, tof=tof, bins=bins, per_ray=True)
+        lo, hi = x0, x0 + (n_lut - 1) * dx
+        for l in range(n):
+            d32 = (xe[l] - xs[l]).astype(np.float32)
+            p = int(np.argmax(np.abs(d32)))
+            inplane = [a for a in range(3) if a != p]
+            a64, b64 = xs[l].astype(float), xe[l].astype(float)
+            length = float(np.linalg.norm(b64 - a64))
+            b = int(bins[l])
+            cnt = 0
+            if 0 <= b < 7:
+                cb = (b - 3) * 2.0 + (float(off[l]) if with_offset else 0.0)
+                for k in range(dim[p]):
+                    t = (origin[p] + k * vs[p] - a64[p]) / (b64[p] - a64[p])
+                    if t < 0 or t > 1:
+                        continue
+                    X = a64 + t * (b64 - a64)
+                    idx = [(X[a] - origin[a]) / vs[a] for a in inplane]
+                    touch = all(math.floor(i) + 1 >= 0 and math.floor(i) <= dim[a] - 1 for i, a in zip(idx, inplane))
+                    x = (t - 0.5) * length - cb
+                    cnt += touch and lo < x < hi
+            assert per[l] == cnt, (with_offset, l)
+        assert tot == per.sum() > 0
+
+
+def test_tof_kernel_values_textbook():
+    """The oracle's TOF bin weight w(x) (bin centre at x = 0) equals the truncated-normal mass
+    over the bin: Phi(min(x + bw/2, T)/sigma) - Phi(max(x - bw/2, -T)/sigma), T = n_sigmas sigma,
+    and 0 once the bin lies beyond the truncation (scipy's normal CDF, not erf).  Catches a
+    truncation applied after the convolution, a missing 1/2 or sqrt(2)."""
+    bw, sig, ns = 28.0, 58.5 / 2.355, 3.0
+    t = tofd(bw, sig, ns, 1)
+    x = np.linspace(-120.0, 120.0, 2401)
+    w = oracle.tof_kernel(x, t)
+    s, T = float(t["sigma"]), float(t["n_sigmas"]) * float(t["sigma"])
+    hb = 0.5 * float(t["bin_width"])
+    a = np.clip(x - hb, -T, T)
+    b = np.clip(x + hb, -T, T)
+    ref = stats.norm.cdf(b / s) - stats.norm.cdf(a / s)
+    np.testing.assert_allclose(w, ref, rtol=0, atol=2e-15)
+    assert np.all(w[np.abs(x) >= T + hb] == 0.0) and w.max() > 0.4

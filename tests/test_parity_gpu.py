@@ -438,3 +438,107 @@ def test_run_sheet_paths_on_grid_shapes(gpu, gi):
     p = gpu.fwd_tof_lm(xs_d, xe_d, b_d, G, T, torch.ones(dim, device=d), order=order)
     p_ref = oracle.fwd_tof_lm(xs, xe, origin, vs, dim, tof, bins, np.ones(dim))
     assert rel_l2(np64(p), p_ref) <= FWD_TOL
+
+
+def _cus():
+    return torch.cuda.get_device_properties(0).multi_processor_count
+
+
+def _timed_back_vs_oracle(gpu, xs, xe, bins, seed):
+    """The benchmark's back-projection call -- pp_lm_presort, then pp_back_tof_lm in that order --
+    on the given events, element by element against the oracle."""
+    g = geom_of(C.GRID_CLIN)
+    G = gpu.ImageGeom(g["dim"], g["voxsize"], g["origin"])
+    tof = tof_of(C.TOF_CLIN)
+    T = gpu.TofParams(tof["bin_width"], tof["sigma"], tof["n_sigmas"], tof["n_bins"])
+    n = xs.shape[0]
+    y = np.random.default_rng(seed).uniform(0.2, 1.0, size=n).astype(np.float32)
+    order = gpu.presort(xs, xe, G, bins, T)
+    img = torch.zeros(G.dim, dtype=torch.float32, device=xs.device)
+    gpu.pp_back_tof_lm(xs, xe, bins, G, T, img, torch.from_numpy(y).to(xs.device), order)
+    ref = oracle.back_tof_lm(xs.cpu().numpy(), xe.cpu().numpy(), g["origin"], g["voxsize"], g["dim"], tof,
+                             bins.cpu().numpy(), y)
+    assert rel_l2(np64(img), ref) <= BACK_TOL
+    return ref
+
+
+def test_timed_back_call_prefix(gpu, lm40):
+    """The first 2^21 events of the 40M workload, presorted and back projected as the benchmark
+    does: at this size the launch gives each workgroup 8 groups of 256 rays, so sheets persist
+    across groups."""
+    xs, xe, bins, _ = lm40
+    m = 1 << 21
+    assert m > 7 * 1024 * _cus()  # 8 groups per workgroup
+    ref = _timed_back_vs_oracle(gpu, xs[:m].contiguous(), xe[:m].contiguous(), bins[:m].contiguous(), 47)
+    assert ref.max() > 0
+
+
+def test_timed_back_call_dense_lines(gpu, lm40):
+    """The events of the 40M workload whose transaxial direction lies in [0, pi/18): presorted,
+    their lines are as densely populated as in the full 40M list (runs of the length the timed
+    40M call sees), so the sheet loop and flush work as in the benchmark; element by element
+    against the oracle."""
+    xs, xe, bins, _ = lm40
+    d = xe[:, :2] - xs[:, :2]
+    phi = torch.remainder(torch.atan2(d[:, 1], d[:, 0]), np.pi)
+    sel = torch.nonzero(phi < np.pi / 18).squeeze(1)
+    assert sel.numel() > 7 * 1024 * _cus()
+    _timed_back_vs_oracle(gpu, xs[sel].contiguous(), xe[sel].contiguous(), bins[sel].contiguous(), 48)
+
+
+def test_sheet_flush_writes_below_grid(gpu):
+    """Runs of rays on one transaxial line whose axial coordinate leaves the grid through z = 0
+    just after plane 63: in the wave of planes 64-127 the only sample is the conservative end
+    plane, whose z pair lies entirely below the grid (its value goes to the sheet's spare row).
+    The flush must not carry that row into the image.  Non-TOF and TOF listmode, against the
+    oracle."""
+    dim, vs = (100, 8, 8), (1.0, 1.0, 1.0)
+    G = gpu.ImageGeom(dim, vs)
+    o = G.origin
+    xs_l, xe_l = [], []
+    for line, y0 in enumerate((-1.7, 0.3, 2.2)):
+        for r in range(6):
+            # axial index 3.0 at plane 0 falling to -1 at plane 63.5 (+ a small shift per ray)
+            w0 = 3.0 + 0.004 * r
+            slope = -4.0 / 63.5
+            x_a, x_b = o[0] - 10.5, o[0] + 110.5
+            z_a = o[2] + (w0 + slope * (x_a - o[0])) * vs[2]
+            z_b = o[2] + (w0 + slope * (x_b - o[0])) * vs[2]
+            xs_l.append((x_a, y0, z_a))
+            xe_l.append((x_b, y0, z_b))
+    xs = np.array(xs_l, dtype=np.float32)
+    xe = np.array(xe_l, dtype=np.float32)
+    n = xs.shape[0]
+    rng = np.random.default_rng(49)
+    y = rng.uniform(0.5, 1.5, size=n).astype(np.float32)
+    tof = tofd(30.0, 20.0, 3.0, 5)
+    bins = np.full(n, 2, dtype=np.int16)
+    dv = torch.device("cuda")
+    xs_d, xe_d = torch.from_numpy(xs).to(dv), torch.from_numpy(xe).to(dv)
+    T = gpu.TofParams(tof["bin_width"], tof["sigma"], tof["n_sigmas"], tof["n_bins"])
+    b = gpu.back(xs_d, xe_d, G, torch.from_numpy(y).to(dv))
+    bl = gpu.back_tof_lm(xs_d, xe_d, torch.from_numpy(bins).to(dv), G, T, torch.from_numpy(y).to(dv))
+    torch.cuda.synchronize()
+    ref = oracle.back(xs, xe, o, vs, dim, y)
+    ref_l = oracle.back_tof_lm(xs, xe, o, vs, dim, tof, bins, y)
+    assert ref.sum() > 0 and ref_l.sum() > 0
+    assert rel_l2(np64(b), ref) <= BACK_TOL
+    assert rel_l2(np64(bl), ref_l) <= BACK_TOL
+    # plane 64 (the end plane, stencil entirely below the grid) and beyond receive nothing
+    assert float(b[64:].abs().sum()) == 0.0 and float(bl[64:].abs().sum()) == 0.0
+    assert float(b[63].abs().sum()) > 0.0
+
+
+def test_tof_gaussian_table_matches_oracle(gpu):
+    """pp_tof_gaussian_table: the library's table of the Gaussian bin weight equals the oracle's
+    TOF kernel at the table's nodes (float32 rounding), for the clinical kernel and a narrow one."""
+    for spec in (C.TOF_CLIN, C.TofSpec(4.0, 1.3, 2.5, 9)):
+        tof = tof_of(spec)
+        T = gpu.TofParams(tof["bin_width"], tof["sigma"], tof["n_sigmas"], tof["n_bins"])
+        TL = gpu.gaussian_tof_table(T, 0.05)
+        n = TL.lut.numel()
+        x = TL.lut_x0 + TL.lut_dx * np.arange(n, dtype=np.float64)
+        ref = oracle.tof_kernel(x, tof)
+        got = TL.lut.cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(got - ref)) <= 2.0 ** -24 * max(ref.max(), 1e-30) + 1e-12
+        assert TL.lut_x0 + (n - 1) * TL.lut_dx == pytest.approx(-TL.lut_x0, rel=1e-6) and TL.lut_dx <= 0.05

@@ -46,6 +46,9 @@ def test_results_equal_alone(gpu, setup, use_graph):
     server = serve.OsemServer(T, sens, max_slots=4, hbm_budget=8e9, use_graph=use_graph)
     res = server.run(trace)
     assert sorted(r.rid for r in res) == list(range(10))
+    # continuous batching: some frames were on the GPU together
+    iv = sorted((r.admitted, r.finished) for r in res)
+    assert any(b[0] < a[1] for a, b in zip(iv, iv[1:])), iv
     by_id = {r.rid: r for r in res}
     for req in trace:
         r = by_id[req.rid]
@@ -81,3 +84,51 @@ def test_sequential_baseline_same_images(gpu, setup):
     for req in trace:
         ref = _alone(req, sens, T)
         assert rel_l2(seq[req.rid].cpu().numpy(), ref.cpu().numpy()) <= 1e-4
+
+
+@pytest.fixture(scope="module")
+def setup_oracle(gpu):
+    """Serving inputs whose sensitivity images come from the oracle (non-TOF back projection of
+    ones over 5 of the 380 views, then the 4.5 mm resolution model), so that served images can be
+    compared with oracle reconstructions."""
+    import oracle
+
+    dev = torch.device("cuda")
+    t = C.TOF_CLIN
+    T = gpu.TofParams(t.bin_width, t.sigma, t.n_sigmas, t.n_bins)
+    src = C.phantom_clin(device=dev)
+    pool = generate_tof_lm_events(C.SCANNER_CLIN, C.SINO_CLIN.n_rad, C.SINO_CLIN.max_rd, C.GRID_CLIN, src,
+                                  1_000_000, seed=75, tof_bin_width=t.bin_width, tof_sigma=t.sigma,
+                                  n_tof_bins=t.n_bins, device=dev)
+    lxs, lxe = C.SINO_CLIN.lors(views=torch.arange(0, 380, 76))
+    grids, sens32 = [], []
+    for g in C.SERVE_GRIDS:
+        s = oracle.back(lxs.numpy(), lxe.numpy(), g.origin, g.voxsize, g.dim, np.ones(lxs.shape[0]))
+        s = oracle.gauss3d(s, g.voxsize, 4.5).astype(np.float32)
+        grids.append(gpu.ImageGeom(g.dim, g.voxsize, g.origin))
+        sens32.append(s)
+    return pool, grids, sens32, T
+
+
+def test_served_images_match_oracle(gpu, setup_oracle):
+    """Frames served in the continuous-batching mix (both grids, the resolution model on, graph
+    replay) reconstruct what the oracle reconstructs for each frame alone: relative L2 <= 1e-4."""
+    import oracle
+    from paper_2212_12519_amd import serve
+
+    pool, grids, sens32, T = setup_oracle
+    dev = torch.device("cuda")
+    sens = [(g, torch.from_numpy(s).to(dev)) for g, s in zip(grids, sens32)]
+    trace = serve.make_trace(pool, grids, 5, seed=76, events_range=(60_000, 250_000), rate_hz=200.0)
+    server = serve.OsemServer(T, sens, max_slots=3, hbm_budget=8e9, use_graph=True, res_fwhm=4.5)
+    res = {r.rid: r for r in server.run(trace)}
+    assert sorted(res) == list(range(5))
+    tof = {"bin_width": T.bin_width, "sigma": T.sigma, "n_sigmas": T.n_sigmas, "n_bins": T.n_bins}
+    for req in trace:
+        gi = grids.index(req.grid)
+        g = req.grid
+        s_ref = sens32[gi].astype(np.float64)
+        x_ref = oracle.lm_osem(req.xstart.cpu().numpy(), req.xend.cpu().numpy(), req.tof_bin.cpu().numpy(),
+                               g.origin, g.voxsize, g.dim, tof, s_ref, req.bg, req.n_iter, req.n_sub,
+                               (s_ref > 0).astype(np.float64), fwhm=4.5)
+        assert rel_l2(res[req.rid].image.cpu().numpy(), x_ref) <= 1e-4, req.rid

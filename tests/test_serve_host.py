@@ -60,3 +60,37 @@ def test_slot_table_host_mirror():
     assert (tbl[0].subset, tbl[0].steps_left) == (5, 19)
     assert (tbl[1].subset, tbl[1].steps_left) == (1, 0)  # 3 -> 0 -> 1, then finished
     assert (tbl[2].subset, tbl[2].steps_left) == (0, 5)
+
+
+def test_admission_per_grid_fifo():
+    """A request waiting for a slot of its own grid does not hold up requests of another grid;
+    within a grid, requests are admitted in arrival order (no overtaking)."""
+    from collections import deque
+
+    from paper_2212_12519_amd import serve
+
+    class Req:
+        def __init__(self, rid, grid):
+            self.rid, self.grid = rid, grid
+
+    class Srv(serve.OsemServer):
+        def __init__(self, free):
+            self.free = dict(free)
+            self.admitted = []
+
+        def _admit(self, req, now):
+            if self.free[req.grid] == 0:
+                return False
+            self.free[req.grid] -= 1
+            self.admitted.append(req.rid)
+            return True
+
+    import paper_2212_12519_amd._lib as L
+
+    ga = L.ImageGeom((4, 4, 4), (1, 1, 1))
+    gb = L.ImageGeom((8, 8, 4), (1, 1, 1))
+    srv = Srv({ga: 1, gb: 2})
+    q = deque([Req(0, ga), Req(1, ga), Req(2, gb), Req(3, ga), Req(4, gb), Req(5, gb)])
+    left = srv._admit_queue(q, 0.0)
+    assert srv.admitted == [0, 2, 4]
+    assert [r.rid for r in left] == [1, 3, 5]
