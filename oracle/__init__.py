@@ -58,6 +58,7 @@ def _load():
     lib.orc_count_samples.restype = I64
     lib.orc_lm_osem.argtypes = [P, P, P, I64, P, P, P] + tof + [P, ctypes.c_double, I32, I32, P, P]
     lib.orc_gauss3d.argtypes = [P, P, P, P, P]
+    lib.orc_tof_sino_osem.argtypes = [P, P, I64, P, I32, P, P, P, F, F, F, F, I32, P, ctypes.c_double, I32, P]
     lib.orc_tof_kernel.argtypes = [P, I64, F, F, F, P, I32, ctypes.c_double, ctypes.c_double, P]
     lib.orc_max_threads.restype = ctypes.c_int
     _lib = lib
@@ -260,4 +261,23 @@ def lm_osem(xstart, xend, bins, origin, voxsize, dim, tof, sens, bg, n_iter, n_s
     lib.orc_lm_osem(_ptr(xs), _ptr(xe), _ptr(b), xs.shape[0], _ptr(o), _ptr(h), _ptr(d), *ta, _ptr(s),
                     ctypes.c_double(bg), ctypes.c_int32(n_iter), ctypes.c_int32(n_sub), _ptr(x),
                     None if f is None else _ptr(f))
+    return x
+
+
+def tof_sino_osem(xstart, xend, subset, n_sub, origin, voxsize, dim, tof, y, bg, n_iter, x0):
+    """TOF sinogram OSEM (Gaussian kernel): LOR l in subset ``subset[l]``; per subset
+    x <- x * A_j^T (y / (A_j x + bg)) / A_j^T 1 (0 where A_j^T 1 == 0).  y: [n, n_bins] counts.
+    Returns the float64 image after n_iter passes over the n_sub subsets."""
+    lib = _load()
+    xs, xe = _f32(xstart, 3), _f32(xend, 3)
+    n = xs.shape[0]
+    o, h, d = _geom(origin, voxsize, dim)
+    ta = _tofargs(tof)
+    if ta[5] is not None:
+        raise ValueError("tof_sino_osem: Gaussian kernel only")
+    sb = np.ascontiguousarray(np.asarray(subset, dtype=np.int32).reshape(n))
+    yy = np.ascontiguousarray(np.asarray(y, dtype=np.float64).reshape(n, ta[4].value))
+    x = np.array(np.asarray(x0, dtype=np.float64).reshape(tuple(d)), copy=True, order="C")
+    lib.orc_tof_sino_osem(_ptr(xs), _ptr(xe), n, _ptr(sb), int(n_sub), _ptr(o), _ptr(h), _ptr(d), *ta[:5], _ptr(yy),
+                          ctypes.c_double(bg), int(n_iter), _ptr(x))
     return x

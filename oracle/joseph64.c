@@ -579,3 +579,72 @@ void orc_lm_osem(const float* xs, const float* xe, const int16_t* bins, int64_t 
     free(acc);
     if (fwhm) free(xf);
 }
+
+
+/* TOF sinogram OSEM: the sinogram counterpart of the listmode OSEM above (the paper's Sec. 4
+ * discusses the memory such a reconstruction needs and chunk-wise processing for long axial
+ * fields of view).  LOR l belongs to subset sub[l] (LORs with sub[l] outside [0, n_sub) take no
+ * part); y holds the measured counts [n][n_bins], bg the additive expectation of every bin.
+ * For it in [0, n_iter), subset j in [0, n_sub):
+ *     sens_j = A_j^T 1                 (all LORs of subset j, all bins)
+ *     acc    = A_j^T (y / (A_j x + bg)), a (LOR, bin) whose expectation is not positive
+ *              contributing nothing
+ *     x_v   <- x_v acc_v / sens_j,v   if sens_j,v > 0, else 0.
+ * x holds the initial image on entry and the result on return. */
+void orc_tof_sino_osem(const float* xs, const float* xe, int64_t n, const int32_t* sub, int32_t n_sub,
+                       const float* origin, const float* vs, const int32_t* dim, float bin_width, float sigma,
+                       float n_sigmas, float center_offset, int32_t n_bins, const double* y, double bg,
+                       int32_t n_iter, double* x) {
+    grid64 g = mkgrid(origin, vs, dim);
+    tof64 tf = mktof(bin_width, sigma, n_sigmas, center_offset, n_bins, NULL, 0, 0.0, 1.0, NULL, NULL);
+    const int64_t nv = nvox(&g), nb = n_bins;
+    int64_t* cnt = (int64_t*)calloc((size_t)n_sub + 1, sizeof(int64_t));
+    if (!cnt) abort();
+    for (int64_t l = 0; l < n; ++l)
+        if (sub[l] >= 0 && sub[l] < n_sub) ++cnt[sub[l] + 1];
+    for (int j = 0; j < n_sub; ++j) cnt[j + 1] += cnt[j];
+    /* the LORs of each subset, copied out in their original order */
+    float* sxs = (float*)malloc((size_t)(3 * cnt[n_sub] + 3) * sizeof(float));
+    float* sxe = (float*)malloc((size_t)(3 * cnt[n_sub] + 3) * sizeof(float));
+    double* sy = (double*)malloc((size_t)(nb * cnt[n_sub] + 1) * sizeof(double));
+    double* q = (double*)malloc((size_t)(nb * cnt[n_sub] + 1) * sizeof(double));
+    double* sens = (double*)calloc((size_t)(nv * n_sub), sizeof(double));
+    double* acc = (double*)malloc((size_t)nv * sizeof(double));
+    int64_t* fill = (int64_t*)malloc((size_t)(n_sub + 1) * sizeof(int64_t));
+    if (!sxs || !sxe || !sy || !q || !sens || !acc || !fill) abort();
+    memcpy(fill, cnt, (size_t)(n_sub + 1) * sizeof(int64_t));
+    for (int64_t l = 0; l < n; ++l) {
+        if (sub[l] < 0 || sub[l] >= n_sub) continue;
+        int64_t d = fill[sub[l]]++;
+        memcpy(sxs + 3 * d, xs + 3 * l, 3 * sizeof(float));
+        memcpy(sxe + 3 * d, xe + 3 * l, 3 * sizeof(float));
+        memcpy(sy + nb * d, y + nb * l, (size_t)nb * sizeof(double));
+    }
+    for (int j = 0; j < n_sub; ++j) {
+        int64_t a = cnt[j], m = cnt[j + 1] - cnt[j];
+        for (int64_t i = 0; i < nb * m; ++i) q[nb * a + i] = 1.0;
+        back_all(sxs + 3 * a, sxe + 3 * a, m, &g, &tf, 1, NULL, sens + nv * j, q + nb * a);
+    }
+    for (int it = 0; it < n_iter; ++it) {
+        for (int j = 0; j < n_sub; ++j) {
+            int64_t a = cnt[j], m = cnt[j + 1] - cnt[j];
+            forward_all(sxs + 3 * a, sxe + 3 * a, m, &g, &tf, 1, NULL, x, q + nb * a);
+            for (int64_t i = nb * a; i < nb * (a + m); ++i) {
+                double e = q[i] + bg;
+                q[i] = (e > 0.0) ? sy[i] / e : 0.0;
+            }
+            memset(acc, 0, (size_t)nv * sizeof(double));
+            back_all(sxs + 3 * a, sxe + 3 * a, m, &g, &tf, 1, NULL, acc, q + nb * a);
+            const double* sj = sens + nv * j;
+            for (int64_t v = 0; v < nv; ++v) x[v] = (sj[v] > 0.0) ? x[v] * acc[v] / sj[v] : 0.0;
+        }
+    }
+    free(cnt);
+    free(sxs);
+    free(sxe);
+    free(sy);
+    free(q);
+    free(sens);
+    free(acc);
+    free(fill);
+}
