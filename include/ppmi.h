@@ -37,7 +37,8 @@
  *     or a tabulated kernel (pp_tof_t.lut).
  *   Pointers: every array argument is a DEVICE pointer owned by the caller;
  *     the geometry / TOF structs are HOST pointers read during the call.
- *     The library allocates nothing and keeps no state between calls.
+ *     The library allocates nothing and keeps no state between calls (one
+ *     exception: the per-GPU workspace of pp_lm_presort_noalloc).
  *   Streams: `stream` is a hipStream_t (NULL = the default stream).  Calls
  *     are asynchronous: they enqueue kernels and return.  Calls on different
  *     streams are independent.  Every call may be captured into a HIP graph.
@@ -170,6 +171,21 @@ size_t pp_lm_presort_workspace_bytes(int64_t n);
 int pp_lm_presort(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n,
                   const pp_image_t* geom, const pp_tof_t* tof, int32_t n_sub, int32_t* order, void* workspace,
                   size_t workspace_bytes, void* stream);
+
+/* pp_lm_presort for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops that forbid allocation): the same key,
+ * sort and output, with the workspace taken from a buffer the library holds
+ * on each GPU (64 MiB, allocated when the library is loaded on that GPU and
+ * kept until the process ends) instead of a caller argument.  The call
+ * itself allocates nothing.  n is limited to the counts whose
+ * pp_lm_presort_workspace_bytes(n) fits 64 MiB (about 2 million events);
+ * larger n returns PP_EINVAL_N with nothing launched.  Every call on one GPU
+ * uses that GPU's one buffer: calls that overlap in time on one GPU (on
+ * different streams, or from different host threads without ordering) race
+ * on it and must be serialised by the caller; calls on one stream are
+ * ordered.  Every other argument and error code is that of pp_lm_presort. */
+int pp_lm_presort_noalloc(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n,
+                          const pp_image_t* geom, const pp_tof_t* tof, int32_t n_sub, int32_t* order, void* stream);
 
 /* Reorders event arrays: out[i] = in[order[i]] (tof_bin / tof_bin_out may be
  * NULL together).  In and out must not overlap.  Entries of order outside

@@ -398,6 +398,24 @@ int pp_lm_presort(const float* xstart, const float* xend, const int16_t* tof_bin
                                      workspace_bytes, as_stream(stream)));
 }
 
+int pp_lm_presort_noalloc(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n,
+                          const pp_image_t* geom, const pp_tof_t* tof, int32_t n_sub, int32_t* order, void* stream) {
+    GeomK g;
+    TofK t{};
+    PP_TRY(make_geom(geom, g));
+    if (tof_bin) PP_TRY(make_tof(tof, t));
+    if (n < 0 || n > INT32_MAX || n_sub < 1 || n_sub > 4096) return PP_EINVAL_N;
+    if (n == 0) return PP_OK;
+    if (!xstart || !xend || !order) return PP_EINVAL_PTR;
+    const size_t need = presort_workspace_bytes(n);
+    if (need == 0 || need > kPresortScratchBytes) return PP_EINVAL_N;
+    void* ws = nullptr;
+    hipError_t e = presort_scratch(&ws);
+    if (e != hipSuccess) return hip_status(e);
+    return hip_status(launch_presort(coords(xstart, xend), tof_bin, n, g, tof_bin ? t.nb : 1, n_sub, order, ws,
+                                     kPresortScratchBytes, as_stream(stream)));
+}
+
 int pp_gather_events(const float* xstart, const float* xend, const int16_t* tof_bin, const int32_t* order, int64_t n,
                      float* xstart_out, float* xend_out, int16_t* tof_bin_out, void* stream) {
     if (n < 0 || n > INT32_MAX) return PP_EINVAL_N;

@@ -27,6 +27,10 @@ hipError_t launch_fwd_tof_lm(const RaySrc& src, const int16_t* bins, int64_t n, 
 hipError_t launch_back_tof_lm(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g,
                               const TofK& t, float* img, const float* p, const int32_t* order, hipStream_t s);
 size_t presort_workspace_bytes(int64_t n);
+// capacity of the library-owned presort workspace (one per GPU) and its device address on the
+// current GPU
+constexpr size_t kPresortScratchBytes = size_t(64) << 20;
+hipError_t presort_scratch(void** ptr);
 hipError_t launch_presort(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g, int nb,
                           int n_sub, int32_t* order, void* ws, size_t ws_bytes, hipStream_t s);
 hipError_t launch_gather_events(const float* xs, const float* xe, const int16_t* bins, const int32_t* order, int64_t n,

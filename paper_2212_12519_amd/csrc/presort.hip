@@ -19,6 +19,8 @@
 
 #include <hipcub/hipcub.hpp>
 
+#include <mutex>
+
 #include "joseph.hpp"
 #include "launch.hpp"
 
@@ -89,6 +91,36 @@ static size_t sort_temp_bytes(int64_t n) {
 size_t presort_workspace_bytes(int64_t n) {
     if (n <= 0) return 0;
     return 2 * align256((size_t)n * 8) + align256((size_t)n * 4) + align256(sort_temp_bytes(n));
+}
+
+// Workspace of the presort for callers that cannot allocate device memory: one array per GPU,
+// resident from the library's load on that GPU until the process ends.  Host code never passes
+// the array's name to a kernel or a copy (on the host it names a stand-in, not device memory):
+// it uses the device address that hipGetSymbolAddress returns for the current GPU, resolved
+// once per GPU and kept.
+static __device__ __align__(256) unsigned char scratch[kPresortScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t presort_scratch(void** ptr) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_presort(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g, int nb,

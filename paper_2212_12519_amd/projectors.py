@@ -116,6 +116,21 @@ def pp_lm_presort(xstart, xend, tof_bin, geom, tof, order, workspace, n_sub=1):
     return order
 
 
+def pp_lm_presort_noalloc(xstart, xend, tof_bin, geom, tof, order, n_sub=1):
+    """pp_lm_presort with the library's own per-GPU workspace (no allocation; limited n)."""
+    g = as_geom(geom)
+    _dev(xstart, xend, tof_bin, order)
+    n = _rays(xstart, xend)
+    _order(order, n)
+    tc = None
+    if tof_bin is not None:
+        _bins(tof_bin, n)
+        tc = as_tof(tof).c(n)
+    check(load().pp_lm_presort_noalloc(ptr(xstart), ptr(xend), ptr(tof_bin), n, g.c(), tc, int(n_sub), ptr(order),
+                                       stream_of(order)))
+    return order
+
+
 def presort(xstart, xend, geom, tof_bin=None, tof=None, n_sub=1):
     order = torch.empty(xstart.shape[0], dtype=torch.int32, device=xstart.device)
     if xstart.shape[0] == 0:
