@@ -218,6 +218,17 @@ int pp_count_samples(const float* xstart, const float* xend, const int16_t* tof_
 int pp_tof_gaussian_table(const pp_tof_t* tof, float dx_max, float* lut, int32_t capacity, int32_t* n_out,
                           float* x0_out, float* dx_out, void* stream);
 
+/* How the listmode kernels (pp_*_tof_lm*, pp_lm_osem_subset_batched) evaluate
+ * the bin weight of `tof` (host-only, nothing launched): *form = 1 for a
+ * table (lut set); 2 for a piecewise polynomial of |x| fitted by the library
+ * to the Gaussian weight (two Chebyshev pieces split where the truncation
+ * makes w non-smooth, accepted only if its float32 evaluation stays within
+ * 5e-7 of the peak weight of the exact weight); 0 for the two clipped erf
+ * (per-ray sigma, or a fit that missed that bound).  The sinogram kernels
+ * always use the erf (or the table).  Errors: those of the TOF checks;
+ * PP_EINVAL_PTR if form is NULL. */
+int pp_tof_weight_form(const pp_tof_t* tof, int32_t* form);
+
 /* ------------------------------------------------------------------------
  * Crystal-index events (index-based LOR geometry).  A scanner identifies a
  * listmode event by the two crystals that detected it; the entry points

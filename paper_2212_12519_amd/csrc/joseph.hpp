@@ -26,6 +26,10 @@ struct GeomK {
     int stride[3]; // element strides (n1*n2, n2, 1)
 };
 
+// Degrees of the two polynomial pieces of the Gaussian bin weight (tof_poly).
+constexpr int kPolyCentral = 8;
+constexpr int kPolyTail = 7;
+
 struct TofK {
     double bw;            // bin width, mm
     double inv_bw;        // 1 / bw
@@ -42,6 +46,13 @@ struct TofK {
     int nb;               // bins
     const float* sig_ray; // sigma of each ray (mm), or nullptr: every ray has sigma
     const float* off_ray; // centre offset of each ray (mm), or nullptr: c0 holds the offset
+    // The Gaussian bin weight w(x) as two polynomials of y = |x| (tof_poly), fitted on the host;
+    // poly == 0 when the fit missed its error bound (the erf form is used then).
+    int poly;
+    float pk1, pk2;            // pieces: y < pk1 central, pk1 <= y < pk2 tail, 0 beyond
+    float pa1, pb1, pa2, pb2;  // central variable y^2 pa1 + pb1, tail variable y pa2 + pb2 (both in [-1, 1])
+    float pc[kPolyCentral + 1];  // central polynomial, pc[i] the coefficient of the i-th power
+    float pt[kPolyTail + 1];     // tail polynomial
 };
 
 constexpr float kErfC = 1.2011224087864498f;  // sqrt(log2(e)): scale of the erf argument (erf_scaled)
@@ -361,17 +372,51 @@ __device__ __forceinline__ float tof_lut(double x, const TofK& t) {
     return fmaf(f, b - a, a);
 }
 
-// Weight of a bin for a plane sample at signed distance x (mm) from the bin centre, up to the
-// factor kTofScale<Lut>: for the Gaussian (inv = kErfC / (sqrt(2) sigma)) 2 w(x) = 2 (G(x + bw/2) -
-// G(x - bw/2)), the difference of the two clipped erf, for a table w(x).  Every caller folds
-// kTofScale into its per-ray constant (ell, or ell times the ray's value); a power-of-two factor
-// commutes with float rounding, so the weights are applied exactly as if scaled per sample.
-template <bool Lut>
-constexpr float kTofScale = Lut ? 1.0f : 0.5f;
+// The Gaussian bin weight w(x) = G(x + bw/2) - G(x - bw/2) as a piecewise polynomial of y = |x|
+// (w is even).  w is smooth except where one of the clipped G starts or stops moving: at
+// y = |n_sigmas sigma - bw/2| and at the end of the support y = n_sigmas sigma + bw/2.  Between
+// those points it is analytic, so each piece is a Chebyshev interpolant (fitted on the host in
+// float64 from the exact erf, converted to powers of a variable in [-1, 1]): the central piece in
+// y^2, the tail piece in y.  Both pieces are evaluated (two independent Horner chains, no
+// transcendental instruction) and the one for y selected; 0 beyond the support.  The host checks
+// the float32 evaluation against the exact weight and falls back to the erf form if it misses
+// its bound.
+__device__ __forceinline__ float tof_poly(float x, const TofK& t) {
+    const float y = fabsf(x);
+    const float s1 = fmaf(y * y, t.pa1, t.pb1), s2 = fmaf(y, t.pa2, t.pb2);
+    float a = t.pc[kPolyCentral], b = t.pt[kPolyTail];
+#pragma unroll
+    for (int i = kPolyCentral - 1; i >= 0; --i) {
+        a = fmaf(a, s1, t.pc[i]);
+        if (i < kPolyTail) b = fmaf(b, s2, t.pt[i]);
+    }
+    return y < t.pk1 ? a : (y < t.pk2 ? b : 0.0f);
+}
 
-template <bool Lut>
+// How a kernel evaluates the TOF bin weight: the two clipped erf (any sigma, also per ray), the
+// table, or the fitted polynomial (one sigma for all rays).
+enum TofForm : int { kFormErf = 0, kFormLut = 1, kFormPoly = 2 };
+
+// The form a call uses for listmode kernels: the table when given, else the polynomial when its
+// fit is valid and every ray shares sigma, else the erf.
+__host__ __device__ inline int tof_form(const TofK& t) {
+    if (t.lut) return kFormLut;
+    return (t.poly && !t.sig_ray) ? kFormPoly : kFormErf;
+}
+
+// Weight of a bin for a plane sample at signed distance x (mm) from the bin centre, up to the
+// factor kTofScale<Form>: for the erf form (inv = kErfC / (sqrt(2) sigma)) 2 w(x) = 2 (G(x + bw/2) -
+// G(x - bw/2)), the difference of the two clipped erf; table and polynomial give w(x).  Every
+// caller folds kTofScale into its per-ray constant (ell, or ell times the ray's value); a
+// power-of-two factor commutes with float rounding, so the weights are applied exactly as if
+// scaled per sample.
+template <int Form>
+constexpr float kTofScale = Form == kFormErf ? 0.5f : 1.0f;
+
+template <int Form>
 __device__ __forceinline__ float tof_weight_unscaled(double x, const TofK& t, float inv) {
-    if (Lut) return tof_lut(x, t);
+    if (Form == kFormLut) return tof_lut(x, t);
+    if (Form == kFormPoly) return tof_poly((float)x, t);
     const float xf = (float)x, h = t.hbw * inv;
     return erf_scaled(__builtin_amdgcn_fmed3f(fmaf(xf, inv, h), -t.u_max, t.u_max)) -
            erf_scaled(__builtin_amdgcn_fmed3f(fmaf(xf, inv, -h), -t.u_max, t.u_max));

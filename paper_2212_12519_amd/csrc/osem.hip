@@ -46,7 +46,7 @@ __host__ __device__ inline int64_t slot_chunks(int64_t n_events, int32_t n_sub) 
 
 // Per event: forward project through the frame's current image (setup), then scatter
 // ell / ybar times the TOF weight (sample) -- the run/sheet back projection of sheet.hpp.
-template <bool Lut>
+template <int Form>
 struct ModeOsem {
     static constexpr bool kAux = false;
     const float* __restrict__ x;
@@ -61,20 +61,20 @@ struct ModeOsem {
         const __amdgpu_buffer_rsrc_t ib = img_buffer(x, g);
         float fwd = 0.0f;
         for (int k = r.k_lo; k <= r.k_hi; ++k) {
-            const float w = tof_weight_unscaled<Lut>(fma((double)k, r.ds, r.s0), t, t.u_per_mm);
+            const float w = tof_weight_unscaled<Form>(fma((double)k, r.ds, r.s0), t, t.u_per_mm);
             fwd += w * stencil_gather(ib, r, stencil_at(r, k));
         }
-        const float ybar = r.ell * kTofScale<Lut> * fwd + bg;
+        const float ybar = r.ell * kTofScale<Form> * fwd + bg;
         if (!(ybar > 0.0f)) return false;
-        cv = r.ell / ybar * kTofScale<Lut>;
+        cv = r.ell / ybar * kTofScale<Form>;
         return true;
     }
     __device__ float sample(double x, float cv, int /*aux*/) const {
-        return tof_weight_unscaled<Lut>(x, t, t.u_per_mm) * cv;
+        return tof_weight_unscaled<Form>(x, t, t.u_per_mm) * cv;
     }
 };
 
-template <bool Lut>
+template <int Form>
 __global__ void __launch_bounds__(kSheetBlock) k_osem_accumulate(const pp_frame_desc_t* __restrict__ slots,
                                                                  int n_slots, GeomK g, TofK t, int nw_lds) {
     extern __shared__ double smem[];
@@ -95,7 +95,7 @@ __global__ void __launch_bounds__(kSheetBlock) k_osem_accumulate(const pp_frame_
         const int64_t off_j = j * base_n + (j < rem ? j : rem);
         const int64_t q0 = (c - s.chunk_begin) * kOsemChunk;
         if (q0 < 0 || q0 >= n_j) continue;  // chunk offsets not from pp_osem_chunks: nothing to do
-        ModeOsem<Lut> m{s.x_fwd ? s.x_fwd : s.x, s.tof_bin + off_j, s.bg, t};
+        ModeOsem<Form> m{s.x_fwd ? s.x_fwd : s.x, s.tof_bin + off_j, s.bg, t};
         const RaySrc src = s.crystal_pair ? RaySrc{s.crystal_xyz, nullptr, reinterpret_cast<const int2*>(s.crystal_pair),
                                                    s.n_crystals}
                                           : RaySrc{s.xstart, s.xend, nullptr, 0};
@@ -141,28 +141,30 @@ __global__ void k_fill(float* __restrict__ dst, int64_t n, float value) {
 
 int64_t osem_chunks(int64_t n_events, int32_t n_sub) { return slot_chunks(n_events, n_sub); }
 
-template <bool Lut>
+template <int Form>
 static hipError_t launch_accumulate(const pp_frame_desc_t* slots, int n_slots, const GeomK& g, const TofK& t, int cus,
                                    hipStream_t s) {
     const int nw = (g.n[2] <= kSheetMaxW) ? g.n[2] : 0;
     const size_t lds = SheetLayout::bytes(nw, g);
-    hipError_t e = hipFuncSetAttribute((const void*)k_osem_accumulate<Lut>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_osem_accumulate<Form>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     // persistent grid: as many workgroups as can be resident at once (LDS-limited)
     int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_osem_accumulate<Lut>, kSheetBlock, lds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_osem_accumulate<Form>, kSheetBlock, lds);
     if (e != hipSuccess) return e;
     if (per_cu < 1) per_cu = 1;
-    hipLaunchKernelGGL(k_osem_accumulate<Lut>, dim3(cus * per_cu), dim3(kSheetBlock), lds, s, slots, n_slots, g, t,
+    hipLaunchKernelGGL(k_osem_accumulate<Form>, dim3(cus * per_cu), dim3(kSheetBlock), lds, s, slots, n_slots, g, t,
                        nw);
     return hipGetLastError();
 }
 
 hipError_t launch_osem_accumulate(const pp_frame_desc_t* slots, int n_slots, const GeomK& g, const TofK& t, int cus,
                                   hipStream_t s) {
-    return t.lut ? launch_accumulate<true>(slots, n_slots, g, t, cus, s)
-                 : launch_accumulate<false>(slots, n_slots, g, t, cus, s);
+    const int form = tof_form(t);
+    if (form == kFormLut) return launch_accumulate<kFormLut>(slots, n_slots, g, t, cus, s);
+    if (form == kFormPoly) return launch_accumulate<kFormPoly>(slots, n_slots, g, t, cus, s);
+    return launch_accumulate<kFormErf>(slots, n_slots, g, t, cus, s);
 }
 
 hipError_t launch_osem_update(pp_frame_desc_t* slots, int n_slots, int64_t n_vox, int n_blocks, hipStream_t s) {

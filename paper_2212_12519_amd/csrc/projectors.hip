@@ -46,7 +46,7 @@ __global__ void __launch_bounds__(kBlock) k_fwd(RaySrc src,
 // of a wave gather from the same planes at each step; with per-ray parameters the windows start
 // at different planes, so the loop runs over absolute planes instead (wave-synchronous: all
 // lanes at plane k, each active inside its own window), keeping the gathers of a step coherent.
-template <bool Lut, bool PerRay>
+template <int Form, bool PerRay>
 __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(RaySrc src,
                                                        const int16_t* __restrict__ bins, int64_t n, GeomK g,
                                                        TofK t, const float* __restrict__ img,
@@ -68,17 +68,17 @@ __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(RaySrc src,
         const int k0 = wave_min(lo), k1 = wave_max(hi);
         for (int k = k0; k <= k1; ++k) {
             if (k >= lo && k <= hi) {
-                const float w = tof_weight_unscaled<Lut>(fma((double)k, r.ds, r.s0), t, q.inv);
+                const float w = tof_weight_unscaled<Form>(fma((double)k, r.ds, r.s0), t, q.inv);
                 acc += w * stencil_gather(ib, r, stencil_at(r, k));
             }
         }
     } else if (on) {
         for (int k = r.k_lo; k <= r.k_hi; ++k) {
-            const float w = tof_weight_unscaled<Lut>(fma((double)k, r.ds, r.s0), t, q.inv);
+            const float w = tof_weight_unscaled<Form>(fma((double)k, r.ds, r.s0), t, q.inv);
             acc += w * stencil_gather(ib, r, stencil_at(r, k));
         }
     }
-    if (on) acc *= r.ell * kTofScale<Lut>;
+    if (on) acc *= r.ell * kTofScale<Form>;
     if (l >= 0) p[l] = acc;
 }
 
@@ -213,20 +213,25 @@ hipError_t launch_back(const RaySrc& src, int64_t n, const GeomK& g, float* img,
 hipError_t launch_fwd_tof_lm(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g,
                              const TofK& t, const float* img, float* p, const int32_t* order, hipStream_t s) {
     const bool per = t.sig_ray || t.off_ray;
-    auto* k = t.lut ? (per ? k_fwd_tof_lm<true, true> : k_fwd_tof_lm<true, false>)
-                    : (per ? k_fwd_tof_lm<false, true> : k_fwd_tof_lm<false, false>);
+    const int form = tof_form(t);
+    auto* k = form == kFormLut    ? (per ? k_fwd_tof_lm<kFormLut, true> : k_fwd_tof_lm<kFormLut, false>)
+              : form == kFormPoly ? (per ? k_fwd_tof_lm<kFormPoly, true> : k_fwd_tof_lm<kFormPoly, false>)
+                                  : (per ? k_fwd_tof_lm<kFormErf, true> : k_fwd_tof_lm<kFormErf, false>);
     hipLaunchKernelGGL(k, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, src, bins, n, g, t, img, p, order);
     return hipGetLastError();
 }
 
 hipError_t launch_back_tof_lm(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g,
                               const TofK& t, float* img, const float* p, const int32_t* order, hipStream_t s) {
+    const int form = tof_form(t);
     if (t.sig_ray || t.off_ray) {
-        if (t.lut) return launch_runs(ModeTofLm<true, true>{p, bins, t}, src, n, g, img, order, s);
-        return launch_runs(ModeTofLm<false, true>{p, bins, t}, src, n, g, img, order, s);
+        if (form == kFormLut) return launch_runs(ModeTofLm<kFormLut, true>{p, bins, t}, src, n, g, img, order, s);
+        if (form == kFormPoly) return launch_runs(ModeTofLm<kFormPoly, true>{p, bins, t}, src, n, g, img, order, s);
+        return launch_runs(ModeTofLm<kFormErf, true>{p, bins, t}, src, n, g, img, order, s);
     }
-    if (t.lut) return launch_runs(ModeTofLm<true>{p, bins, t}, src, n, g, img, order, s);
-    return launch_runs(ModeTofLm<false>{p, bins, t}, src, n, g, img, order, s);
+    if (form == kFormLut) return launch_runs(ModeTofLm<kFormLut>{p, bins, t}, src, n, g, img, order, s);
+    if (form == kFormPoly) return launch_runs(ModeTofLm<kFormPoly>{p, bins, t}, src, n, g, img, order, s);
+    return launch_runs(ModeTofLm<kFormErf>{p, bins, t}, src, n, g, img, order, s);
 }
 
 static int sino_block(int nb) { return nb <= 64 ? 256 : 64; }  // LDS tile <= 64 KiB

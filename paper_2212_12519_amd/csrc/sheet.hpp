@@ -73,9 +73,10 @@ struct ModeNonTof {
     __device__ float sample(double /*x*/, float cv, int /*aux*/) const { return cv; }
 };
 
-// Listmode TOF.  With per-ray TOF parameters (PerRay) the ray's offset is folded into its TOF
-// coordinate at setup and aux carries the bits of its erf argument per mm (TofRay::inv).
-template <bool Lut, bool PerRay = false>
+// Listmode TOF, the weight in form Form (TofForm).  With per-ray TOF parameters (PerRay) the ray's
+// offset is folded into its TOF coordinate at setup and aux carries the bits of its erf argument
+// per mm (TofRay::inv).
+template <int Form, bool PerRay = false>
 struct ModeTofLm {
     static constexpr bool kAux = PerRay;
     const float* __restrict__ p;
@@ -90,12 +91,12 @@ struct ModeTofLm {
             return false;
         if (PerRay) r.s0 -= q.shift;
         if (!tof_window_rel(r, t.c0 + b * t.bw, q.lo, q.hi)) return false;
-        cv = r.ell * pl * kTofScale<Lut>;
+        cv = r.ell * pl * kTofScale<Form>;
         if (PerRay) aux = __float_as_int(q.inv);
         return true;
     }
     __device__ float sample(double x, float cv, int aux) const {
-        return tof_weight_unscaled<Lut>(x, t, PerRay ? __int_as_float(aux) : t.u_per_mm) * cv;
+        return tof_weight_unscaled<Form>(x, t, PerRay ? __int_as_float(aux) : t.u_per_mm) * cv;
     }
 };
 

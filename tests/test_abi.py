@@ -198,3 +198,26 @@ def test_python_binding_rejects_cpu_tensors():
     x = torch.zeros((4, 3))
     with pytest.raises(TypeError):
         pp.fwd(x, x, pp.ImageGeom((2, 2, 2), (1, 1, 1)), torch.zeros(2, 2, 2))
+
+
+def test_tof_weight_form(lib):
+    """pp_tof_weight_form (host-only): the fitted polynomial for the clinical kernel and for a
+    per-ray offset, the table when one is given, the erf for per-ray sigma and where no fit of the
+    fixed degrees reaches the bound (truncation at 8 sigma: w spans too many decades)."""
+    from paper_2212_12519_amd._lib import PP_EINVAL_PTR, PP_EINVAL_TOF, PP_OK, CTof
+
+    form = ctypes.c_int32(-1)
+
+    def f(t):
+        form.value = -1
+        assert lib.pp_tof_weight_form(t, ctypes.byref(form)) == PP_OK
+        return form.value
+
+    clin = (28.0, 58.5 / 2.355, 3.0, 29)
+    assert f(_tof(*clin)) == 2
+    assert f(_tof(28.0, 58.5 / 2.355, 8.0, 29)) == 0
+    assert f(CTof(*clin[:3], 0.0, clin[3], None, 0, 0.0, 0.0, None, DUMMY)) == 2  # per-ray offset only
+    assert f(CTof(*clin[:3], 0.0, clin[3], None, 0, 0.0, 0.0, DUMMY, None)) == 0  # per-ray sigma
+    assert f(CTof(*clin[:3], 0.0, clin[3], DUMMY, 100, -50.0, 1.0, None, None)) == 1  # table
+    assert lib.pp_tof_weight_form(_tof(sig=0.0), ctypes.byref(form)) == PP_EINVAL_TOF
+    assert lib.pp_tof_weight_form(_tof(*clin), None) == PP_EINVAL_PTR
