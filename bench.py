@@ -49,8 +49,8 @@ def kernel_sources_sha():
 
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "tof_lm_40M_traffic.json")
 # the device kernel each timed entry point of the listmode step launches
-KERNEL_OF = {"pp_lm_presort": "ppmi::k_lm_keys", "pp_fwd_tof_lm": "ppmi::k_fwd_tof_lm<false, false>",
-             "pp_back_tof_lm": "ppmi::k_back_runs<ppmi::ModeTofLm<false, false> >"}
+KERNEL_OF = {"pp_lm_presort": "ppmi::k_lm_keys", "pp_fwd_tof_lm": "ppmi::k_fwd_tof_lm<2, false>",
+             "pp_back_tof_lm": "ppmi::k_back_runs<ppmi::ModeTofLm<2, false> >"}
 
 
 def profiled_traffic(entry):
@@ -122,7 +122,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the OSEM serving leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=25.0, help="calibrated oracle time for the CPU baseline")
-    ap.add_argument("--only", default=None, help="profiling helper: lm | sino | serve")
+    ap.add_argument("--only", default=None, help="profiling helper: lm | sino | sino_osem | serve")
     ap.add_argument("--serve-requests", type=int, default=None, help="requests in the serving leg (default 256)")
     ap.add_argument("--no-res", action="store_true", help="serving leg without the resolution model")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
@@ -190,7 +190,7 @@ def lm_leg(args, pp, C, dev):
         lambda: pp.pp_fill(bimg, 0.0), args.steps, args.warmup)
     # the same projector pair in the events' own (unsorted) order (skipped when profiling the step)
     t_fwd_u = t_back_u = float("nan")
-    crys, per_ray = {}, {}
+    crys, per_ray, nontof = {}, {}, {}
     if args.only is None:
         _, t_fwd_u, t_back_u = timed_pairs(lambda: pp.pp_fwd_tof_lm(xs, xe, bins, G, T, img, p),
                                            lambda: pp.pp_back_tof_lm(xs, xe, bins, G, T, bimg, p),
@@ -217,6 +217,20 @@ def lm_leg(args, pp, C, dev):
         per_ray = {"t_fwd_ms": pf, "t_back_ms": pb}
         log(f"TOF-LM per-event sigma and offset: fwd {pf:.2f} ms, back {pb:.2f} ms")
         del sig, off, TP
+        # non-TOF listmode on the same events (the paper's slowest GPU case): presort without
+        # TOF bins, forward and back projection of the whole chord
+        n_samples_nt = int(pp.count_samples(xs, xe, G).sum(dtype=torch.int64).item())
+        wall_n, (ns_, nf, nb_) = timed_phases(
+            [lambda: pp.pp_lm_presort(xs, xe, None, G, None, order, sort_ws),
+             lambda: pp.pp_fwd(xs, xe, G, img, p, order),
+             lambda: pp.pp_back(xs, xe, G, bimg, p, order)],
+            lambda: pp.pp_fill(bimg, 0.0), 5, 2)
+        alg_nt = (24 + 4) * n_ev + 16 * n_samples_nt
+        nontof = {"t_presort_ms": ns_, "t_fwd_ms": nf, "t_back_ms": nb_, "events_per_s": n_ev / (wall_n / 5),
+                  "samples_per_event": n_samples_nt / n_ev, "fwd_alg_gbs": alg_nt / (nf * 1e-3) / 1e9,
+                  "back_alg_gbs": alg_nt / (nb_ * 1e-3) / 1e9}
+        log(f"non-TOF LM: presort {ns_:.2f} ms, fwd {nf:.2f} ms, back {nb_:.2f} ms, "
+            f"{n_samples_nt / n_ev:.1f} samples/event")
     log(f"TOF-LM: presort {t_sort:.2f} ms, fwd {t_fwd:.2f} ms, back {t_back:.2f} ms, wall "
         f"{1e3 * wall / args.steps:.2f} ms/step; unsorted order: fwd {t_fwd_u:.2f} ms back {t_back_u:.2f} ms; "
         f"{n_samples / n_ev:.1f} samples/event")
@@ -230,7 +244,7 @@ def lm_leg(args, pp, C, dev):
         "samples_per_event": n_samples / n_ev, "alg_bytes_per_launch": alg_bytes,
         "dominant": dom_name, "achieved_gbs": achieved,
         "fwd_alg_gbs": alg_bytes / (t_fwd * 1e-3) / 1e9, "back_alg_gbs": alg_bytes / (t_back * 1e-3) / 1e9,
-        "crystal_index_events": crys, "per_event_tof_params": per_ray,
+        "crystal_index_events": crys, "per_event_tof_params": per_ray, "nontof_listmode": nontof,
     }
     return res, (xs, xe, bins, img, G, T)
 
@@ -324,6 +338,98 @@ def sino_leg(args, pp, C, dev):
     return out
 
 
+def autograd_leg(args, pp, C, dev, lm_inputs):
+    """Batch of 8 images 128 x 128 x 64 (2.78 mm) through the TOF listmode projector inside
+    torch.autograd with the Poisson NLL (background 0.1, y = 1 per event): one step = forward
+    projection of the batch, the loss, and its backward (the back projection of the batch).
+    Events are presorted once when the operator is built."""
+    import torch
+
+    from paper_2212_12519_amd.autograd import JosephOperator, poisson_nll
+    from synth.phantom import ellipsoid_lesion_phantom
+
+    xs, xe, bins, _, _, T = lm_inputs
+    grid = C.GRID_DL
+    G = pp.ImageGeom(grid.dim, grid.voxsize, grid.origin)
+    imgs = torch.stack([ellipsoid_lesion_phantom(grid, seed=s, device=dev) for s in C.SEEDS_DL_IMAGES])
+    op = JosephOperator(xs, xe, G, kind="tof_lm", tof=T, tof_bin=bins, presort=True)
+    y = torch.ones((imgs.shape[0], op.n), dtype=torch.float32, device=dev)
+    state = {}
+
+    def fwd():
+        x = imgs.clone().requires_grad_(True)
+        state["x"], state["loss"] = x, poisson_nll(op(x) + C.BG_DL, y)
+
+    def bwd():
+        state["loss"].backward()
+
+    steps = max(2, min(args.steps, 5))
+    wall, (tf, tb) = timed_phases([fwd, bwd], lambda: None, steps, 1)
+    n_img = imgs.shape[0]
+    res = {"batch": n_img, "image": list(grid.dim), "n_events": op.n, "t_forward_ms": tf, "t_backward_ms": tb,
+           "ms_per_step": 1e3 * wall / steps, "image_events_per_s": n_img * op.n / (wall / steps)}
+    log(f"autograd batch of {n_img}: forward+loss {tf:.1f} ms, backward {tb:.1f} ms, "
+        f"{n_img * op.n / (wall / steps) / 1e6:.0f} M image-events/s")
+    del op, imgs, y, state
+    torch.cuda.empty_cache()
+    return res
+
+
+def sino_osem_leg(args, pp, C, dev):
+    """TOF sinogram OSEM on the full clinical sinogram (335,008,000 LORs x 29 bins): 8 view subsets
+    (view mod 8), counts y = the TOF forward projection of the phantom (expected counts), one
+    iteration = 8 subset updates, each in chunks of 2^22 LORs through a 0.49 GB workspace, with
+    1 shard (the plain path) and 4 shards (four private accumulator images summed in the update
+    pass).  Reports s per iteration and the peak device memory of the leg."""
+    import torch
+
+    from paper_2212_12519_amd import sino_osem
+
+    grid, tofs = C.GRID_CLIN, C.TOF_CLIN
+    G = pp.ImageGeom(grid.dim, grid.voxsize, grid.origin)
+    T = pp.TofParams(tofs.bin_width, tofs.sigma, tofs.n_sigmas, tofs.n_bins)
+    n_sub, work_lors = 8, 1 << 22
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats(dev)
+    base = torch.cuda.memory_allocated(dev)
+    img = C.phantom_clin(device=dev)
+    work = torch.empty((work_lors, tofs.n_bins), dtype=torch.float32, device=dev)
+    subsets = []
+    for j in range(n_sub):
+        xs, xe = C.SINO_CLIN.lors(views=list(range(j, C.SINO_CLIN.shape[1], n_sub)), device=dev, radial_chunk=50)
+        y = torch.empty((xs.shape[0], tofs.n_bins), dtype=torch.float32, device=dev)
+        for a in range(0, xs.shape[0], work_lors):
+            b = min(xs.shape[0], a + work_lors)
+            pp.pp_fwd_tof_sino(xs[a:b], xe[a:b], G, T, img, y[a:b])
+        subsets.append((xs, xe, y))
+    n = sum(s[0].shape[0] for s in subsets)
+    t0 = time.perf_counter()
+    _, sens = sino_osem.tof_sino_osem(subsets, G, T, torch.ones(grid.dim, device=dev), 0, work_lors=work_lors)
+    torch.cuda.synchronize()
+    t_sens = time.perf_counter() - t0
+    out = {"n_lors": n, "n_bins": tofs.n_bins, "subsets": n_sub, "work_lors": work_lors, "t_sensitivity_s": t_sens}
+    for shards in (1, 4):
+        x = torch.ones(grid.dim, dtype=torch.float32, device=dev)
+        acc = torch.zeros((shards,) + tuple(grid.dim), dtype=torch.float32, device=dev)
+
+        def iteration():
+            for (xs, xe, y), s in zip(subsets, sens):
+                sino_osem.pp_tof_sino_osem_subset(xs, xe, y, G, T, 0.0, x, acc, s, work)
+
+        reps = 2
+        wall, (t_it,) = timed_phases([iteration], lambda: None, reps, 1)
+        out[f"shards_{shards}"] = {"s_per_iteration": t_it * 1e-3, "lors_per_s": n / (t_it * 1e-3)}
+        log(f"TOF-sino OSEM, {shards} shard(s): {t_it:.1f} ms per iteration (8 subsets)")
+    out["peak_device_gb"] = (torch.cuda.max_memory_allocated(dev) - base) / 1e9
+    out["resident_data_gb"] = sum(s[0].numel() * 8 + s[2].numel() * 4 for s in subsets) / 1e9
+    log(f"TOF-sino OSEM peak device memory {out['peak_device_gb']:.1f} GB "
+        f"(LORs + counts {out['resident_data_gb']:.1f} GB)")
+    del subsets, sens, work, img
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.write_traffic:
@@ -357,10 +463,13 @@ def main():
         return
     if args.only in (None, "sino") and not args.no_sino:
         extra["sinogram"] = sino_leg(args, pp, C, dev)
-    if args.only == "sino":
+    if args.only in (None, "sino_osem") and not args.no_sino:
+        extra["tof_sino_osem"] = sino_osem_leg(args, pp, C, dev)
+    if args.only in ("sino", "sino_osem"):
         print(json.dumps(extra))
         return
     if args.only is None:
+        extra["autograd"] = autograd_leg(args, pp, C, dev, lm_inputs)
         extra["resolution_model"] = resmodel_leg(args, pp, C, dev)
     if args.only in (None, "serve") and not args.no_serve:
         from paper_2212_12519_amd import serve
@@ -387,7 +496,7 @@ def main():
                      "alg_bytes_per_launch": lm["alg_bytes_per_launch"]},
         "cpu_baseline": cpu,
         "lm": {k: lm[k] for k in ("t_presort_ms", "t_fwd_ms", "t_back_ms", "unsorted_t_fwd_ms", "unsorted_t_back_ms",
-                                  "samples_per_event", "fwd_alg_gbs", "back_alg_gbs")},
+                                  "samples_per_event", "fwd_alg_gbs", "back_alg_gbs", "nontof_listmode")},
     })
     result.update(extra)
     print(json.dumps(result), flush=True)

@@ -343,6 +343,46 @@ int pp_osem_update_batched(pp_frame_desc_t* d_slots, int32_t n_slots, const pp_i
 /* OSEM start image: x_v = 1 where sens_v > 0, else 0. */
 int pp_osem_init(float* x, const float* sens, int64_t n_vox, void* stream);
 
+/* ------------------------------------------------------------------------
+ * TOF sinogram OSEM in LOR chunks.  The sinogram counterpart of the listmode
+ * OSEM above: x <- x * A_j^T (y / (A_j x + bg)) / A_j^T 1 per subset j (0
+ * where A_j^T 1 == 0; a (LOR, bin) whose expectation A_j x + bg is not
+ * positive contributes nothing).  The paper's Sec. 4 discusses the memory a
+ * TOF sinogram reconstruction needs (the data and its expectation, tens of
+ * GB) and chunk-wise processing for long axial fields of view: here only the
+ * counts y and the LOR end points are resident; the expectation of at most
+ * work_lors LORs at a time lives in a caller workspace.
+ * The caller stores each subset's LORs contiguously (e.g. subset j = views
+ * with view mod n_sub == j) and calls once per subset.
+ * ------------------------------------------------------------------------ */
+
+/* Subset sensitivity: sens += A^T 1 over the n_lors LORs (all n_bins bins),
+ * back projected in chunks of work_lors LORs through work (DEVICE float32
+ * [work_lors][n_bins], overwritten).  Errors: PP_EINVAL_TOF also for
+ * per-ray TOF parameters; PP_EINVAL_N for work_lors not in [1, 2^31). */
+int pp_tof_sino_sensitivity(const float* xstart, const float* xend, int64_t n_lors, const pp_image_t* geom,
+                            const pp_tof_t* tof, float* sens, float* work, int64_t work_lors, void* stream);
+
+/* One subset update of the n_lors LORs of subset j (xstart, xend [n][3];
+ * y [n][n_bins] counts; sens = A_j^T 1 from pp_tof_sino_sensitivity over the
+ * same LORs).  For each chunk of at most work_lors LORs: forward TOF sinogram
+ * projection of x into work, work <- y / (work + bg) (0 where work + bg <=
+ * 0), back projection of work into an accumulator.  Shards: the LORs are
+ * split into n_shards contiguous ranges, shard s back projected into its own
+ * image acc + s n_vox -- the private images K GPUs would fill, each with its
+ * share of the LORs -- and one final pass sums the shard images, applies
+ * x <- x * sum / sens (0 where sens == 0) and zeroes every shard image.
+ *   x:    DEVICE [n_vox], updated in place;
+ *   acc:  DEVICE [n_shards][n_vox], zero on entry, zero on return;
+ *   work: DEVICE float32 [work_lors][n_bins] workspace.
+ * x, acc, sens and work must not overlap (PP_EINVAL_PTR).  n_lors == 0 still
+ * applies the update (an empty subset has sens == 0: x becomes 0).
+ * Errors: PP_EINVAL_TOF also for per-ray TOF parameters; PP_EINVAL_N for
+ * n_shards not in [1, 1024], work_lors not in [1, 2^31) or bg non-finite. */
+int pp_tof_sino_osem_subset(const float* xstart, const float* xend, const float* y, int64_t n_lors,
+                            const pp_image_t* geom, const pp_tof_t* tof, float bg, float* x, float* acc,
+                            int32_t n_shards, const float* sens, float* work, int64_t work_lors, void* stream);
+
 /* Image-based resolution model (the paper's listmode OSEM uses a 3D Gaussian
  * of 4.5 mm FWHM, Sec. 2.6): dst = G src, G the discrete Gaussian blur with,
  * along image axis a, taps exp(-i^2 / (2 s_a^2)) for |i| <= floor(4 s_a + 1/2),

@@ -175,6 +175,8 @@ def load():
         "pp_count_samples_crystals": [P, I32, P, P, I64, G, T, P, P],
         "pp_gather_crystal_events": [P, P, P, I64, P, P, P],
         "pp_tof_weight_form": [T, ctypes.POINTER(I32)],
+        "pp_tof_sino_sensitivity": [P, P, I64, G, T, P, P, I64, P],
+        "pp_tof_sino_osem_subset": [P, P, P, I64, G, T, ctypes.c_float, P, P, I32, P, P, I64, P],
         "pp_tof_gaussian_table": [T, ctypes.c_float, P, I32, ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_float),
                                   ctypes.POINTER(ctypes.c_float), P],
     }

@@ -204,6 +204,13 @@ bool overlap(const void* a, const void* b, int64_t bytes) {
     return p < q + bytes && q < p + bytes;
 }
 
+// [a, a + a_bytes) and [b, b + b_bytes) share a byte
+bool overlap2(const void* a, int64_t a_bytes, const void* b, int64_t b_bytes) {
+    const char* p = static_cast<const char*>(a);
+    const char* q = static_cast<const char*>(b);
+    return p < q + b_bytes && q < p + a_bytes;
+}
+
 // grid limit: 2^31 - 1 workgroups of >= 64 threads
 constexpr int64_t kMaxRays = ((int64_t(1) << 31) - 1) * 64;
 
@@ -554,6 +561,41 @@ int pp_osem_update_batched(pp_frame_desc_t* d_slots, int32_t n_slots, const pp_i
     if (e == hipSuccess) e = launch_osem_res_update(d_slots, n_slots, g, k, cus, s);
     if (e == hipSuccess) e = launch_osem_advance(d_slots, n_slots, s);
     return hip_status(e);
+}
+
+int pp_tof_sino_sensitivity(const float* xstart, const float* xend, int64_t n_lors, const pp_image_t* geom,
+                            const pp_tof_t* tof, float* sens, float* work, int64_t work_lors, void* stream) {
+    GeomK g;
+    TofK t;
+    PP_TRY(make_geom(geom, g));
+    PP_TRY(make_tof(tof, t));
+    if (t.sig_ray || t.off_ray) return PP_EINVAL_TOF;
+    PP_TRY(check_n(n_lors));
+    if (work_lors < 1 || work_lors >= (int64_t(1) << 31)) return PP_EINVAL_N;
+    if (n_lors == 0) return PP_OK;
+    if (!xstart || !xend || !sens || !work) return PP_EINVAL_PTR;
+    return hip_status(launch_tof_sino_sensitivity(xstart, xend, n_lors, g, t, sens, work, work_lors, as_stream(stream)));
+}
+
+int pp_tof_sino_osem_subset(const float* xstart, const float* xend, const float* y, int64_t n_lors,
+                            const pp_image_t* geom, const pp_tof_t* tof, float bg, float* x, float* acc,
+                            int32_t n_shards, const float* sens, float* work, int64_t work_lors, void* stream) {
+    GeomK g;
+    TofK t;
+    PP_TRY(make_geom(geom, g));
+    PP_TRY(make_tof(tof, t));
+    if (t.sig_ray || t.off_ray) return PP_EINVAL_TOF;
+    PP_TRY(check_n(n_lors));
+    if (n_shards < 1 || n_shards > 1024 || work_lors < 1 || work_lors >= (int64_t(1) << 31) || !std::isfinite(bg))
+        return PP_EINVAL_N;
+    if (!x || !acc || !sens || (n_lors > 0 && (!xstart || !xend || !y || !work))) return PP_EINVAL_PTR;
+    const int64_t vb = (int64_t)g.n[0] * g.n[1] * g.n[2] * (int64_t)sizeof(float), ab = vb * n_shards;
+    const int64_t wb = work_lors * t.nb * (int64_t)sizeof(float);
+    if (overlap2(x, vb, acc, ab) || overlap2(x, vb, sens, vb) || overlap2(acc, ab, sens, vb) ||
+        (n_lors > 0 && (overlap2(work, wb, x, vb) || overlap2(work, wb, acc, ab) || overlap2(work, wb, sens, vb))))
+        return PP_EINVAL_PTR;
+    return hip_status(launch_tof_sino_osem_subset(xstart, xend, y, n_lors, g, t, bg, x, acc, n_shards, sens, work,
+                                                  work_lors, device_cus(), as_stream(stream)));
 }
 
 int pp_gauss3d(const float* src, float* dst, float* tmp, const pp_image_t* geom, const float* fwhm, void* stream) {

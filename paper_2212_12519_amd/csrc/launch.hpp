@@ -48,6 +48,11 @@ hipError_t launch_osem_accumulate(const pp_frame_desc_t* slots, int n_slots, con
 hipError_t launch_osem_update(pp_frame_desc_t* slots, int n_slots, int64_t n_vox, int n_blocks, hipStream_t s);
 hipError_t launch_osem_advance(pp_frame_desc_t* slots, int n_slots, hipStream_t s);
 hipError_t launch_fill(float* dst, int64_t n, float value, hipStream_t s);
+hipError_t launch_tof_sino_osem_subset(const float* xs, const float* xe, const float* y, int64_t n, const GeomK& g,
+                                       const TofK& t, float bg, float* x, float* acc, int n_shards,
+                                       const float* sens, float* work, int64_t work_lors, int cus, hipStream_t s);
+hipError_t launch_tof_sino_sensitivity(const float* xs, const float* xe, int64_t n, const GeomK& g, const TofK& t,
+                                       float* sens, float* work, int64_t work_lors, hipStream_t s);
 
 struct GaussK;
 hipError_t launch_gauss3d(const float* src, float* dst, float* tmp, const GeomK& g, const GaussK& k, int cus,

@@ -221,3 +221,33 @@ def test_tof_weight_form(lib):
     assert f(CTof(*clin[:3], 0.0, clin[3], DUMMY, 100, -50.0, 1.0, None, None)) == 1  # table
     assert lib.pp_tof_weight_form(_tof(sig=0.0), ctypes.byref(form)) == PP_EINVAL_TOF
     assert lib.pp_tof_weight_form(_tof(*clin), None) == PP_EINVAL_PTR
+
+
+def test_tof_sino_osem_argument_errors(lib):
+    """pp_tof_sino_sensitivity / pp_tof_sino_osem_subset reject bad counts, shards, workspaces,
+    per-ray TOF parameters and overlapping images before any launch."""
+    from paper_2212_12519_amd._lib import PP_EINVAL_N, PP_EINVAL_PTR, PP_EINVAL_TOF, CTof
+
+    g = _geom()
+    t = _tof()
+    per = CTof(1.0, 1.0, 3.0, 0.0, 5, None, 0, 0.0, 0.0, DUMMY, None)
+    f = lib.pp_tof_sino_osem_subset
+    nvb = 4 * 4 * 4 * 4  # bytes of one image of _geom()
+    X, A, S, W = ctypes.c_void_p(1 << 24), ctypes.c_void_p(1 << 25), ctypes.c_void_p(1 << 26), ctypes.c_void_p(1 << 27)
+    assert f(DUMMY, DUMMY, DUMMY, 10, g, t, 0.1, X, A, 0, S, W, 100, None) == PP_EINVAL_N  # no shard
+    assert f(DUMMY, DUMMY, DUMMY, 10, g, t, 0.1, X, A, 1025, S, W, 100, None) == PP_EINVAL_N
+    assert f(DUMMY, DUMMY, DUMMY, 10, g, t, 0.1, X, A, 1, S, W, 0, None) == PP_EINVAL_N  # no workspace rows
+    assert f(DUMMY, DUMMY, DUMMY, 10, g, t, float("nan"), X, A, 1, S, W, 100, None) == PP_EINVAL_N
+    assert f(DUMMY, DUMMY, DUMMY, -1, g, t, 0.1, X, A, 1, S, W, 100, None) == PP_EINVAL_N
+    assert f(DUMMY, DUMMY, DUMMY, 10, g, per, 0.1, X, A, 1, S, W, 100, None) == PP_EINVAL_TOF
+    assert f(DUMMY, DUMMY, None, 10, g, t, 0.1, X, A, 1, S, W, 100, None) == PP_EINVAL_PTR
+    # x inside the second shard image; workspace over sens
+    A2 = ctypes.c_void_p((1 << 24) - nvb)
+    assert f(DUMMY, DUMMY, DUMMY, 10, g, t, 0.1, X, A2, 2, S, W, 100, None) == PP_EINVAL_PTR
+    assert f(DUMMY, DUMMY, DUMMY, 10, g, t, 0.1, X, A, 1, S, ctypes.c_void_p((1 << 26) - 8), 100,
+             None) == PP_EINVAL_PTR
+    s = lib.pp_tof_sino_sensitivity
+    assert s(DUMMY, DUMMY, 10, g, t, S, W, 0, None) == PP_EINVAL_N
+    assert s(DUMMY, DUMMY, 10, g, per, S, W, 10, None) == PP_EINVAL_TOF
+    assert s(DUMMY, DUMMY, 10, g, t, None, W, 10, None) == PP_EINVAL_PTR
+    assert s(DUMMY, DUMMY, 0, g, t, None, None, 10, None) == 0  # nothing to do
