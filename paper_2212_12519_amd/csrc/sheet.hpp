@@ -144,29 +144,9 @@ struct ModeTofSino {
     }
 };
 
-// The column entries (j, j + 1) of thread-private column k: col_get reads them, col_put stores
-// pa + a, pb + b back.  The sheet loop reads the pair when z moves to it and writes it back when
-// z moves on, so the read's latency overlaps the work in between instead of stalling a
-// read-modify-write (LDS float atomics run at ~0.2 T adds/s on this GPU against ~2.7 T/s for
-// read-modify-write of thread-private words).  A read issued after the write-back of an
-// overlapping pair sees it: one wave's LDS accesses complete in order.  Entries outside the grid
-// (j = -1, j + 1 = nw, or no entry yet) go to the spare row nw, which is never flushed, so both
-// calls are four plain LDS accesses with no branch.
-// The LDS indices of the pair are kept from the read to the write-back (ia, ib).
+// Row of z entry j in a thread's column: entries outside the grid (j = -1, j = nw, or no entry yet)
+// go to the spare row nw, which is never flushed, so that a pair's LDS accesses need no branch.
 __device__ __forceinline__ int col_row(int j, int nw) { return ((unsigned)j < (unsigned)nw) ? j : nw; }
-
-__device__ __forceinline__ void col_get(const float* col, int j, int k, int nw, int cs, int& ia, int& ib, float& pa,
-                                        float& pb) {
-    ia = (int)__umul24((unsigned)col_row(j, nw), (unsigned)cs) + k;  // rows and strides < 2^24
-    ib = (int)__umul24((unsigned)col_row(j + 1, nw), (unsigned)cs) + k;
-    pa = col[ia];
-    pb = col[ib];
-}
-
-__device__ __forceinline__ void col_put(float* col, int ia, int ib, float pa, float a, float pb, float b) {
-    col[ia] = pa + a;
-    col[ib] = pb + b;
-}
 
 // Flush the sheet of line (p, U0, dU) with contiguous atomics and clear it: only the planes
 // whose thread accumulated something (touched), listed in tl[], only the z entries between the
@@ -414,8 +394,11 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
             int jc = kNoEntry;
             float accA = 0.0f, accB = 0.0f;
             float preA = 0.0f, preB = 0.0f;  // column values of the pair jc, read when z moved to it
-            int ia = (int)__umul24((unsigned)nw, (unsigned)cs) + k, ib = ia;  // its LDS indices (spare row;
-                                                                              // used only while kin)
+            // the column this thread writes: its own plane's, or for threads past the line's last plane
+            // the unused last column (cs - 1 is never a plane of a sheet line), whose spare-row entry
+            // takes their (zero) write-backs
+            const int kc = kin ? k : cs - 1;
+            int ia = (int)__umul24((unsigned)nw, (unsigned)cs) + kc, ib = ia;  // LDS indices of the pair
             for (int b0 = h; b0 < h + len; b0 += 64) {
                 const int nb = min(64, h + len - b0);
                 const int qlh = lohi[b0 + min(lane, nb - 1)];
@@ -440,6 +423,13 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
                     todo &= todo - 1ull;
                     return en;
                 };
+                // Every step writes the current pair back (its column values plus what the previous
+                // step added) and reads the pair of this step's z -- the same pair again when z did not
+                // change or the lane contributes nothing.  The same LDS accesses on every step and no
+                // branch: the wait for a pair's values comes a whole step after their read, at the next
+                // write-back, and the record loads of the next rays are never held up behind a read
+                // issued late in a step.  (A write-back followed by the read of an overlapping pair is
+                // seen by that read: one wave's LDS accesses complete in order.)
                 auto step = [&](const Rec& c) {
                     const bool act = kin && k >= (c.lh & 0xffff) && k <= (c.lh >> 16);
                     const double W = fma((double)k, c.dW, c.W0);
@@ -448,36 +438,54 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
                     const float fw = (float)(W - fj);
                     const float v0 = m.sample(fma((double)k, c.ds, c.s0), c.cv, Mode::kAux ? c.ax : 0);
                     const float v = act ? v0 : 0.0f;
-                    // the pair of z entries stays in registers until z changes
-                    if (v != 0.0f && j0 != jc) {
-                        col_put(col, ia, ib, preA, accA, preB, accB);
-                        jc = j0;
-                        zlo = min(zlo, jc);
-                        zhi = max(zhi, jc + 1);
-                        col_get(col, jc, k, nw, cs, ia, ib, preA, preB);
-                        accA = 0.0f;
-                        accB = 0.0f;
-                    }
-                    accA = fmaf(1.0f - fw, v, accA);
-                    accB = fmaf(fw, v, accB);
+                    col[ia] = preA + accA;
+                    col[ib] = preB + accB;
+                    const bool move = v != 0.0f && j0 != jc;
+                    jc = move ? j0 : jc;
+                    zlo = move ? min(zlo, j0) : zlo;
+                    zhi = move ? max(zhi, j0 + 1) : zhi;
+                    ia = move ? (int)__umul24((unsigned)col_row(j0, nw), (unsigned)cs) + kc : ia;
+                    ib = move ? (int)__umul24((unsigned)col_row(j0 + 1, nw), (unsigned)cs) + kc : ib;
+                    preA = col[ia];
+                    preB = col[ib];
+                    accA = (1.0f - fw) * v;
+                    accB = fw * v;
                 };
+                // A compiler-only barrier after each prefetch keeps the loads where they are: the
+                // column accesses of step() are float and the records double / int, so without it the
+                // compiler may sink the loads to their first use and wait on them there.
                 int e = next(0);
                 Rec ra = load(e);
+                asm volatile("" ::: "memory");
+                {   // a step without a ray (write the pair back, read it again): the LDS accesses
+                    // entering the loop then follow the same pattern as from one step to the next,
+                    // so the waits at the top of the loop are as exact as inside it
+                    typedef __attribute__((address_space(3))) float lds_float;
+                    volatile lds_float* vc = (volatile lds_float*)col;
+                    vc[ia] = preA + accA;
+                    vc[ib] = preB + accB;
+                    preA = vc[ia];
+                    preB = vc[ib];
+                    accA = 0.0f;
+                    accB = 0.0f;
+                }
                 while (true) {
                     bool more = todo != 0ull;
                     e = next(e);
                     const Rec rb = load(e);
+                    asm volatile("" ::: "memory");
                     step(ra);
                     if (!more) break;
                     more = todo != 0ull;
                     e = next(e);
                     ra = load(e);
+                    asm volatile("" ::: "memory");
                     step(rb);
                     if (!more) break;
                 }
             }
-            // threads past the line's last plane (k >= cs possible) never leave the initial state
-            if (kin) col_put(col, ia, ib, preA, accA, preB, accB);
+            col[ia] = preA + accA;
+            col[ib] = preB + accB;
             touched = touched || jc != kNoEntry;  // jc may be an out-of-grid entry after writes
             // no barrier between runs: a run writes only the thread's own column; other threads read
             // the columns only in a flush, whose first barrier follows every wave's last write here
