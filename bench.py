@@ -452,14 +452,17 @@ def main():
     lm = lm_inputs = None
     if args.only in (None, "lm"):
         lm, lm_inputs = lm_leg(args, pp, C, dev)
-    if args.only == "lm":
+    if args.only is not None:
         # a plain device copy of known size (1 GiB read + 1 GiB written), so hardware byte
-        # counters collected on this run can be scaled to bytes
+        # counters collected on a profiling run can be scaled to bytes
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"lm": lm, "calibration_copy_bytes": src.numel() * 4}))
+        extra["calibration_copy_bytes"] = src.numel() * 4
+        del src, dst
+    if args.only == "lm":
+        print(json.dumps({"lm": lm, **extra}))
         return
     if args.only in (None, "sino") and not args.no_sino:
         extra["sinogram"] = sino_leg(args, pp, C, dev)

@@ -80,8 +80,8 @@ void cheb_powers(F f, int N, double* c) {
 
 // The device's tof_poly, evaluated on the host in the same float32 operations.
 float tof_poly_host(float x, const TofK& t) {
-    const float y = std::fabs(x);
-    const float s1 = std::fmaf(y * y, t.pa1, t.pb1), s2 = std::fmaf(y, t.pa2, t.pb2);
+    const float y = std::fabs(x), u = y * t.pq1;
+    const float s1 = std::fmaf(u, u, -1.0f), s2 = std::fmaf(y, t.pa2, t.pb2);
     float a = t.pc[kPolyCentral], b = t.pt[kPolyTail];
     for (int i = kPolyCentral - 1; i >= 0; --i) {
         a = std::fmaf(a, s1, t.pc[i]);
@@ -107,8 +107,7 @@ void fit_tof_poly(TofK& t, double sig, double ns, double bw) {
     for (int i = 0; i <= kPolyTail; ++i) t.pt[i] = (float)c2[i];
     t.pk1 = (float)k1;
     t.pk2 = (float)k2;
-    t.pa1 = (float)(2.0 / (k1 * k1));
-    t.pb1 = -1.0f;
+    t.pq1 = (float)(std::sqrt(2.0) / k1);
     t.pa2 = (float)(2.0 / (k2 - k1));
     t.pb2 = (float)(-(k1 + k2) / (k2 - k1));
     const double peak = w(0.0);

@@ -50,7 +50,8 @@ struct TofK {
     // poly == 0 when the fit missed its error bound (the erf form is used then).
     int poly;
     float pk1, pk2;            // pieces: y < pk1 central, pk1 <= y < pk2 tail, 0 beyond
-    float pa1, pb1, pa2, pb2;  // central variable y^2 pa1 + pb1, tail variable y pa2 + pb2 (both in [-1, 1])
+    float pq1;                 // central variable (y pq1)^2 - 1 = 2 y^2 / k1^2 - 1 (pq1 = sqrt(2) / k1)
+    float pa2, pb2;            // tail variable y pa2 + pb2; both variables in [-1, 1] on their piece
     float pc[kPolyCentral + 1];  // central polynomial, pc[i] the coefficient of the i-th power
     float pt[kPolyTail + 1];     // tail polynomial
 };
@@ -382,8 +383,8 @@ __device__ __forceinline__ float tof_lut(double x, const TofK& t) {
 // the float32 evaluation against the exact weight and falls back to the erf form if it misses
 // its bound.
 __device__ __forceinline__ float tof_poly(float x, const TofK& t) {
-    const float y = fabsf(x);
-    const float s1 = fmaf(y * y, t.pa1, t.pb1), s2 = fmaf(y, t.pa2, t.pb2);
+    const float y = fabsf(x), u = y * t.pq1;
+    const float s1 = fmaf(u, u, -1.0f), s2 = fmaf(y, t.pa2, t.pb2);
     float a = t.pc[kPolyCentral], b = t.pt[kPolyTail];
 #pragma unroll
     for (int i = kPolyCentral - 1; i >= 0; --i) {

@@ -398,7 +398,18 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
             // the unused last column (cs - 1 is never a plane of a sheet line), whose spare-row entry
             // takes their (zero) write-backs
             const int kc = kin ? k : cs - 1;
-            int ia = (int)__umul24((unsigned)nw, (unsigned)cs) + kc, ib = ia;  // LDS indices of the pair
+            // byte offsets into the column buffer of the pair's two entries (rows col_row(jc) and
+            // col_row(jc + 1)), recomputed from jc on every step
+            typedef __attribute__((address_space(3))) char lds_char;
+            typedef __attribute__((address_space(3))) float lds_float;
+            lds_char* colb = (lds_char*)col;
+            // LDS byte addresses (the buffer's own address folded into the per-thread term, so that
+            // an address is one multiply-add of the row)
+            const unsigned cs4 = 4u * (unsigned)cs;
+            const unsigned kc4 = 4u * (unsigned)kc + (unsigned)(uintptr_t)colb;
+            auto row_off = [&](int j) { return (int)(__umul24((unsigned)col_row(j, nw), cs4) + kc4); };
+            auto at = [&](int addr) { return (lds_float*)(uintptr_t)(unsigned)addr; };
+            int ia = row_off(nw), ib = ia;
             for (int b0 = h; b0 < h + len; b0 += 64) {
                 const int nb = min(64, h + len - b0);
                 const int qlh = lohi[b0 + min(lane, nb - 1)];
@@ -438,16 +449,16 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
                     const float fw = (float)(W - fj);
                     const float v0 = m.sample(fma((double)k, c.ds, c.s0), c.cv, Mode::kAux ? c.ax : 0);
                     const float v = act ? v0 : 0.0f;
-                    col[ia] = preA + accA;
-                    col[ib] = preB + accB;
+                    *at(ia) = preA + accA;
+                    *at(ib) = preB + accB;
                     const bool move = v != 0.0f && j0 != jc;
                     jc = move ? j0 : jc;
                     zlo = move ? min(zlo, j0) : zlo;
                     zhi = move ? max(zhi, j0 + 1) : zhi;
-                    ia = move ? (int)__umul24((unsigned)col_row(j0, nw), (unsigned)cs) + kc : ia;
-                    ib = move ? (int)__umul24((unsigned)col_row(j0 + 1, nw), (unsigned)cs) + kc : ib;
-                    preA = col[ia];
-                    preB = col[ib];
+                    ia = row_off(jc);
+                    ib = row_off(jc + 1);
+                    preA = *at(ia);
+                    preB = *at(ib);
                     accA = (1.0f - fw) * v;
                     accB = fw * v;
                 };
@@ -460,12 +471,12 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
                 {   // a step without a ray (write the pair back, read it again): the LDS accesses
                     // entering the loop then follow the same pattern as from one step to the next,
                     // so the waits at the top of the loop are as exact as inside it
-                    typedef __attribute__((address_space(3))) float lds_float;
-                    volatile lds_float* vc = (volatile lds_float*)col;
-                    vc[ia] = preA + accA;
-                    vc[ib] = preB + accB;
-                    preA = vc[ia];
-                    preB = vc[ib];
+                    volatile lds_float* va = at(ia);
+                    volatile lds_float* vb = at(ib);
+                    *va = preA + accA;
+                    *vb = preB + accB;
+                    preA = *va;
+                    preB = *vb;
                     accA = 0.0f;
                     accB = 0.0f;
                 }
@@ -484,8 +495,8 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
                     if (!more) break;
                 }
             }
-            col[ia] = preA + accA;
-            col[ib] = preB + accB;
+            *at(ia) = preA + accA;
+            *at(ib) = preB + accB;
             touched = touched || jc != kNoEntry;  // jc may be an out-of-grid entry after writes
             // no barrier between runs: a run writes only the thread's own column; other threads read
             // the columns only in a flush, whose first barrier follows every wave's last write here
