@@ -122,7 +122,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the OSEM serving leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=25.0, help="calibrated oracle time for the CPU baseline")
-    ap.add_argument("--only", default=None, help="profiling helper: lm | sino | sino_osem | serve")
+    ap.add_argument("--only", default=None, help="profiling helper: lm | sino | sino_osem | res | serve")
     ap.add_argument("--serve-requests", type=int, default=None, help="requests in the serving leg (default 256)")
     ap.add_argument("--no-res", action="store_true", help="serving leg without the resolution model")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
@@ -251,8 +251,9 @@ def lm_leg(args, pp, C, dev):
 
 def resmodel_leg(args, pp, C, dev):
     """The resolution model's separable Gaussian (pp_gauss3d, 4.5 mm FWHM) on the clinical grid and
-    the 128 x 128 x 64 serving grid: 3 passes, each reading and writing the image once (8 B per
-    voxel per pass of algorithmic HBM traffic)."""
+    the 128 x 128 x 64 serving grid.  Two byte counts: the three separable passes, each reading and
+    writing the image (24 B per voxel), and the image read and written once (8 B per voxel, what
+    any implementation must move)."""
     import torch
 
     from paper_2212_12519_amd.osem import RES_FWHM_MM
@@ -265,9 +266,12 @@ def resmodel_leg(args, pp, C, dev):
         fwhm = (RES_FWHM_MM,) * 3
         _, t, _ = timed_pairs(lambda: pp.pp_gauss3d(src, dst, tmp, G, fwhm), lambda: None, lambda: None, 20, 3)
         alg = 3 * 8 * src.numel()
+        once = 8 * src.numel()
         out[name] = {"t_ms": t, "alg_bytes": alg, "alg_gbs": alg / (t * 1e-3) / 1e9,
-                     "hbm_frac": alg / (t * 1e-3) / 1e9 / HBM_PEAK_GBS}
-        log(f"resolution model {name}: {t * 1e3:.1f} us, {alg / (t * 1e-3) / 1e9:.0f} GB/s")
+                     "hbm_frac": alg / (t * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "compulsory_bytes": once, "compulsory_frac": once / (t * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        log(f"resolution model {name}: {t * 1e3:.1f} us, {alg / (t * 1e-3) / 1e9:.0f} GB/s (3 passes), "
+            f"{once / (t * 1e-3) / 1e9:.0f} GB/s (image read + written once)")
     return out
 
 
@@ -473,7 +477,11 @@ def main():
         return
     if args.only is None:
         extra["autograd"] = autograd_leg(args, pp, C, dev, lm_inputs)
+    if args.only in (None, "res"):
         extra["resolution_model"] = resmodel_leg(args, pp, C, dev)
+    if args.only == "res":
+        print(json.dumps(extra))
+        return
     if args.only in (None, "serve") and not args.no_serve:
         from paper_2212_12519_amd import serve
 

@@ -182,7 +182,7 @@ int make_gauss(const float* fwhm, const GeomK& g, GaussK& k) {
         for (int i = 0; i < 2 * kGaussMaxR + 1; ++i) k.w[a][i] = 0.0f;
         if (f == 0.0) {
             k.r[a] = 0;
-            k.w[a][0] = 1.0f;
+            k.w[a][kGaussMaxR] = 1.0f;
             continue;
         }
         const double sig = f / (2.0 * std::sqrt(2.0 * std::log(2.0))) / g.h[a];
@@ -191,7 +191,7 @@ int make_gauss(const float* fwhm, const GeomK& g, GaussK& k) {
         const int r = (int)rr;
         double w[2 * kGaussMaxR + 1], sum = 0.0;
         for (int i = -r; i <= r; ++i) sum += (w[i + r] = std::exp(-(double)i * i / (2.0 * sig * sig)));
-        for (int i = 0; i <= 2 * r; ++i) k.w[a][i] = (float)(w[i] / sum);
+        for (int i = 0; i <= 2 * r; ++i) k.w[a][kGaussMaxR - r + i] = (float)(w[i] / sum);
         k.r[a] = r;
     }
     return PP_OK;

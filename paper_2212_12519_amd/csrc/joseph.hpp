@@ -58,7 +58,8 @@ struct TofK {
 
 constexpr float kErfC = 1.2011224087864498f;  // sqrt(log2(e)): scale of the erf argument (erf_scaled)
 
-// Resolution-model blur taps per axis: w[a][i + r[a]] for |i| <= r[a].
+// Resolution-model blur taps per axis: tap i of axis a at w[a][i + kGaussMaxR] (centred, so that a
+// tap's offset is a compile-time index when i is), 0 for |i| > r[a].
 constexpr int kGaussMaxR = 31;
 struct GaussK {
     int r[3];
