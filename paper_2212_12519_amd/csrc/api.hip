@@ -548,10 +548,9 @@ int pp_osem_update_batched(pp_frame_desc_t* d_slots, int32_t n_slots, const pp_i
     if (n_slots == 0) return PP_OK;
     if (!d_slots) return PP_EINVAL_PTR;
     const int64_t n_vox = (int64_t)g.n[0] * g.n[1] * g.n[2];
-    const int64_t total = (int64_t)n_slots * n_vox;
-    int64_t blocks = (total + 255) / 256;
+    int64_t blocks = (n_vox + 255) / 256;  // per slot
     const int cus = device_cus();
-    const int64_t cap = (int64_t)cus * 16;
+    const int64_t cap = (int64_t)cus * 4;
     if (blocks > cap) blocks = cap;
     hipStream_t s = as_stream(stream);
     // slots without the model: plain update; slots with it: the blur passes with the fused update;

@@ -103,18 +103,17 @@ __global__ void __launch_bounds__(kSheetBlock) k_osem_accumulate(const pp_frame_
     }
 }
 
-__global__ void __launch_bounds__(kOsemBlock) k_osem_update(const pp_frame_desc_t* __restrict__ slots, int n_slots,
-                                                            int64_t n_vox) {
-    const int64_t total = (int64_t)n_slots * n_vox;
+// grid: (blocks per slot, slots); a workgroup of a slot that is not live (or has the resolution
+// model: blur.hip updates it) returns at once, so empty slots of a large table cost almost nothing
+__global__ void __launch_bounds__(kOsemBlock) k_osem_update(const pp_frame_desc_t* __restrict__ slots, int64_t n_vox) {
+    const pp_frame_desc_t& s = slots[blockIdx.y];
+    if (!slot_live(s) || s.x_fwd != nullptr) return;  // block-uniform
+    const float scale = 1.0f / (float)s.n_sub;
     const int64_t stride = (int64_t)gridDim.x * kOsemBlock;
-    for (int64_t i = (int64_t)blockIdx.x * kOsemBlock + threadIdx.x; i < total; i += stride) {
-        const int si = (int)(i / n_vox);
-        const int64_t v = i - (int64_t)si * n_vox;
-        const pp_frame_desc_t& s = slots[si];
-        if (!slot_live(s) || s.x_fwd != nullptr) continue;  // resolution-model slots: blur.hip
+    for (int64_t v = (int64_t)blockIdx.x * kOsemBlock + threadIdx.x; v < n_vox; v += stride) {
         const float sv = s.sens[v];
         const float a = s.acc[v];
-        s.x[v] = (sv > 0.0f) ? s.x[v] * a / (sv / (float)s.n_sub) : 0.0f;
+        s.x[v] = (sv > 0.0f) ? s.x[v] * a / (sv * scale) : 0.0f;
         s.acc[v] = 0.0f;
     }
 }
@@ -168,8 +167,15 @@ hipError_t launch_osem_accumulate(const pp_frame_desc_t* slots, int n_slots, con
 }
 
 hipError_t launch_osem_update(pp_frame_desc_t* slots, int n_slots, int64_t n_vox, int n_blocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_osem_update, dim3(n_blocks), dim3(kOsemBlock), 0, s, slots, n_slots, n_vox);
-    return hipGetLastError();
+    constexpr int kMaxY = 65535;  // grid limit along y: tables beyond it go in several launches
+    for (int first = 0; first < n_slots; first += kMaxY) {
+        const int count = (n_slots - first < kMaxY) ? (n_slots - first) : kMaxY;
+        hipLaunchKernelGGL(k_osem_update, dim3((unsigned)n_blocks, (unsigned)count), dim3(kOsemBlock), 0, s,
+                           slots + first, n_vox);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_osem_advance(pp_frame_desc_t* slots, int n_slots, hipStream_t s) {

@@ -110,17 +110,22 @@ class OsemServer:
             self.grids[g] = _GridState(g, sens, O.SlotTable(max_slots, self.device), list(range(max_slots)))
         self.in_use = 0
         self.rejected = []
+        self.waited_budget, self.waited_slot = set(), set()  # requests admission deferred, by cause
+        self.peak_bytes = 0
+        self.peak_live = 0
         load()
 
     def _admit(self, req, now):
         st = self.grids[as_geom(req.grid)]
-        if not st.free:
-            return False
         nbytes = frame_footprint(req.xstart.shape[0], st.geom.n_vox, self.res_fwhm is not None)
         if nbytes > self.budget:
             self.rejected.append(req.rid)  # can never fit: refuse instead of blocking the queue
             return True
+        if not st.free:
+            self.waited_slot.add(req.rid)
+            return False
         if self.in_use + nbytes > self.budget:
+            self.waited_budget.add(req.rid)
             return False
         slot = st.free.pop(0)
         xs, xe, tb = O.prepare_frame(req.xstart, req.xend, req.tof_bin, st.geom, self.tof, req.n_sub)
@@ -133,6 +138,8 @@ class OsemServer:
         st.live[slot] = _Live(req, slot, (xs, xe, tb, acc, xf, tmp), x, now, nbytes)
         st.dirty = True
         self.in_use += nbytes
+        self.peak_bytes = max(self.peak_bytes, self.in_use)
+        self.peak_live = max(self.peak_live, sum(len(g.live) for g in self.grids.values()))
         return True
 
     def _admit_queue(self, queue, now):
@@ -266,15 +273,24 @@ def make_trace(pool, grids, n_requests, seed, events_range, rate_hz, n_iter=3, n
     return out
 
 
-# A step of a few average frames (5M events each, 8 subsets) already fills the GPU; more slots
-# only make admitted frames share the GPU longer (higher latency, same throughput).
+# Slots per grid of the latency-oriented configuration: a step of a few average frames (5M events
+# each, 8 subsets) already fills the GPU, so more slots only make admitted frames share the GPU
+# longer (higher latency, the same throughput).  The budget-bound configuration of the benchmark
+# gives each grid BUDGET_SLOTS slots, so that the HBM budget, not the table, limits admission.
 SERVE_SLOTS = 6
+BUDGET_SLOTS = 128
 
 
 def bench_leg(args, log):
-    """Serving measurement for bench.py: 256 Poisson-arriving TOF LM-OSEM frames (3 it x 8 subsets,
+    """Serving measurement for bench.py: Poisson-arriving TOF LM-OSEM frames (3 it x 8 subsets,
     0.5M-20M events log-uniform, 128x128x64 or 215x215x71 grid), continuous batching vs sequential
-    plain calls on the same trace.  Returns a dict for the benchmark's JSON line."""
+    plain calls on the same traces.
+      * overload: 256 requests at 3x the sequential service rate (frames/s = capacity), batched with
+        SERVE_SLOTS slots per grid, with BUDGET_SLOTS slots per grid (the 32 GB HBM budget binds),
+        sequential plain calls on presorted events and on the events as given (first 64);
+      * load 1.25x and 0.5x of the sequential service rate, 128 requests each, batched and
+        sequential (presorted): latency is service time plus queueing.
+    Returns a dict for the benchmark's JSON line."""
     from synth import configs as C
     from synth import generate_tof_lm_events
     import paper_2212_12519_amd as pp
@@ -293,9 +309,33 @@ def bench_leg(args, log):
     del lxs, lxe
     torch.cuda.empty_cache()
     n_req = int(getattr(args, "serve_requests", None) or C.N_REQUESTS)
-    server = OsemServer(T, sens, max_slots=SERVE_SLOTS, hbm_budget=32e9, steps_per_tick=1, use_graph=True,
+    budget = 32e9
+
+    def server(slots):
+        sv = OsemServer(T, sens, max_slots=slots, hbm_budget=budget, steps_per_tick=1, use_graph=True,
                         res_fwhm=res)
-    server.run(make_trace(pool, grids, 4, C.SEED_SERVE + 2, (500_000, 600_000), 1e9))  # warm-up and capture
+        sv.run(make_trace(pool, grids, 4, C.SEED_SERVE + 2, (500_000, 600_000), 1e9))  # warm-up and capture
+        return sv
+
+    def batched(sv, trace, label):
+        sv.waited_budget, sv.waited_slot, sv.peak_bytes, sv.peak_live = set(), set(), 0, 0
+        out = sv.run(trace)
+        st = latency_stats(out, 0.0)
+        st.update({"slots_per_grid": sv.grids[grids[0]].table.capacity, "peak_live_frames": sv.peak_live,
+                   "peak_admitted_gb": sv.peak_bytes / 1e9, "waited_for_hbm_budget": len(sv.waited_budget),
+                   "waited_for_slot": len(sv.waited_slot), "rejected": len(sv.rejected)})
+        log(f"serving {label}: p50 {st['p50_s']:.3f} s p99 {st['p99_s']:.3f} s, {st['frames_per_s']:.2f} frames/s, "
+            f"peak {sv.peak_live} frames / {sv.peak_bytes / 1e9:.1f} GB, waited budget {len(sv.waited_budget)} "
+            f"slot {len(sv.waited_slot)}")
+        return out, st
+
+    def sequential(trace, label, presorted=True):
+        out = run_sequential(trace, T, sens, presorted=presorted, res_fwhm=res)
+        st = latency_stats(out, 0.0)
+        log(f"serving {label}: p50 {st['p50_s']:.3f} s p99 {st['p99_s']:.3f} s, {st['frames_per_s']:.2f} frames/s")
+        return out, st
+
+    sv = server(SERVE_SLOTS)
     # calibrate the sequential (presorted) service time on a burst from the same distribution
     cal = make_trace(pool, grids, 16, C.SEED_SERVE + 1, C.SERVE_EVENTS_RANGE, 1e9)
     run_sequential(cal[:2], T, sens, res_fwhm=res)
@@ -306,26 +346,34 @@ def bench_leg(args, log):
     rate = 3.0 / service
     trace = make_trace(pool, grids, n_req, C.SEED_SERVE, C.SERVE_EVENTS_RANGE, rate)
     log(f"serving: {n_req} requests, sequential service ~{service * 1e3:.0f} ms/frame, arrival rate {rate:.2f}/s")
-    res_b = server.run(trace)
-    sb = latency_stats(res_b, 0.0)
-    log(f"serving batched: p50 {sb['p50_s']:.3f} s p99 {sb['p99_s']:.3f} s, {sb['frames_per_s']:.2f} frames/s")
-    res_s = run_sequential(trace, T, sens, res_fwhm=res)
-    ss = latency_stats(res_s, 0.0)
-    log(f"serving sequential presorted: p50 {ss['p50_s']:.3f} s p99 {ss['p99_s']:.3f} s, "
-        f"{ss['frames_per_s']:.2f} frames/s")
+    res_b, sb = batched(sv, trace, f"batched ({SERVE_SLOTS} slots/grid)")
+    res_s, ss = sequential(trace, "sequential presorted")
     n_u = min(n_req, 64)
-    res_u = run_sequential(trace[:n_u], T, sens, presorted=False, res_fwhm=res)
-    su = latency_stats(res_u, 0.0)
-    log(f"serving sequential as-given (first {n_u}): p50 {su['p50_s']:.3f} s p99 {su['p99_s']:.3f} s, "
-        f"{su['frames_per_s']:.2f} frames/s")
+    _, su = sequential(trace[:n_u], f"sequential as-given (first {n_u})", presorted=False)
     sb_u = latency_stats([r for r in res_b if r.rid < n_u], 0.0)
     by_id = {r.rid: r.image for r in res_s}
     diffs = [float(torch.linalg.vector_norm(r.image - by_id[r.rid]) / torch.linalg.vector_norm(by_id[r.rid]))
              for r in res_b[:16]]
+    del res_b, res_s
+    # the same overload trace with the HBM budget as the binding limit
+    sv_big = server(BUDGET_SLOTS)
+    _, sbb = batched(sv_big, trace, f"batched ({BUDGET_SLOTS} slots/grid, budget-bound)")
+    del sv_big
+    torch.cuda.empty_cache()
+    # latency at loads below and just above the sequential service rate
+    loads = {}
+    n_load = max(8, n_req // 2)
+    for load_x in (1.25, 0.5):
+        tr = make_trace(pool, grids, n_load, C.SEED_SERVE + 3, C.SERVE_EVENTS_RANGE, load_x / service)
+        _, b_st = batched(sv, tr, f"batched at {load_x}x load")
+        _, s_st = sequential(tr, f"sequential presorted at {load_x}x load")
+        loads[f"{load_x}x"] = {"requests": n_load, "arrival_rate_hz": load_x / service, "batched": b_st,
+                               "sequential_plain_presorted": s_st}
     return {"requests": n_req, "arrival_rate_hz": rate, "offered_load_vs_sequential": 3.0, "iterations": 3,
-            "subsets": 8, "resolution_model_fwhm_mm": res, "batched": sb, "sequential_plain_presorted": ss,
+            "subsets": 8, "resolution_model_fwhm_mm": res, "sequential_service_s": service, "batched": sb,
+            "batched_budget_bound": sbb, "sequential_plain_presorted": ss,
             "sequential_plain_as_given": dict(su, note=f"first {n_u} requests of the same trace"),
             "batched_first_requests": sb_u,
             "speedup_frames_per_s_vs_plain_presorted": sb["frames_per_s"] / ss["frames_per_s"],
             "max_rel_l2_batched_vs_plain": max(diffs) if diffs else None,
-            "hbm_budget_gb": 32.0, "rejected": len(server.rejected)}
+            "hbm_budget_gb": budget / 1e9, "load_sweep": loads}
