@@ -35,35 +35,55 @@ HBM_PEAK_GBS = 8000.0
 STEP_SOURCES = ("api.hip", "joseph.hpp", "launch.hpp", "presort.hip", "projectors.hip", "sheet.hpp")
 
 
-def kernel_sources_sha():
-    """sha256 over the sources of the listmode step's kernels."""
+# the sources of the clinical sinogram legs' kernels
+SINO_SOURCES = ("api.hip", "joseph.hpp", "launch.hpp", "projectors.hip", "sheet.hpp")
+
+
+def kernel_sources_sha(sources=STEP_SOURCES):
+    """sha256 over the given kernel sources (default: the listmode step's)."""
     import hashlib
 
     d = os.path.join(ROOT, "paper_2212_12519_amd", "csrc")
     h = hashlib.sha256()
-    for f in STEP_SOURCES:
+    for f in sources:
         h.update(f.encode())
         h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()
 
 
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "tof_lm_40M_traffic.json")
+SINO_TRAFFIC_JSON = os.path.join(ROOT, "profiles", "clinical_sino_traffic.json")
+# the sinogram legs' device kernels
+SINO_KERNELS = {"nontof_fwd": "ppmi::k_fwd", "nontof_back": "ppmi::k_back_runs<ppmi::ModeNonTof>",
+                "tof_fwd": "ppmi::k_fwd_tof_sino<false>",
+                "tof_back": "ppmi::k_back_runs<ppmi::ModeTofSino<false, false> >"}
+
+
+def traffic_record(which):
+    """(path, sources) of a traffic record: "lm" (the listmode step) or "sino" (the sinogram legs)."""
+    return (TRAFFIC_JSON, STEP_SOURCES) if which == "lm" else (SINO_TRAFFIC_JSON, SINO_SOURCES)
+
+
+def profiled_kernel_bytes(which, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter record `which`, or None when the
+    record is missing or the kernel sources changed since the counters were taken."""
+    path, sources = traffic_record(which)
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if kernel_sources_sha(sources) != rec.get("source_sha256"):
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return k["traffic_bytes"] if k else None
 # the device kernel each timed entry point of the listmode step launches
 KERNEL_OF = {"pp_lm_presort": "ppmi::k_lm_keys", "pp_fwd_tof_lm": "ppmi::k_fwd_tof_lm<2, false>",
              "pp_back_tof_lm": "ppmi::k_back_runs<ppmi::ModeTofLm<2, false> >"}
 
 
 def profiled_traffic(entry):
-    """HBM bytes per launch of the kernel behind `entry` from the committed counter profile, or
-    None when the kernel sources changed since the counters were taken."""
-    try:
-        rec = json.load(open(TRAFFIC_JSON))
-    except (OSError, ValueError):
-        return None
-    if kernel_sources_sha() != rec.get("source_sha256"):
-        return None
-    k = rec.get("kernels", {}).get(KERNEL_OF.get(entry, ""))
-    return k["traffic_bytes"] if k else None
+    """HBM bytes per launch of the listmode-step kernel behind `entry` (see profiled_kernel_bytes)."""
+    return profiled_kernel_bytes("lm", KERNEL_OF.get(entry, ""))
 
 
 def kernel_short_name(name):
@@ -74,10 +94,11 @@ def kernel_short_name(name):
     return name.split("(", 1)[0]
 
 
-def write_traffic(fetch_csv, write_csv, copy_bytes=1 << 30):
+def write_traffic(fetch_csv, write_csv, which="lm", copy_bytes=1 << 30):
     """Turn two rocprofv3 counter-collection CSVs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) of
-    `bench.py --only lm` into the traffic record: per kernel of the step the mean KiB per
-    launch, scaled to bytes by what the same counters read for the run's 1 GiB device copy."""
+    `bench.py --only lm` (which="lm") or `--only sino` (which="sino") into the traffic record: per
+    library kernel the mean KiB per launch, scaled to bytes by what the same counters read for the
+    run's 1 GiB device copy."""
     import csv
 
     def per_kernel(path, counter):
@@ -95,15 +116,16 @@ def write_traffic(fetch_csv, write_csv, copy_bytes=1 << 30):
     cf, cw = max(max(fe[k]) for k in copy), max(max(wr[k]) for k in copy)
     fs, ws = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
     kernels = {}
-    for k in KERNEL_OF.values():
-        if k in fe and k in wr:
+    for k in sorted(set(fe) & set(wr)):
+        if k.startswith("ppmi::"):
             f, w = sum(fe[k]) / len(fe[k]), sum(wr[k]) / len(wr[k])
             kernels[k] = {"fetch_kib": f, "write_kib": w, "launches": len(fe[k]),
                           "traffic_bytes": 1024.0 * (f * fs + w * ws)}
+    path, sources = traffic_record(which)
     rec = {"kernels": kernels, "copy_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
-           "fetch_scale": fs, "write_scale": ws, "source_sha256": kernel_sources_sha(),
-           "sources": ["paper_2212_12519_amd/csrc/" + f for f in STEP_SOURCES]}
-    with open(TRAFFIC_JSON, "w") as fh:
+           "fetch_scale": fs, "write_scale": ws, "source_sha256": kernel_sources_sha(sources),
+           "sources": ["paper_2212_12519_amd/csrc/" + f for f in sources]}
+    with open(path, "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec, indent=1))
 
@@ -125,8 +147,9 @@ def parse():
     ap.add_argument("--only", default=None, help="profiling helper: lm | sino | sino_osem | res | serve")
     ap.add_argument("--serve-requests", type=int, default=None, help="requests in the serving leg (default 256)")
     ap.add_argument("--no-res", action="store_true", help="serving leg without the resolution model")
-    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
-                    help="no GPU work: write the traffic record from two rocprofv3 counter CSVs of --only lm")
+    ap.add_argument("--write-traffic", nargs="+", metavar="ARG", default=None,
+                    help="no GPU work: FETCH_CSV WRITE_CSV [lm|sino] -- write the traffic record from two "
+                         "rocprofv3 counter CSVs of --only lm (default) or --only sino")
     return ap.parse_args()
 
 
@@ -320,10 +343,19 @@ def sino_leg(args, pp, C, dev):
     wall, tf, tb = timed_pairs(lambda: pp.pp_fwd(xs, xe, G, img, p), lambda: pp.pp_back(xs, xe, G, bimg, p),
                                lambda: pp.pp_fill(bimg, 0.0), reps, 1)
     alg = (24 + 4) * n + 16 * n_samples
+
+    def measured(key, t_ms):
+        b = profiled_kernel_bytes("sino", SINO_KERNELS[key])
+        return (None, None) if b is None else (b / (t_ms * 1e-3) / 1e9, b / (t_ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+
+    mf, mff = measured("nontof_fwd", tf)
+    mb, mbf = measured("nontof_back", tb)
     out["nontof"] = {"n_lors": n, "t_fwd_ms": tf, "t_back_ms": tb, "lors_per_s_fwd_back": n / ((tf + tb) * 1e-3),
                      "samples_per_lor": n_samples / n, "fwd_alg_gbs": alg / (tf * 1e-3) / 1e9,
-                     "fwd_hbm_frac": alg / (tf * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "back_alg_gbs": alg / (tb * 1e-3) / 1e9}
+                     "fwd_alg_frac": alg / (tf * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "fwd_hbm_measured_gbs": mf, "fwd_hbm_measured_frac": mff,
+                     "back_alg_gbs": alg / (tb * 1e-3) / 1e9, "back_hbm_measured_gbs": mb,
+                     "back_hbm_measured_frac": mbf}
     log(f"sino non-TOF: fwd {tf:.1f} ms back {tb:.1f} ms")
     del p
     tofs = C.TOF_CLIN
@@ -333,9 +365,13 @@ def sino_leg(args, pp, C, dev):
                                lambda: pp.pp_back_tof_sino(xs, xe, G, T, bimg, pt),
                                lambda: pp.pp_fill(bimg, 0.0), reps, 1)
     alg_t = (24 + 4 * tofs.n_bins) * n + 16 * n_samples
+    mf, mff = measured("tof_fwd", tf)
+    mb, mbf = measured("tof_back", tb)
     out["tof_sino"] = {"n_lors": n, "n_bins": tofs.n_bins, "t_fwd_ms": tf, "t_back_ms": tb,
                        "lors_per_s_fwd_back": n / ((tf + tb) * 1e-3), "fwd_alg_gbs": alg_t / (tf * 1e-3) / 1e9,
-                       "fwd_hbm_frac": alg_t / (tf * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                       "fwd_alg_frac": alg_t / (tf * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "fwd_hbm_measured_gbs": mf, "fwd_hbm_measured_frac": mff,
+                       "back_hbm_measured_gbs": mb, "back_hbm_measured_frac": mbf}
     log(f"sino TOF: fwd {tf:.1f} ms back {tb:.1f} ms")
     del pt, xs, xe
     torch.cuda.empty_cache()
@@ -437,6 +473,8 @@ def sino_osem_leg(args, pp, C, dev):
 def main():
     args = parse()
     if args.write_traffic:
+        if len(args.write_traffic) not in (2, 3) or args.write_traffic[2:] not in ([], ["lm"], ["sino"]):
+            raise SystemExit("--write-traffic FETCH_CSV WRITE_CSV [lm|sino]")
         write_traffic(*args.write_traffic)
         return
     if args.gpus != 1:

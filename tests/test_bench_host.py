@@ -51,3 +51,22 @@ def test_traffic_record_scales_counters_by_the_copy(tmp_path, monkeypatch):
     assert k["launches"] == 2
     assert k["traffic_bytes"] == 1024.0 * (1000.0 * 2.0 + 500.0 * 1.0)
     assert rec["source_sha256"] == bench.kernel_sources_sha()
+
+
+def test_sino_traffic_record_and_lookup(tmp_path, monkeypatch):
+    """The sinogram record keeps every library kernel of the counter files (not the copy), and a
+    lookup returns its bytes while the sinogram kernels' sources are unchanged, None otherwise."""
+    bench = load_bench()
+    monkeypatch.setattr(bench, "SINO_TRAFFIC_JSON", str(tmp_path / "sino.json"))
+    fwd = "void " + bench.SINO_KERNELS["tof_fwd"] + "(ppmi::RaySrc, ...)"
+    copy = "__amd_rocclr_copyBuffer(unsigned char*, ...)"
+    fetch, write = tmp_path / "f.csv", tmp_path / "w.csv"
+    _counter_csv(fetch, "FETCH_SIZE", [(copy, 524288.0), (fwd, 300.0)])
+    _counter_csv(write, "WRITE_SIZE", [(copy, 1048576.0), (fwd, 100.0)])
+    bench.write_traffic(str(fetch), str(write), "sino")
+    rec = json.load(open(tmp_path / "sino.json"))
+    assert list(rec["kernels"]) == [bench.SINO_KERNELS["tof_fwd"]]
+    assert bench.profiled_kernel_bytes("sino", bench.SINO_KERNELS["tof_fwd"]) == 1024.0 * (300.0 * 2.0 + 100.0)
+    rec["source_sha256"] = "stale"
+    json.dump(rec, open(tmp_path / "sino.json", "w"))
+    assert bench.profiled_kernel_bytes("sino", bench.SINO_KERNELS["tof_fwd"]) is None
