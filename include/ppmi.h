@@ -151,6 +151,20 @@ int pp_fwd_tof_lm(const float* xstart, const float* xend, const int16_t* tof_bin
                   const pp_image_t* geom, const pp_tof_t* tof, const float* img, float* p, const int32_t* order,
                   void* stream);
 
+/* pp_fwd_tof_lm of the same events through n_img images of the grid at once
+ * (a batch of images, as in networks that project several images per step,
+ * Sec. 1 and 4 of the paper): imgs float32 [n_img][dim0][dim1][dim2],
+ * p float32 [n_img][n_events], p[b][e] the projection of event e through
+ * image b -- equal to pp_fwd_tof_lm of image b alone (the same arithmetic in
+ * the same order).  The ray setup, the TOF window, plane positions,
+ * stencils and TOF weights are computed once for all images; the library
+ * projects up to 8 images per launch.  n_img in [0, 2^20] (else
+ * PP_EINVAL_N); n_img == 0 or n_events == 0 is a no-op.  Other arguments
+ * and errors as pp_fwd_tof_lm. */
+int pp_fwd_tof_lm_batch(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n_events,
+                        const pp_image_t* geom, const pp_tof_t* tof, const float* imgs, int32_t n_img, float* p,
+                        const int32_t* order, void* stream);
+
 /* TOF listmode back projection, adjoint of pp_fwd_tof_lm: img += A^T p. */
 int pp_back_tof_lm(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n_events,
                    const pp_image_t* geom, const pp_tof_t* tof, float* img, const float* p, const int32_t* order,

@@ -5,8 +5,10 @@ image grid; calling it applies the forward projector A and ``.T`` applies the
 back projector A^T.  Both are torch.autograd.Functions whose backward pass is
 the other hand-written kernel: d(Ax)/dx^T g = A^T g and d(A^T y)/dy^T g = A g,
 so the pair is exactly adjoint and double backward works.  Leading batch
-dimensions are looped over (images [..., n0, n1, n2] <-> projections
-[..., n] or [..., n, n_bins]).
+dimensions (images [..., n0, n1, n2] <-> projections [..., n] or [..., n,
+n_bins]) go through the batched listmode forward projection (one pass over
+the events for all images) for the TOF listmode kind, and are looped over
+otherwise.
 """
 from __future__ import annotations
 
@@ -72,8 +74,11 @@ class JosephOperator:
         if tuple(x.shape[-3:]) != self.geom.dim:
             raise ValueError(f"image shape {tuple(x.shape[-3:])} != grid {self.geom.dim}")
         xf = x.reshape(-1, *self.geom.dim)
-        out = torch.stack([self._fwd1(xf[b]) for b in range(xf.shape[0])]) if xf.shape[0] else \
-            x.new_empty((0, *self.proj_shape))
+        if self.kind == "tof_lm" and xf.shape[0] > 1:  # one batched projection of all images
+            out = P.fwd_tof_lm_batch(self.xs, self.xe, self.bins, self.geom, self.tof, xf.contiguous(), self.order)
+        else:
+            out = torch.stack([self._fwd1(xf[b]) for b in range(xf.shape[0])]) if xf.shape[0] else \
+                x.new_empty((0, *self.proj_shape))
         return out.reshape(*lead, *self.proj_shape)
 
     def adjoint_raw(self, y):

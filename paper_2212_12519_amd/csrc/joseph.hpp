@@ -278,11 +278,32 @@ __device__ __forceinline__ float img_load(__amdgpu_buffer_rsrc_t ib, bool ok, in
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ib, ok ? (unsigned)idx * 4u : 0xFFFFFFFFu, 0, 0));
 }
 
+// A raw buffer over `count` consecutive images of the grid (count * voxels * 4 < 2^32, checked on the
+// host): stencil_gather_at reads image b of them at the offset b * image bytes.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t img_buffer_n(const float* img, const GeomK& g, int count) {
+    const unsigned bytes = (unsigned)g.n[0] * (unsigned)g.n[1] * (unsigned)g.n[2] * 4u * (unsigned)count;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(img), (short)0, (int)bytes, 0x00020000);
+}
+
 // bilinear interpolation with zero padding
 __device__ __forceinline__ float stencil_gather(__amdgpu_buffer_rsrc_t ib, const RayK& r, const Stencil& st) {
     // the neighbours' indices as additions to the base (an empty asm keeps the compiler from
     // turning them back into products, which are quarter-rate instructions)
     int base = st.base;
+    asm volatile("" : "+v"(base));
+    const int b01 = base + r.sw, b10 = base + r.su;
+    const float v00 = img_load(ib, st.i0ok && st.j0ok, base);
+    const float v01 = img_load(ib, st.i0ok && st.j1ok, b01);
+    const float v10 = img_load(ib, st.i1ok && st.j0ok, b10);
+    const float v11 = img_load(ib, st.i1ok && st.j1ok, b10 + r.sw);
+    const float gu = 1.0f - st.fu, gw = 1.0f - st.fw;
+    return gu * (gw * v00 + st.fw * v01) + st.fu * (gw * v10 + st.fw * v11);
+}
+
+// stencil_gather of the image that starts `img_off` voxels into the buffer (same arithmetic)
+__device__ __forceinline__ float stencil_gather_at(__amdgpu_buffer_rsrc_t ib, const RayK& r, const Stencil& st,
+                                                   int img_off) {
+    int base = st.base + img_off;
     asm volatile("" : "+v"(base));
     const int b01 = base + r.sw, b10 = base + r.su;
     const float v00 = img_load(ib, st.i0ok && st.j0ok, base);

@@ -24,6 +24,8 @@ hipError_t launch_tof_gauss_table(float* lut, int n, double x0, double dx, doubl
                                   hipStream_t s);
 hipError_t launch_fwd_tof_lm(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g,
                              const TofK& t, const float* img, float* p, const int32_t* order, hipStream_t s);
+hipError_t launch_fwd_tof_lm_batch(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g, const TofK& t,
+                                   const float* imgs, int n_img, float* p, const int32_t* order, hipStream_t s);
 hipError_t launch_back_tof_lm(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g,
                               const TofK& t, float* img, const float* p, const int32_t* order, hipStream_t s);
 size_t presort_workspace_bytes(int64_t n);

@@ -82,6 +82,54 @@ __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(RaySrc src,
     if (l >= 0) p[l] = acc;
 }
 
+// Batched listmode forward: the same events through `nimg` images of the grid (imgs[b] at b * voxels,
+// at most kFwdBatch per launch), p[b * n + l] for image b.  Ray setup, TOF window, plane positions,
+// stencils and TOF weights are computed once per sample for all images; only the four gathers and the
+// accumulation are per image, in the order of k_fwd_tof_lm, so each image's result is that kernel's.
+constexpr int kFwdBatch = 8;
+
+template <int Form, bool PerRay>
+__global__ void __launch_bounds__(kBlock) k_fwd_tof_lm_batch(RaySrc src, const int16_t* __restrict__ bins, int64_t n,
+                                                             GeomK g, TofK t, const float* __restrict__ imgs,
+                                                             int nimg, float* __restrict__ p,
+                                                             const int32_t* __restrict__ order) {
+    constexpr bool kWaveSync = PerRay;
+    const __amdgpu_buffer_rsrc_t ib = img_buffer_n(imgs, g, nimg);
+    const int nv = g.n[0] * g.n[1] * g.n[2];
+    const int64_t l = ray_index(order, n);
+    const int b = l >= 0 ? bins[l] : -1;
+    float acc[kFwdBatch];
+#pragma unroll
+    for (int q = 0; q < kFwdBatch; ++q) acc[q] = 0.0f;
+    RayK r;
+    TofRay tq;
+    bool on = b >= 0 && b < t.nb && tof_ray<PerRay>(t, l, tq) && ray_setup(src, l, g, r);
+    if (on) {
+        if (PerRay) r.s0 -= tq.shift;
+        on = tof_window_rel(r, t.c0 + b * t.bw, tq.lo, tq.hi);
+    }
+    auto sample = [&](int k) {
+        const float w = tof_weight_unscaled<Form>(fma((double)k, r.ds, r.s0), t, tq.inv);
+        const Stencil st = stencil_at(r, k);
+#pragma unroll
+        for (int q = 0; q < kFwdBatch; ++q)
+            if (q < nimg) acc[q] += w * stencil_gather_at(ib, r, st, q * nv);  // nimg: uniform
+    };
+    if (kWaveSync) {  // every lane of the wave reaches this point
+        const int lo = on ? r.k_lo : (1 << 30), hi = on ? r.k_hi : -(1 << 30);
+        const int k0 = wave_min(lo), k1 = wave_max(hi);
+        for (int k = k0; k <= k1; ++k)
+            if (k >= lo && k <= hi) sample(k);
+    } else if (on) {
+        for (int k = r.k_lo; k <= r.k_hi; ++k) sample(k);
+    }
+    if (l < 0) return;
+    const float scale = on ? r.ell * kTofScale<Form> : 0.0f;
+#pragma unroll
+    for (int q = 0; q < kFwdBatch; ++q)
+        if (q < nimg) p[(int64_t)q * n + l] = on ? acc[q] * scale : 0.0f;
+}
+
 // ------------------------------------------------------- TOF sinogram ----
 //
 // Each thread keeps its n_bins accumulators in LDS (column per thread, so a
@@ -219,6 +267,27 @@ hipError_t launch_fwd_tof_lm(const RaySrc& src, const int16_t* bins, int64_t n, 
                                   : (per ? k_fwd_tof_lm<kFormErf, true> : k_fwd_tof_lm<kFormErf, false>);
     hipLaunchKernelGGL(k, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, src, bins, n, g, t, img, p, order);
     return hipGetLastError();
+}
+
+hipError_t launch_fwd_tof_lm_batch(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g, const TofK& t,
+                                   const float* imgs, int n_img, float* p, const int32_t* order, hipStream_t s) {
+    const bool per = t.sig_ray || t.off_ray;
+    const int form = tof_form(t);
+    auto* k = form == kFormLut    ? (per ? k_fwd_tof_lm_batch<kFormLut, true> : k_fwd_tof_lm_batch<kFormLut, false>)
+              : form == kFormPoly ? (per ? k_fwd_tof_lm_batch<kFormPoly, true> : k_fwd_tof_lm_batch<kFormPoly, false>)
+                                  : (per ? k_fwd_tof_lm_batch<kFormErf, true> : k_fwd_tof_lm_batch<kFormErf, false>);
+    // images per launch: at most kFwdBatch, and their bytes within the 32-bit buffer range
+    const int64_t nv = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    int64_t per_launch = ((int64_t(1) << 32) - 1) / (nv * 4);
+    if (per_launch > kFwdBatch) per_launch = kFwdBatch;
+    for (int b0 = 0; b0 < n_img; b0 += (int)per_launch) {
+        const int cnt = (n_img - b0 < per_launch) ? (n_img - b0) : (int)per_launch;
+        hipLaunchKernelGGL(k, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, src, bins, n, g, t, imgs + b0 * nv, cnt,
+                           p + b0 * n, order);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_back_tof_lm(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g,
