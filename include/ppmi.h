@@ -45,6 +45,13 @@
  *   Forward projections overwrite their output.  Back projections ADD into
  *     the image (the caller zeroes it), which allows chunked / subset calls.
  *     Their result depends on the order of floating-point atomic adds.
+ *     Ray lists in an order that puts rays of one transaxial line next to
+ *     each other (presorted listmode, sinograms) are accumulated per line in
+ *     32-bit fixed point in on-chip memory first: each line's scale is a
+ *     power of two fitted to the largest values its rays can add, so that an
+ *     added value carries an absolute rounding error of at most 2^-17 of the
+ *     largest value its own ray adds; rays whose values are too small for
+ *     that precision beside the line's others are added in float directly.
  *   Zero-length or non-finite rays, and listmode bins outside [0, n_bins),
  *     contribute nothing (no error: they are data).  n == 0 is a no-op.
  *

@@ -150,6 +150,7 @@ int make_tof(const pp_tof_t* ti, TofK& t) {
         t.lut_n = ti->lut_n;
         t.lut_inv_dx = (float)(1.0 / dx);
         t.poly = 0;
+        t.wpeak = 0.0f;
         return PP_OK;
     }
     if (!std::isfinite(ti->sigma) || !(ti->sigma > 0.0f) || !std::isfinite(ti->n_sigmas) || !(ti->n_sigmas > 0.0f))
@@ -164,6 +165,7 @@ int make_tof(const pp_tof_t* ti, TofK& t) {
     t.nsig = ti->n_sigmas;
     t.win = ns * sig + 0.5 * bw;
     t.u_per_mm = (float)(erf_c / (std::sqrt(2.0) * sig));
+    t.wpeak = (float)std::erf(std::fmin(0.5 * bw, ns * sig) / (std::sqrt(2.0) * sig));
     t.nb = ti->n_bins;
     t.lo = -t.win;
     t.hi = t.win;

@@ -43,6 +43,7 @@ struct TofK {
     float u_per_mm;       // kErfC / (sqrt(2) sigma): the scaled erf argument (erf_scaled) per mm
     float u_max;          // kErfC n_sigmas / sqrt(2): the truncation in units of that argument
     float nsig;           // n_sigmas
+    float wpeak;          // the Gaussian bin weight's largest value, w(0) (0 with a table)
     int nb;               // bins
     const float* sig_ray; // sigma of each ray (mm), or nullptr: every ray has sigma
     const float* off_ray; // centre offset of each ray (mm), or nullptr: c0 holds the offset

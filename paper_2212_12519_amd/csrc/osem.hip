@@ -72,6 +72,8 @@ struct ModeOsem {
     __device__ float sample(double x, float cv, int /*aux*/) const {
         return tof_weight_unscaled<Form>(x, t, t.u_per_mm) * cv;
     }
+    __device__ float mag(float cv, int /*aux*/) const { return fabsf(cv); }
+    __device__ float weight_bound(float* red) const { return tof_weight_bound<Form>(t, red); }
 };
 
 template <int Form>

@@ -11,21 +11,22 @@
 // (k, i0(k), :) and (k, i0(k) + 1, :) along the fastest axis (2).
 //
 // A workgroup takes 256 consecutive rays of the processing order and splits
-// them into runs (bitwise-equal p, U0, dU).  For every run of >= kRunMin rays
-// each thread becomes a plane k: it walks the run's rays and accumulates the
-// W-interpolated values into its own LDS column (thread-private addresses: no
-// atomics, no bank conflicts; the current pair of z entries is kept in
-// registers, its column values read when z moves to it and written back when z
-// moves on), then the waves flush the sheet with contiguous, duplicate-free
-// atomics -- one memory request per ~16 values instead of one per value.  The
-// column stride is the grid's longest line + 1, so that two workgroups fit a
-// CU's LDS on clinical grids: the loop needs the second workgroup's waves.  The
-// u-weights (1 - fu, fu) are shared by the run and applied at the flush.  Rays
-// in short runs (or with p == 2, or grids whose axis 2 exceeds the LDS column)
-// take the direct wave-synchronous, run-combined scatter.  The arithmetic per
-// (ray, plane) sample is the same as in the direct path; only the order of
-// float additions differs.
+// them into runs (bitwise-equal p, U0, dU).  The rays of every run of >=
+// kRunMin rays are spread over the workgroup's eight half-waves (32 lanes),
+// one ray per half-wave, whose lanes walk the ray's plane window 32 planes at a
+// time and add the W-interpolated values into an LDS image of the sheet
+// (planes x z, one column per plane) with LDS atomics; then the waves flush
+// the sheet with contiguous, duplicate-free atomics -- one memory request per
+// ~16 values instead of one per value.  The column stride is the grid's
+// longest line + 1, so that two workgroups fit a CU's LDS on clinical grids.
+// The u-weights (1 - fu, fu) are shared by the run and applied at the flush.
+// Rays in short runs (or with p == 2, or grids whose axis 2 exceeds the LDS
+// column) take the direct wave-synchronous, run-combined scatter.  The
+// arithmetic per (ray, plane) sample is the same as in the direct path; only
+// the order of float additions differs.
 #pragma once
+
+#include <type_traits>
 
 #include "joseph.hpp"
 
@@ -35,7 +36,12 @@ constexpr int kSheetBlock = 256;
 constexpr int kRunMin = 2;
 constexpr int kSheetMaxW = 128;  // largest axis-2 size with an LDS sheet
 constexpr int kSheetGroups = 8;  // groups of 256 rays per workgroup (a sheet persists across them)
-constexpr int kNoEntry = -(1 << 30);  // "no z entry cached": no ray's floor(W) comes near it
+// Largest sum of value bounds a sheet takes, in its fixed-point units: 2^31 less room for the
+// rounding of every added value (at most kSheetGroups * 256 additions to one entry, 1/2 each).
+constexpr float kSheetCap = 2147483648.0f - 1048576.0f;
+// Fewest bits a ray's largest value keeps in a sheet's fixed point (its relative rounding error is
+// then at most 2^-(kSheetBits + 1)); rays with smaller values take the direct scatter.
+constexpr int kSheetBits = 16;
 
 // LDS layout of k_back_runs (bytes): per-ray arrays, then the column buffer.
 struct SheetLayout {
@@ -54,12 +60,38 @@ struct SheetLayout {
     static size_t bytes(int nw, const GeomK& g) { return ray_bytes() + (size_t)(nw + 1) * col_stride(g) * 4; }
 };
 
+// Largest |x| over a table of n floats (every thread of the workgroup calls it; red: 4 floats of
+// LDS).  A linear interpolation of the table never exceeds it.
+__device__ inline float table_abs_max(const float* __restrict__ tab, int n, float* red) {
+    float v = 0.0f;
+    for (int i = threadIdx.x; i < n; i += kSheetBlock) v = fmaxf(v, fabsf(tab[i]));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    __syncthreads();  // red[] may still be read by a previous call
+    if (__lane_id() == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
+// Upper bound of |tof_weight_unscaled<Form>|: the Gaussian bin weight peaks at w(0) (at most 1 with
+// per-ray sigma), the erf form gives 2 w (its erf within 1e-6), the polynomial is within 5e-7 w(0)
+// of w (margin: the caller's), and a table's interpolation stays within its largest entry.
+template <int Form>
+__device__ inline float tof_weight_bound(const TofK& t, float* red) {
+    if (Form == kFormLut) return table_abs_max(t.lut, t.lut_n, red);
+    const float w0 = t.sig_ray ? 1.0f : t.wpeak + 1e-6f;
+    return Form == kFormErf ? 2.0f * w0 : w0;
+}
+
 // Per-ray value hooks:
 //   setup(l, r, cv, aux): prepare ray l (false = no contribution); cv = ell * p (the constant
 //                    factor of every sample); for listmode TOF, r.s0 is made relative to the bin
 //                    centre; aux: a per-ray word the mode keeps (kAux)
 //   sample(x, cv, aux): the value scattered at the plane sample with TOF coordinate
-//                    x = fma(k, r.ds, r.s0)
+//                    x = fma(k, r.ds, r.s0); linear in cv
+//   mag(cv, aux):    an upper bound of |sample(x, cv, aux)| / weight_bound() over all x
+//   weight_bound(red): the largest |TOF weight| a sample can take (1 without TOF); every thread of
+//                    the workgroup calls it (a table is reduced with red[4] of LDS)
 struct ModeNonTof {
     static constexpr bool kAux = false;
     const float* __restrict__ p;
@@ -71,6 +103,8 @@ struct ModeNonTof {
         return true;
     }
     __device__ float sample(double /*x*/, float cv, int /*aux*/) const { return cv; }
+    __device__ float mag(float cv, int /*aux*/) const { return fabsf(cv); }
+    __device__ float weight_bound(float* /*red*/) const { return 1.0f; }
 };
 
 // Listmode TOF, the weight in form Form (TofForm).  With per-ray TOF parameters (PerRay) the ray's
@@ -98,6 +132,8 @@ struct ModeTofLm {
     __device__ float sample(double x, float cv, int aux) const {
         return tof_weight_unscaled<Form>(x, t, PerRay ? __int_as_float(aux) : t.u_per_mm) * cv;
     }
+    __device__ float mag(float cv, int /*aux*/) const { return fabsf(cv); }
+    __device__ float weight_bound(float* red) const { return tof_weight_bound<Form>(t, red); }
 };
 
 // Sinogram TOF: the value at a plane sample is ell * sum over the bins b of its TOF window of
@@ -142,56 +178,62 @@ struct ModeTofSino {
         }
         return c * cv;
     }
+    // a bin weight is at most w(0) (1 with per-ray sigma) or the table's largest entry
+    __device__ float mag(float cv, int aux) const {
+        const float* pr = p + (int64_t)aux * t.nb;
+        float a = 0.0f;
+        for (int b = 0; b < t.nb; ++b) a += fabsf(pr[b]);
+        return fabsf(cv) * a;
+    }
+    __device__ float weight_bound(float* red) const {
+        return Lut ? table_abs_max(t.lut, t.lut_n, red) : (t.sig_ray ? 1.0f : t.wpeak + 1e-6f);
+    }
 };
 
-// Row of z entry j in a thread's column: entries outside the grid (j = -1, j = nw, or no entry yet)
-// go to the spare row nw, which is never flushed, so that a pair's LDS accesses need no branch.
-__device__ __forceinline__ int col_row(int j, int nw) { return ((unsigned)j < (unsigned)nw) ? j : nw; }
-
-// Flush the sheet of line (p, U0, dU) with contiguous atomics and clear it: only the planes
-// whose thread accumulated something (touched), listed in tl[], only the z entries between the
-// lowest and the highest any of them wrote ([zlo, zhi] of each thread, united over the
-// workgroup), and with the (plane, z) entries spread over all threads (consecutive threads take
-// consecutive z of a plane).  Every thread of the workgroup calls it; the caller synchronises
-// before and after.
-__device__ __forceinline__ void sheet_flush(float* __restrict__ img, float* col, const GeomK& g, int p, double U0,
-                                            double dU, bool touched, int zlo, int zhi, int nw, int cs, int* tl,
-                                            int* tcount) {
+// Flush the sheet of line (p, U0, dU) with contiguous atomics and clear it (its fixed-point values
+// times inv_scale are added to the image): the entries of the
+// rectangle [klo, khi] x [zlo, zhi] (planes, z entries) united over the workgroup's lanes -- each
+// lane passes the planes and the z entries it added to since the last flush -- that hold a value,
+// spread over all threads (consecutive threads take consecutive z of a plane).  Every thread of the
+// workgroup calls it; part[] takes 4 words; the caller synchronises after it.
+__device__ __forceinline__ void sheet_flush(float* __restrict__ img, int* col, const GeomK& g, int p, double U0,
+                                            double dU, float inv_scale, int klo, int khi, int zlo, int zhi, int nw,
+                                            int cs, int* part) {
     constexpr int B = kSheetBlock;
     const int tid = threadIdx.x, lane = (int)__lane_id(), wave = tid >> 6;
-    const unsigned long long bal = __ballot(touched);
-    // per wave: touched count (bits 0-7), lowest z (bits 8-15), highest z (bits 16-23); nw <= 128.
-    // Both ends are clamped to [0, nw - 1] per lane: a thread whose writes all went to out-of-grid
-    // entries (a pair below z = 0 at the conservative end plane of a window, or above nw - 1) has
-    // zhi < 0 or zlo >= nw, and an unclamped negative value would sign-extend into the packed word.
-    const int wlo = wave_min(touched ? min(max(zlo, 0), nw - 1) : 255);
-    const int whi = wave_max(touched ? max(min(zhi, nw - 1), 0) : 0);
-    if (lane == 0) tcount[wave] = __popcll(bal) | (wlo << 8) | (whi << 16);
+    // per wave, packed in one word: lowest plane (bits 0-7), highest plane (8-15), lowest z
+    // (16-23), highest z (24-31); planes < 256 and nw <= 128.  A lane that added nothing passes
+    // klo > khi; z is clamped to the grid per lane (a lane whose pairs were all out of the grid, as
+    // at the conservative end plane of a window, has zhi < 0 or zlo >= nw).
+    const bool any = klo <= khi;
+    const int a = wave_min(any ? klo : 255), b = wave_max(any ? khi : 0);
+    const int c = wave_min(any ? min(max(zlo, 0), nw - 1) : 255);
+    const int d = wave_max(any ? max(min(zhi, nw - 1), 0) : 0);
+    if (lane == 0) part[wave] = a | (b << 8) | (c << 16) | (d << 24);
     __syncthreads();
-    int off = 0, nt = 0, z0 = 255, z1 = 0;
+    int k0 = 255, k1 = 0, z0 = 255, z1 = 0;
     for (int w = 0; w < B / 64; ++w) {
-        const int c = tcount[w];
-        off += (w < wave) ? (c & 0xff) : 0;
-        nt += c & 0xff;
-        z0 = min(z0, (c >> 8) & 0xff);
-        z1 = max(z1, (c >> 16) & 0xff);
+        const unsigned q = (unsigned)part[w];
+        k0 = min(k0, (int)(q & 0xff));
+        k1 = max(k1, (int)((q >> 8) & 0xff));
+        z0 = min(z0, (int)((q >> 16) & 0xff));
+        z1 = max(z1, (int)(q >> 24));
     }
-    if (touched) tl[off + __popcll(bal & ((1ull << lane) - 1ull))] = tid;
-    __syncthreads();
     const int su = (p == 0) ? g.stride[1] : g.stride[0];
     const int sp = g.stride[p];
     const int nu = (p == 0) ? g.n[1] : g.n[0];
-    const int nz = max(z1 - z0 + 1, 0);
-    const int total = nt * nz;
+    const int nk = max(k1 - k0 + 1, 0), nz = max(z1 - z0 + 1, 0);
+    const int total = nk * nz;
     const float inv_nz = 1.0f / (float)max(nz, 1);
     for (int e = tid; e < total; e += B) {
         // e / nz: (e + 1/2) / nz stays >= 1/(2 nz) away from an integer, far above float error
         const int pi = (int)(((float)e + 0.5f) * inv_nz), j = z0 + e - pi * nz;
-        const int k = tl[pi];
-        float* cp = col + j * cs + k;
-        const float v = *cp;
-        if (v != 0.0f) {
-            *cp = 0.0f;
+        const int k = k0 + pi;
+        int* cp = col + j * cs + k;
+        const int q = *cp;
+        if (q != 0) {
+            *cp = 0;
+            const float v = (float)q * inv_scale;
             const double U = fma((double)k, dU, U0);
             const double fi = floor(U);
             const int i0 = (int)fi;
@@ -226,10 +268,12 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
     int* masks = cnt + B;  // 8 words: run-boundary ballots of the 4 waves
     int* list = masks + 8;  // sheet-run heads; count at list[B]; per-wave counts at list[B + 4 ..]
     int* aux = list + B + 8;  // per-ray word of the mode (sinogram TOF: the ray index)
-    // the flush's list of touched planes reuses start[] and masks[], which only the run
-    // detection before the sheet loop uses
-    int* tl = start;
-    float* col = reinterpret_cast<float*>(aux + B + 8);  // [nw][cs]
+    // the flush's per-wave words reuse masks[], which only the run detection before the sheet
+    // loop uses
+    // free words: aux[B .. B + 3] the per-wave sums of the bound prefix, aux[B + 4 .. B + 7] reductions
+    float* wsum = reinterpret_cast<float*>(aux + B);
+    float* red = wsum + 4;
+    int* col = aux + B + 8;  // [nw + 1][cs], 32-bit fixed point
     const int cs = SheetLayout::col_stride(g);
 
     const int tid = threadIdx.x;
@@ -238,11 +282,15 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
     const int nw = g.n[2];
     const bool sheets = nw_lds > 0 && nw <= nw_lds;
     if (sheets)
-        for (int q = tid; q < nw * cs; q += B) col[q] = 0.0f;
+        for (int q = tid; q < nw * cs; q += B) col[q] = 0;
+    // bound of |an added value| per unit of a ray's mag() (margin for float rounding in the bounds)
+    const float wb = m.weight_bound(red) * (1.0f + 0x1p-8f);
     // current sheet (block-uniform copies in registers, updated after barriers)
-    bool sh_on = false, touched = false;  // touched: this thread's plane holds sheet values
-    int zlo = INT_MAX, zhi = INT_MIN;      // z entries it wrote since the last flush (pairs jc, jc + 1)
-    int sh_p = -1, sh_kmax = -1;
+    bool sh_on = false;
+    float sh_scale = 1.0f, sh_used = 0.0f;  // fixed-point scale of the sheet; bounds added (scaled)
+    // planes and z entries this lane added to since the last flush (empty: klo > khi)
+    int t_klo = 255, t_khi = 0, t_zlo = INT_MAX, t_zhi = INT_MIN;
+    int sh_p = -1;
     double sh_U0 = 0.0, sh_dU = 0.0;
     for (int grp = 0; grp < groups; ++grp) {
         const int64_t i = chunk0 + (int64_t)grp * B + tid;
@@ -259,14 +307,24 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
         // compact the valid rays to the front of the group (stable order), so that rays
         // without a contribution do not break runs
         const unsigned long long vb = __ballot(ok);
+        // inclusive prefix sum, in ray order, of the valid rays' bounds of |an added value| (a run's
+        // bound is the difference of two of them)
+        float pm = ok ? m.mag(cv, ax) * wb : 0.0f;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const float o = __shfl_up(pm, off, 64);
+            if (lane >= off) pm += o;
+        }
         __syncthreads();  // previous group's LDS readers are done
         if (lane == 0) list[B + 4 + wave] = __popcll(vb);
+        if (lane == 63) wsum[wave] = pm;
         __syncthreads();
         int voff = 0, nvalid = 0;
         for (int w = 0; w < B / 64; ++w) {
             const int c_w = list[B + 4 + w];
             voff += (w < wave) ? c_w : 0;
             nvalid += c_w;
+            pm += (w < wave) ? wsum[w] : 0.0f;
         }
         const int cp = ok ? voff + __popcll(vb & ((1ull << lane) - 1ull)) : -1;
         if (ok) {
@@ -333,6 +391,9 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
             return sh_on && pax[h] == sh_p && U0[h] == sh_U0 && dU[h] == sh_dU;
         };
         const bool in_sheet = ok && sheet_run(start[cp]);
+        // start[] now takes the bound prefix of the compacted entries (each thread rewrites only the
+        // entry it just read; the loop reads them after the barriers below)
+        if (ok) start[cp] = __float_as_int(pm);
         // parallel compaction of the sheet-run heads (in order): ballot + prefix popcount
         {
             const bool f = sheet_run(tid);
@@ -368,12 +429,20 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
         const int n_long = list[B];
         for (int li = 0; li < n_long; ++li) {
             const int h = list[li];
+            const int len = cnt[h], hend = h + len;
+            // bound of the run's added values (margin for the rounding of the two prefix sums)
+            const float pb1 = __int_as_float(start[hend - 1]), pb0 = h > 0 ? __int_as_float(start[h - 1]) : 0.0f;
+            const float bnd = (pb1 - pb0) + pb1 * 0x1p-14f;
             const bool same_line = sh_on && pax[h] == sh_p && U0[h] == sh_U0 && dU[h] == sh_dU;
-            if (sh_on && !same_line) {
-                sheet_flush(img, col, g, sh_p, sh_U0, sh_dU, touched, zlo, zhi, nw, cs, tl, masks);
-                touched = false;
-                zlo = INT_MAX;
-                zhi = INT_MIN;
+            // the run continues the sheet if its values fit the sheet's fixed-point range
+            const bool fits = same_line && sh_used + bnd * sh_scale <= kSheetCap;
+            if (sh_on && !fits) {
+                sheet_flush(img, col, g, sh_p, sh_U0, sh_dU, 1.0f / sh_scale, t_klo, t_khi, t_zlo, t_zhi, nw, cs,
+                            masks);
+                t_klo = 255;
+                t_khi = 0;
+                t_zlo = INT_MAX;
+                t_zhi = INT_MIN;
                 __syncthreads();
                 sh_on = false;
             }
@@ -382,127 +451,117 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
                 sh_p = pax[h];
                 sh_U0 = U0[h];
                 sh_dU = dU[h];
-                sh_kmax = g.n[sh_p] - 1;
+                // a power of two that puts the run's bound below 2^30.  A run that reaches the end of
+                // the group may go on in the next group: its bound is first extrapolated to a whole
+                // group of such rays, so that a continuation of that size fits the remaining range.
+                const float est = hend == nvalid ? bnd * ((float)B / (float)len) : bnd;
+                int e = 0;
+                frexpf(est, &e);  // est < 2^e
+                sh_scale = ldexpf(1.0f, min(max(30 - e, -126), 126));
+                sh_used = 0.0f;
             }
-            // thread tid accumulates the column of absolute plane k = tid.  Each wave walks the run's
-            // rays whose plane window meets its 64 planes, one ray per step (evaluating 2 or 4 rays
-            // per step measured slower), and the current pair of z entries stays in registers until
-            // z changes.
-            const int k = tid;
-            const int len = cnt[h];
-            const bool kin = k <= sh_kmax;
-            int jc = kNoEntry;
-            float accA = 0.0f, accB = 0.0f;
-            float preA = 0.0f, preB = 0.0f;  // column values of the pair jc, read when z moved to it
-            // the column this thread writes: its own plane's, or for threads past the line's last plane
-            // the unused last column (cs - 1 is never a plane of a sheet line), whose spare-row entry
-            // takes their (zero) write-backs
-            const int kc = kin ? k : cs - 1;
-            // byte offsets into the column buffer of the pair's two entries (rows col_row(jc) and
-            // col_row(jc + 1)), recomputed from jc on every step
-            typedef __attribute__((address_space(3))) char lds_char;
-            typedef __attribute__((address_space(3))) float lds_float;
-            lds_char* colb = (lds_char*)col;
-            // LDS byte addresses (the buffer's own address folded into the per-thread term, so that
-            // an address is one multiply-add of the row)
+            sh_used += bnd * sh_scale;
+            // The eight half-waves of the workgroup take the run's rays in turn (half-wave q: rays
+            // h + q, h + q + 8, ...); a half-wave walks its ray's plane window 32 planes per step,
+            // lane i at plane k_lo + i + 32 c, and adds the two W-interpolated values of each sample
+            // to the column entries (j0, k) and (j0 + 1, k) with LDS atomics.  A ray's window fills
+            // its steps up to the last one (about 95% of the lanes carry a sample on clinical TOF
+            // windows), and the waves share no plane ownership, so they need no barrier until the
+            // flush.  Entries outside the grid (j = -1, j = nw, the conservative end planes) go to
+            // the spare row nw, which is never flushed.
+            const int half = lane >> 5, hl = lane & 31;
+            typedef __attribute__((address_space(3))) int lds_int;
+            // LDS byte addresses: row j of plane k at col + 4 (j cs + k)
             const unsigned cs4 = 4u * (unsigned)cs;
-            const unsigned kc4 = 4u * (unsigned)kc + (unsigned)(uintptr_t)colb;
-            auto row_off = [&](int j) { return (int)(__umul24((unsigned)col_row(j, nw), cs4) + kc4); };
-            auto at = [&](int addr) { return (lds_float*)(uintptr_t)(unsigned)addr; };
-            int ia = row_off(nw), ib = ia;
-            for (int b0 = h; b0 < h + len; b0 += 64) {
-                const int nb = min(64, h + len - b0);
-                const int qlh = lohi[b0 + min(lane, nb - 1)];
-                // rays whose plane window meets this wave's 64 planes (wave-uniform bit mask)
-                const int kw0 = wave * 64, kw1 = min(kw0 + 63, sh_kmax);
-                unsigned long long todo =
-                    __ballot(lane < nb && (qlh & 0xffff) <= kw1 && (qlh >> 16) >= kw0);
-                if (!todo) continue;
-                // Each ray's parameters are read from LDS at a wave-uniform address (a broadcast,
-                // no bank conflict), one ray ahead of its evaluation so that the read latency
-                // overlaps the current ray's arithmetic; two records alternate (no copies).
-                struct Rec {
-                    double W0, dW, s0, ds;
-                    float cv;
-                    int ax, lh;
-                };
-                auto load = [&](int e) {
-                    return Rec{W0[e], dW[e], s0[e], ds[e], cvs[e], aux[e], lohi[e]};
-                };
-                auto next = [&](int fallback) {
-                    const int en = todo ? b0 + __ffsll((long long)todo) - 1 : fallback;
-                    todo &= todo - 1ull;
-                    return en;
-                };
-                // Every step writes the current pair back (its column values plus what the previous
-                // step added) and reads the pair of this step's z -- the same pair again when z did not
-                // change or the lane contributes nothing.  The same LDS accesses on every step and no
-                // branch: the wait for a pair's values comes a whole step after their read, at the next
-                // write-back, and the record loads of the next rays are never held up behind a read
-                // issued late in a step.  (A write-back followed by the read of an overlapping pair is
-                // seen by that read: one wave's LDS accesses complete in order.)
-                auto step = [&](const Rec& c) {
-                    const bool act = kin && k >= (c.lh & 0xffff) && k <= (c.lh >> 16);
-                    const double W = fma((double)k, c.dW, c.W0);
-                    const double fj = floor(W);
-                    const int j0 = (int)fj;
-                    const float fw = (float)(W - fj);
-                    const float v0 = m.sample(fma((double)k, c.ds, c.s0), c.cv, Mode::kAux ? c.ax : 0);
-                    const float v = act ? v0 : 0.0f;
-                    *at(ia) = preA + accA;
-                    *at(ib) = preB + accB;
-                    const bool move = v != 0.0f && j0 != jc;
-                    jc = move ? j0 : jc;
-                    zlo = move ? min(zlo, j0) : zlo;
-                    zhi = move ? max(zhi, j0 + 1) : zhi;
-                    ia = row_off(jc);
-                    ib = row_off(jc + 1);
-                    preA = *at(ia);
-                    preB = *at(ib);
-                    accA = (1.0f - fw) * v;
-                    accB = fw * v;
-                };
-                // A compiler-only barrier after each prefetch keeps the loads where they are: the
-                // column accesses of step() are float and the records double / int, so without it the
-                // compiler may sink the loads to their first use and wait on them there.
-                int e = next(0);
-                Rec ra = load(e);
+            const unsigned colb = (unsigned)(uintptr_t)(__attribute__((address_space(3))) char*)col;
+            auto at = [&](unsigned addr) { return (lds_int*)(uintptr_t)addr; };
+            // a half-wave's ray: its records, read one ray ahead of its steps (a ray index past the
+            // run reads the run head's records and gets an empty window)
+            struct Rec {
+                double W0, dW, s0, ds;
+                float cv, mg;  // mg: the ray's bound of |an added value| (a difference of the prefix)
+                int ax, lh;
+            };
+            auto load = [&](int ra) {
+                const int r = ra + half < hend ? ra + half : h;
+                const float pr0 = r > 0 ? __int_as_float(start[r - 1]) : 0.0f;
+                Rec q{W0[r], dW[r], s0[r], ds[r], cvs[r], __int_as_float(start[r]) - pr0, Mode::kAux ? aux[r] : 0,
+                      lohi[r]};
+                if (ra + half >= hend) q.lh = 0xffff;  // k_lo 65535 > k_hi 0: no planes
+                return q;
+            };
+            // the line's in-plane stencil terms, for rays that add to the image directly
+            const int sp = g.stride[sh_p], su = g.stride[sh_p == 0 ? 1 : 0], nu = g.n[sh_p == 0 ? 1 : 0];
+            const float inv_scale = 1.0f / sh_scale;
+            Rec cur = load(h + 2 * wave);
+            // wait for these reads here: the loop then sees them complete on every path and its steps
+            // carry no LDS wait (which, LDS operations completing in order, would also wait for the
+            // previous step's adds)
+            __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+            for (int ra = h + 2 * wave; ra < hend; ra += 8) {  // wave-uniform
+                const Rec nxt = load(ra + 8);
+                // a compiler-only barrier: keeps the prefetch here rather than next to its use
                 asm volatile("" ::: "memory");
-                {   // a step without a ray (write the pair back, read it again): the LDS accesses
-                    // entering the loop then follow the same pattern as from one step to the next,
-                    // so the waits at the top of the loop are as exact as inside it
-                    volatile lds_float* va = at(ia);
-                    volatile lds_float* vb = at(ib);
-                    *va = preA + accA;
-                    *vb = preB + accB;
-                    preA = *va;
-                    preB = *vb;
-                    accA = 0.0f;
-                    accB = 0.0f;
+                const int klo = cur.lh & 0xffff, khi = cur.lh >> 16;
+                const float cvs_ = cur.cv * sh_scale;  // the sample values in fixed-point units
+                // a ray whose values would keep fewer than kSheetBits bits in the sheet's fixed point
+                // (far smaller values than the run's others) adds them to the image directly, with the
+                // direct path's float atomics
+                const bool direct = cur.mg * sh_scale < (float)(1 << kSheetBits);
+                if (klo <= khi) {
+                    t_klo = min(t_klo, klo);
+                    t_khi = max(t_khi, khi);
                 }
-                while (true) {
-                    bool more = todo != 0ull;
-                    e = next(e);
-                    const Rec rb = load(e);
-                    asm volatile("" ::: "memory");
-                    step(ra);
-                    if (!more) break;
-                    more = todo != 0ull;
-                    e = next(e);
-                    ra = load(e);
-                    asm volatile("" ::: "memory");
-                    step(rb);
-                    if (!more) break;
-                }
+                // planes - 1 of the longer of the two rays (wave-uniform)
+                const int span = max(__builtin_amdgcn_readlane(khi - klo, 0), __builtin_amdgcn_readlane(khi - klo, 32));
+                // the samples of the two rays, 32 planes per step; Mixed: some lane adds directly
+                auto steps = [&](auto mixed) {
+                    for (int c = 0; c <= span; c += 32) {
+                        const int k = klo + hl + c;
+                        if (k <= khi) {
+                            const double W = fma((double)k, cur.dW, cur.W0);
+                            const double fj = floor(W);
+                            const int j0 = (int)fj;
+                            const float fw = (float)(W - fj);
+                            const float v = m.sample(fma((double)k, cur.ds, cur.s0), cvs_, cur.ax);
+                            if (!decltype(mixed)::value || !direct) {
+                                const unsigned kb = 4u * (unsigned)k + colb;
+                                const unsigned a0 = __umul24(min((unsigned)j0, (unsigned)nw), cs4) + kb;
+                                const unsigned a1 = __umul24(min((unsigned)(j0 + 1), (unsigned)nw), cs4) + kb;
+                                __hip_atomic_fetch_add(at(a0), __float2int_rn((1.0f - fw) * v), __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                                __hip_atomic_fetch_add(at(a1), __float2int_rn(fw * v), __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                                t_zlo = min(t_zlo, j0);
+                                t_zhi = max(t_zhi, j0 + 1);
+                            } else {
+                                const float vf = v * inv_scale;  // exact: the scale is a power of two
+                                const double U = fma((double)k, sh_dU, sh_U0);
+                                const double fi = floor(U);
+                                const int i0 = (int)fi;
+                                const float fu = (float)(U - fi), gu = 1.0f - fu, gw = 1.0f - fw;
+                                const int base = k * sp + i0 * su + j0;
+                                const bool i0ok = (unsigned)i0 < (unsigned)nu, i1ok = (unsigned)(i0 + 1) < (unsigned)nu;
+                                const bool j0ok = (unsigned)j0 < (unsigned)nw, j1ok = (unsigned)(j0 + 1) < (unsigned)nw;
+                                if (i0ok && j0ok) unsafeAtomicAdd(img + base, gu * gw * vf);
+                                if (i0ok && j1ok) unsafeAtomicAdd(img + base + 1, gu * fw * vf);
+                                if (i1ok && j0ok) unsafeAtomicAdd(img + base + su, fu * gw * vf);
+                                if (i1ok && j1ok) unsafeAtomicAdd(img + base + su + 1, fu * fw * vf);
+                            }
+                        }
+                    }
+                };
+                if (__ballot(direct && klo <= khi))
+                    steps(std::integral_constant<bool, true>{});
+                else
+                    steps(std::integral_constant<bool, false>{});
+                cur = nxt;
             }
-            *at(ia) = preA + accA;
-            *at(ib) = preB + accB;
-            touched = touched || jc != kNoEntry;  // jc may be an out-of-grid entry after writes
-            // no barrier between runs: a run writes only the thread's own column; other threads read
-            // the columns only in a flush, whose first barrier follows every wave's last write here
+            // no barrier between runs of one line: the adds are atomic, and the columns are read
+            // only in a flush, whose first barrier follows every wave's last add
         }
     }
-    if (sh_on) sheet_flush(img, col, g, sh_p, sh_U0, sh_dU, touched, zlo, zhi, nw, cs, tl, masks);
+    if (sh_on) sheet_flush(img, col, g, sh_p, sh_U0, sh_dU, 1.0f / sh_scale, t_klo, t_khi, t_zlo, t_zhi, nw, cs, masks);
     __syncthreads();  // the LDS may be reused by the caller
 }
 
