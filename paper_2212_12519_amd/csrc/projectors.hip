@@ -54,11 +54,15 @@ __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(RaySrc src,
     constexpr bool kWaveSync = PerRay;
     const __amdgpu_buffer_rsrc_t ib = img_buffer(img, g);
     const int64_t l = ray_index(order, n);
-    const int b = l >= 0 ? bins[l] : -1;
+    // every load of the ray issued together (no short circuit); a thread past the end reads ray 0
+    const int64_t lc = l >= 0 ? l : 0;
+    const int b = bins[lc];
     float acc = 0.0f;
     RayK r;
     TofRay q;
-    bool on = b >= 0 && b < t.nb && tof_ray<PerRay>(t, l, q) && ray_setup(src, l, g, r);
+    const bool geo = ray_setup(src, lc, g, r);
+    const bool tr = tof_ray<PerRay>(t, lc, q);
+    bool on = l >= 0 && b >= 0 && b < t.nb && tr && geo;
     if (on) {
         if (PerRay) r.s0 -= q.shift;
         on = tof_window_rel(r, t.c0 + b * t.bw, q.lo, q.hi);
@@ -97,13 +101,17 @@ __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm_batch(RaySrc src, const i
     const __amdgpu_buffer_rsrc_t ib = img_buffer_n(imgs, g, nimg);
     const int nv = g.n[0] * g.n[1] * g.n[2];
     const int64_t l = ray_index(order, n);
-    const int b = l >= 0 ? bins[l] : -1;
+    // every load of the ray issued together (no short circuit); a thread past the end reads ray 0
+    const int64_t lc = l >= 0 ? l : 0;
+    const int b = bins[lc];
     float acc[kFwdBatch];
 #pragma unroll
     for (int q = 0; q < kFwdBatch; ++q) acc[q] = 0.0f;
     RayK r;
     TofRay tq;
-    bool on = b >= 0 && b < t.nb && tof_ray<PerRay>(t, l, tq) && ray_setup(src, l, g, r);
+    const bool geo = ray_setup(src, lc, g, r);
+    const bool tr = tof_ray<PerRay>(t, lc, tq);
+    bool on = l >= 0 && b >= 0 && b < t.nb && tr && geo;
     if (on) {
         if (PerRay) r.s0 -= tq.shift;
         on = tof_window_rel(r, t.c0 + b * t.bw, tq.lo, tq.hi);

@@ -46,17 +46,18 @@ constexpr int kSheetBits = 16;
 // LDS layout of k_back_runs (bytes): per-ray arrays, then the column buffer.
 struct SheetLayout {
     static constexpr int kDoubles = 6;  // W0 dW s0 ds U0 dU
-    static constexpr int kWords = 7;    // cv, lohi, pax, start, cnt, list, aux; + 24 words
+    static constexpr int kWords = 6;    // cv, lohi, start, cnt, list, aux; + 24 words
     static size_t ray_bytes() { return (size_t)kSheetBlock * (kDoubles * 8 + kWords * 4) + 24 * 4; }
-    // column stride: the longest line a sheet can hold (planes along axis 0 or 1, at most one
-    // per thread) + 1; sized to the grid so that two workgroups share a CU's LDS on the
-    // clinical grid (215 planes, 71 z entries: 79.8 KB)
+    // column stride: the longest line a sheet can hold (planes along axis 0 or 1, at most 256),
+    // rounded up to an odd count, so that the 64 consecutive z entries of one plane that a wave
+    // reads in the flush fall in 64 different LDS banks; sized to the grid so that two workgroups
+    // share a CU's LDS on the clinical grid (215 planes, 71 z entries: 79.1 KB)
     __host__ __device__ static int col_stride(const GeomK& g) {
         const int np = g.n[0] > g.n[1] ? g.n[0] : g.n[1];
-        return (np < kSheetBlock ? np : kSheetBlock) + 1;
+        return (np < kSheetBlock ? np : kSheetBlock) | 1;
     }
     // nw rows of the sheet plus one spare row that absorbs the out-of-grid entries of a z pair
-    // (216-entry rows on the clinical grid: 81,760 bytes, two workgroups per CU)
+    // (217-entry rows on the clinical grid: 81,024 bytes, two workgroups per CU)
     static size_t bytes(int nw, const GeomK& g) { return ray_bytes() + (size_t)(nw + 1) * col_stride(g) * 4; }
 };
 
@@ -98,7 +99,8 @@ struct ModeNonTof {
     __device__ bool setup(int64_t l, const RaySrc& src, const GeomK& g, RayK& r, float& cv,
                           int& /*aux*/) const {
         const float pl = p[l];
-        if (pl == 0.0f || !ray_setup(src, l, g, r)) return false;
+        const bool geo = ray_setup(src, l, g, r);  // evaluated in any case: all loads issue together
+        if (pl == 0.0f || !geo) return false;
         cv = r.ell * pl;
         return true;
     }
@@ -121,8 +123,10 @@ struct ModeTofLm {
         const int b = bins[l];
         const float pl = p[l];
         TofRay q;
-        if (b < 0 || b >= t.nb || pl == 0.0f || !tof_ray<PerRay>(t, l, q) || !ray_setup(src, l, g, r))
-            return false;
+        // every condition evaluated (no short circuit), so that all of the ray's loads issue together
+        const bool geo = ray_setup(src, l, g, r);
+        const bool tr = tof_ray<PerRay>(t, l, q);
+        if (b < 0 || b >= t.nb || pl == 0.0f || !tr || !geo) return false;
         if (PerRay) r.s0 -= q.shift;
         if (!tof_window_rel(r, t.c0 + b * t.bw, q.lo, q.hi)) return false;
         cv = r.ell * pl * kTofScale<Form>;
@@ -190,12 +194,11 @@ struct ModeTofSino {
     }
 };
 
-// Flush the sheet of line (p, U0, dU) with contiguous atomics and clear it (its fixed-point values
-// times inv_scale are added to the image): the entries of the
-// rectangle [klo, khi] x [zlo, zhi] (planes, z entries) united over the workgroup's lanes -- each
-// lane passes the planes and the z entries it added to since the last flush -- that hold a value,
-// spread over all threads (consecutive threads take consecutive z of a plane).  Every thread of the
-// workgroup calls it; part[] takes 4 words; the caller synchronises after it.
+// Flush the sheet of line (p, U0, dU) with contiguous atomics and clear it: the entries that hold a
+// value, in the rectangle [klo, khi] x [zlo, zhi] (planes, z entries) united over the workgroup's
+// lanes (each lane passes the planes and z entries it added to since the last flush), times
+// inv_scale (the fixed point's unit) and the in-plane weights.  Every thread of the workgroup calls
+// it; part[] takes 4 words; the caller synchronises after it.
 __device__ __forceinline__ void sheet_flush(float* __restrict__ img, int* col, const GeomK& g, int p, double U0,
                                             double dU, float inv_scale, int klo, int khi, int zlo, int zhi, int nw,
                                             int cs, int* part) {
@@ -225,6 +228,8 @@ __device__ __forceinline__ void sheet_flush(float* __restrict__ img, int* col, c
     const int nk = max(k1 - k0 + 1, 0), nz = max(z1 - z0 + 1, 0);
     const int total = nk * nz;
     const float inv_nz = 1.0f / (float)max(nz, 1);
+    // the entries spread over all threads, consecutive threads on consecutive z of a plane (64
+    // contiguous image addresses per atomic instruction; the odd column stride puts them in 64 banks)
     for (int e = tid; e < total; e += B) {
         // e / nz: (e + 1/2) / nz stays >= 1/(2 nz) away from an integer, far above float error
         const int pi = (int)(((float)e + 0.5f) * inv_nz), j = z0 + e - pi * nz;
@@ -246,9 +251,9 @@ __device__ __forceinline__ void sheet_flush(float* __restrict__ img, int* col, c
 }
 
 // One workgroup walks `groups` consecutive groups of 256 rays of the processing
-// order.  The sheet of the current line persists across groups (thread t holds
-// the column of absolute plane t, so lines need n_p <= 256); it is flushed when a
-// run of another line starts, and at the end.
+// order.  The sheet of the current line (one column per absolute plane, so lines
+// need n_p <= 256) persists across groups; it is flushed when a run of another
+// line starts, when the line's values outgrow its fixed-point range, and at the end.
 template <class Mode>
 __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
                                 const GeomK& g, float* __restrict__ img, const int32_t* __restrict__ order,
@@ -261,9 +266,10 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
     double* U0 = ds + B;
     double* dU = U0 + B;
     float* cvs = reinterpret_cast<float*>(dU + B);
-    int* lohi = reinterpret_cast<int*>(cvs + B);  // k_lo | k_hi << 16 (sheet rays: planes < 256)
-    int* pax = lohi + B;
-    int* start = pax + B;
+    // k_lo | k_hi << 8 | p << 16 (the plane range is read for sheet rays only, whose planes are < 256)
+    int* lohi = reinterpret_cast<int*>(cvs + B);
+    auto pax = [&](int e) { return lohi[e] >> 16; };
+    int* start = lohi + B;
     int* cnt = start + B;
     int* masks = cnt + B;  // 8 words: run-boundary ballots of the 4 waves
     int* list = masks + 8;  // sheet-run heads; count at list[B]; per-wave counts at list[B + 4 ..]
@@ -336,15 +342,14 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
             dU[cp] = r.dU;
             cvs[cp] = cv;
             aux[cp] = ax;
-            lohi[cp] = (r.k_lo & 0xffff) | (r.k_hi << 16);
-            pax[cp] = r.p;
+            lohi[cp] = (r.k_lo & 0xff) | ((r.k_hi & 0xff) << 8) | (r.p << 16);
         }
         __syncthreads();
         // runs over the compacted entries (thread t examines entry t): maximal stretches with
         // bitwise-equal (p, U0, dU)
         const bool e_ok = tid < nvalid;
         const bool same =
-            e_ok && tid > 0 && pax[tid - 1] == pax[tid] && U0[tid - 1] == U0[tid] && dU[tid - 1] == dU[tid];
+            e_ok && tid > 0 && pax(tid - 1) == pax(tid) && U0[tid - 1] == U0[tid] && dU[tid - 1] == dU[tid];
         int st = (e_ok && !same) ? tid : -1;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
@@ -386,9 +391,9 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
         __syncthreads();
         // a run goes to the sheet if it is long, or if it continues the current sheet's line
         auto sheet_run = [&](int h) {
-            if (!sheets || cnt[h] == 0 || pax[h] == 2 || g.n[pax[h]] > B) return false;
+            if (!sheets || cnt[h] == 0 || pax(h) == 2 || g.n[pax(h)] > B) return false;
             if (cnt[h] >= kRunMin) return true;
-            return sh_on && pax[h] == sh_p && U0[h] == sh_U0 && dU[h] == sh_dU;
+            return sh_on && pax(h) == sh_p && U0[h] == sh_U0 && dU[h] == sh_dU;
         };
         const bool in_sheet = ok && sheet_run(start[cp]);
         // start[] now takes the bound prefix of the compacted entries (each thread rewrites only the
@@ -433,7 +438,7 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
             // bound of the run's added values (margin for the rounding of the two prefix sums)
             const float pb1 = __int_as_float(start[hend - 1]), pb0 = h > 0 ? __int_as_float(start[h - 1]) : 0.0f;
             const float bnd = (pb1 - pb0) + pb1 * 0x1p-14f;
-            const bool same_line = sh_on && pax[h] == sh_p && U0[h] == sh_U0 && dU[h] == sh_dU;
+            const bool same_line = sh_on && pax(h) == sh_p && U0[h] == sh_U0 && dU[h] == sh_dU;
             // the run continues the sheet if its values fit the sheet's fixed-point range
             const bool fits = same_line && sh_used + bnd * sh_scale <= kSheetCap;
             if (sh_on && !fits) {
@@ -448,7 +453,7 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
             }
             if (!sh_on) {
                 sh_on = true;
-                sh_p = pax[h];
+                sh_p = pax(h);
                 sh_U0 = U0[h];
                 sh_dU = dU[h];
                 // a power of two that puts the run's bound below 2^30.  A run that reaches the end of
@@ -487,7 +492,7 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
                 const float pr0 = r > 0 ? __int_as_float(start[r - 1]) : 0.0f;
                 Rec q{W0[r], dW[r], s0[r], ds[r], cvs[r], __int_as_float(start[r]) - pr0, Mode::kAux ? aux[r] : 0,
                       lohi[r]};
-                if (ra + half >= hend) q.lh = 0xffff;  // k_lo 65535 > k_hi 0: no planes
+                if (ra + half >= hend) q.lh = 0xff;  // k_lo 255 > k_hi 0: no planes
                 return q;
             };
             // the line's in-plane stencil terms, for rays that add to the image directly
@@ -502,7 +507,7 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
                 const Rec nxt = load(ra + 8);
                 // a compiler-only barrier: keeps the prefetch here rather than next to its use
                 asm volatile("" ::: "memory");
-                const int klo = cur.lh & 0xffff, khi = cur.lh >> 16;
+                const int klo = cur.lh & 0xff, khi = (cur.lh >> 8) & 0xff;
                 const float cvs_ = cur.cv * sh_scale;  // the sample values in fixed-point units
                 // a ray whose values would keep fewer than kSheetBits bits in the sheet's fixed point
                 // (far smaller values than the run's others) adds them to the image directly, with the
