@@ -43,6 +43,15 @@ constexpr float kSheetCap = 2147483648.0f - 1048576.0f;
 // then at most 2^-(kSheetBits + 1)); rays with smaller values take the direct scatter.
 constexpr int kSheetBits = 16;
 
+// A value in fixed-point units rounded to the nearest integer, halves up: floor(x + 1/2) in one
+// instruction (v_cvt_rpi_i32_f32; the compiler's round-to-nearest-even conversion takes two).  |x|
+// stays below 2^31 in the sheet by construction.
+__device__ __forceinline__ int round_half_up(float x) {
+    int r;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
 // LDS layout of k_back_runs (bytes): per-ray arrays, then the column buffer.
 struct SheetLayout {
     static constexpr int kDoubles = 6;  // W0 dW s0 ds U0 dU
@@ -533,9 +542,9 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
                                 const unsigned kb = 4u * (unsigned)k + colb;
                                 const unsigned a0 = __umul24(min((unsigned)j0, (unsigned)nw), cs4) + kb;
                                 const unsigned a1 = __umul24(min((unsigned)(j0 + 1), (unsigned)nw), cs4) + kb;
-                                __hip_atomic_fetch_add(at(a0), __float2int_rn((1.0f - fw) * v), __ATOMIC_RELAXED,
+                                __hip_atomic_fetch_add(at(a0), round_half_up((1.0f - fw) * v), __ATOMIC_RELAXED,
                                                        __HIP_MEMORY_SCOPE_WORKGROUP);
-                                __hip_atomic_fetch_add(at(a1), __float2int_rn(fw * v), __ATOMIC_RELAXED,
+                                __hip_atomic_fetch_add(at(a1), round_half_up(fw * v), __ATOMIC_RELAXED,
                                                        __HIP_MEMORY_SCOPE_WORKGROUP);
                                 t_zlo = min(t_zlo, j0);
                                 t_zhi = max(t_zhi, j0 + 1);
