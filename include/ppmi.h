@@ -48,10 +48,13 @@
  *     Ray lists in an order that puts rays of one transaxial line next to
  *     each other (presorted listmode, sinograms) are accumulated per line in
  *     32-bit fixed point in on-chip memory first: each line's scale is a
- *     power of two fitted to the largest values its rays can add, so that an
- *     added value carries an absolute rounding error of at most 2^-17 of the
- *     largest value its own ray adds; rays whose values are too small for
- *     that precision beside the line's others are added in float directly.
+ *     power of two fitted to the largest values its rays can add (coarsened
+ *     when more rays of the line arrive), every value is rounded to the unit
+ *     with the rounding remainder carried to the next value, so that sums
+ *     over many values lose nothing systematically; an added value is off by
+ *     at most 1.5 units, and every ray in the fixed point adds values of at
+ *     least 2^8 units at its largest.  Rays whose values are too small for
+ *     that beside the line's others are added in float directly.
  *   Zero-length or non-finite rays, and listmode bins outside [0, n_bins),
  *     contribute nothing (no error: they are data).  n == 0 is a no-op.
  *

@@ -41,7 +41,7 @@ constexpr int kSheetGroups = 8;  // groups of 256 rays per workgroup (a sheet pe
 constexpr float kSheetCap = 2147483648.0f - 1048576.0f;
 // Fewest bits a ray's largest value keeps in a sheet's fixed point (its relative rounding error is
 // then at most 2^-(kSheetBits + 1)); rays with smaller values take the direct scatter.
-constexpr int kSheetBits = 16;
+constexpr int kSheetBits = 8;
 
 // A value in fixed-point units rounded to the nearest integer, halves up: floor(x + 1/2) in one
 // instruction (v_cvt_rpi_i32_f32; the compiler's round-to-nearest-even conversion takes two).  |x|
@@ -203,16 +203,13 @@ struct ModeTofSino {
     }
 };
 
-// Flush the sheet of line (p, U0, dU) with contiguous atomics and clear it: the entries that hold a
-// value, in the rectangle [klo, khi] x [zlo, zhi] (planes, z entries) united over the workgroup's
-// lanes (each lane passes the planes and z entries it added to since the last flush), times
-// inv_scale (the fixed point's unit) and the in-plane weights.  Every thread of the workgroup calls
-// it; part[] takes 4 words; the caller synchronises after it.
-__device__ __forceinline__ void sheet_flush(float* __restrict__ img, int* col, const GeomK& g, int p, double U0,
-                                            double dU, float inv_scale, int klo, int khi, int zlo, int zhi, int nw,
-                                            int cs, int* part) {
+// The rectangle [k0, k1] x [z0, z1] (planes, z entries) of the sheet that the workgroup's lanes
+// added to since the last flush (each lane passes its own klo, khi, zlo, zhi; empty: k0 > k1 or
+// z0 > z1).  Every thread of the workgroup calls it; part[] takes 4 words; it synchronises once.
+__device__ __forceinline__ void sheet_rect(int klo, int khi, int zlo, int zhi, int nw, int* part, int& k0, int& k1,
+                                           int& z0, int& z1) {
     constexpr int B = kSheetBlock;
-    const int tid = threadIdx.x, lane = (int)__lane_id(), wave = tid >> 6;
+    const int lane = (int)__lane_id(), wave = (int)threadIdx.x >> 6;
     // per wave, packed in one word: lowest plane (bits 0-7), highest plane (8-15), lowest z
     // (16-23), highest z (24-31); planes < 256 and nw <= 128.  A lane that added nothing passes
     // klo > khi; z is clamped to the grid per lane (a lane whose pairs were all out of the grid, as
@@ -223,7 +220,7 @@ __device__ __forceinline__ void sheet_flush(float* __restrict__ img, int* col, c
     const int d = wave_max(any ? max(min(zhi, nw - 1), 0) : 0);
     if (lane == 0) part[wave] = a | (b << 8) | (c << 16) | (d << 24);
     __syncthreads();
-    int k0 = 255, k1 = 0, z0 = 255, z1 = 0;
+    k0 = 255, k1 = 0, z0 = 255, z1 = 0;
     for (int w = 0; w < B / 64; ++w) {
         const unsigned q = (unsigned)part[w];
         k0 = min(k0, (int)(q & 0xff));
@@ -231,6 +228,43 @@ __device__ __forceinline__ void sheet_flush(float* __restrict__ img, int* col, c
         z0 = min(z0, (int)((q >> 16) & 0xff));
         z1 = max(z1, (int)(q >> 24));
     }
+}
+
+// Coarsen the sheet's fixed point by 2^sft (1 <= sft <= 24): every entry of the written rectangle
+// is divided by 2^sft and rounded, each thread carrying its rounding remainder (exact, in the old
+// units) into its next entry, so that the entries' sum is kept to within half a new unit per
+// thread: no systematic loss of the many small entries.  Every thread of the workgroup calls it; the
+// caller synchronises after it.
+__device__ __forceinline__ void sheet_rescale(int* col, int cs, int sft, int klo, int khi, int zlo, int zhi, int nw,
+                                              int* part) {
+    constexpr int B = kSheetBlock;
+    int k0, k1, z0, z1;
+    sheet_rect(klo, khi, zlo, zhi, nw, part, k0, k1, z0, z1);
+    const int nk = max(k1 - k0 + 1, 0), nz = max(z1 - z0 + 1, 0);
+    const int total = nk * nz;
+    const float inv_nz = 1.0f / (float)max(nz, 1);
+    long long rem = 0;
+    for (int e = (int)threadIdx.x; e < total; e += B) {
+        const int pi = (int)(((float)e + 0.5f) * inv_nz), j = z0 + e - pi * nz;
+        int* cp = col + j * cs + k0 + pi;
+        const long long t = (long long)*cp + rem;
+        const long long q = (t + (1ll << (sft - 1))) >> sft;
+        rem = t - (q << sft);
+        *cp = (int)q;
+    }
+}
+
+// Flush the sheet of line (p, U0, dU) with contiguous atomics and clear it: the entries that hold a
+// value, in the rectangle the workgroup's lanes wrote (sheet_rect), times inv_scale (the fixed
+// point's unit) and the in-plane weights.  Every thread of the workgroup calls it; part[] takes 4
+// words; the caller synchronises after it.
+__device__ __forceinline__ void sheet_flush(float* __restrict__ img, int* col, const GeomK& g, int p, double U0,
+                                            double dU, float inv_scale, int klo, int khi, int zlo, int zhi, int nw,
+                                            int cs, int* part) {
+    constexpr int B = kSheetBlock;
+    const int tid = threadIdx.x;
+    int k0, k1, z0, z1;
+    sheet_rect(klo, khi, zlo, zhi, nw, part, k0, k1, z0, z1);
     const int su = (p == 0) ? g.stride[1] : g.stride[0];
     const int sp = g.stride[p];
     const int nu = (p == 0) ? g.n[1] : g.n[0];
@@ -303,6 +337,8 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
     // current sheet (block-uniform copies in registers, updated after barriers)
     bool sh_on = false;
     float sh_scale = 1.0f, sh_used = 0.0f;  // fixed-point scale of the sheet; bounds added (scaled)
+    // this lane's rounding remainder, carried from one of its samples to the next (sheet units)
+    float res = 0.0f;
     // planes and z entries this lane added to since the last flush (empty: klo > khi)
     int t_klo = 255, t_khi = 0, t_zlo = INT_MAX, t_zhi = INT_MIN;
     int sh_p = -1;
@@ -448,8 +484,22 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
             const float pb1 = __int_as_float(start[hend - 1]), pb0 = h > 0 ? __int_as_float(start[h - 1]) : 0.0f;
             const float bnd = (pb1 - pb0) + pb1 * 0x1p-14f;
             const bool same_line = sh_on && pax(h) == sh_p && U0[h] == sh_U0 && dU[h] == sh_dU;
-            // the run continues the sheet if its values fit the sheet's fixed-point range
-            const bool fits = same_line && sh_used + bnd * sh_scale <= kSheetCap;
+            // the run continues the sheet if its values fit the sheet's fixed-point range, else after
+            // a coarsening of the sheet's fixed point that makes them fit (a flush instead when that
+            // would cost the sheet more than 24 bits or leave the float range of the scale)
+            bool fits = same_line && sh_used + bnd * sh_scale <= kSheetCap;
+            if (same_line && !fits) {
+                int e = 0;
+                frexpf(sh_used + bnd * sh_scale, &e);  // the sum of the bounds < 2^e
+                const int sft = max(e - 30, 1);       // then below 2^30 after the coarsening
+                if (sft <= 24 && sh_scale >= 0x1p-96f) {
+                    sheet_rescale(col, cs, sft, t_klo, t_khi, t_zlo, t_zhi, nw, masks);
+                    __syncthreads();
+                    sh_scale = ldexpf(sh_scale, -sft);
+                    sh_used = ldexpf(sh_used, -sft) + 1.0f;  // each entry's rounding adds at most 1/2
+                    fits = true;
+                }
+            }
             if (sh_on && !fits) {
                 sheet_flush(img, col, g, sh_p, sh_U0, sh_dU, 1.0f / sh_scale, t_klo, t_khi, t_zlo, t_zhi, nw, cs,
                             masks);
@@ -465,14 +515,13 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
                 sh_p = pax(h);
                 sh_U0 = U0[h];
                 sh_dU = dU[h];
-                // a power of two that puts the run's bound below 2^30.  A run that reaches the end of
-                // the group may go on in the next group: its bound is first extrapolated to a whole
-                // group of such rays, so that a continuation of that size fits the remaining range.
-                const float est = hend == nvalid ? bnd * ((float)B / (float)len) : bnd;
+                // a power of two that puts the run's bound below 2^30 (later runs of the line coarsen
+                // it when they do not fit)
                 int e = 0;
-                frexpf(est, &e);  // est < 2^e
+                frexpf(bnd, &e);  // bnd < 2^e
                 sh_scale = ldexpf(1.0f, min(max(30 - e, -126), 126));
                 sh_used = 0.0f;
+                res = 0.0f;
             }
             sh_used += bnd * sh_scale;
             // The eight half-waves of the workgroup take the run's rays in turn (half-wave q: rays
@@ -542,10 +591,16 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
                                 const unsigned kb = 4u * (unsigned)k + colb;
                                 const unsigned a0 = __umul24(min((unsigned)j0, (unsigned)nw), cs4) + kb;
                                 const unsigned a1 = __umul24(min((unsigned)(j0 + 1), (unsigned)nw), cs4) + kb;
-                                __hip_atomic_fetch_add(at(a0), round_half_up((1.0f - fw) * v), __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-                                __hip_atomic_fetch_add(at(a1), round_half_up(fw * v), __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                                // the sample's value with the carried remainder, rounded; the first
+                                // entry gets its own share rounded, the second the rest, so that the
+                                // lane's added integers track the exact running sum of its values
+                                const float tv = v + res;
+                                const float qt = rintf(tv);
+                                res = tv - qt;
+                                const int q0 = round_half_up(fmaf(-fw, v, v));
+                                const int q1 = (int)qt - q0;
+                                __hip_atomic_fetch_add(at(a0), q0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                                __hip_atomic_fetch_add(at(a1), q1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                                 t_zlo = min(t_zlo, j0);
                                 t_zhi = max(t_zhi, j0 + 1);
                             } else {
