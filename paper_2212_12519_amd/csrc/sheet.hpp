@@ -37,10 +37,12 @@ constexpr int kRunMin = 2;
 constexpr int kSheetMaxW = 128;  // largest axis-2 size with an LDS sheet
 constexpr int kSheetGroups = 8;  // groups of 256 rays per workgroup (a sheet persists across them)
 // Largest sum of value bounds a sheet takes, in its fixed-point units: 2^31 less room for the
-// rounding of every added value (at most kSheetGroups * 256 additions to one entry, 1/2 each).
+// rounding of every added value (at most kSheetGroups * 256 additions to one entry, 1.5 units each)
+// and of the coarsenings (half a unit each).
 constexpr float kSheetCap = 2147483648.0f - 1048576.0f;
-// Fewest bits a ray's largest value keeps in a sheet's fixed point (its relative rounding error is
-// then at most 2^-(kSheetBits + 1)); rays with smaller values take the direct scatter.
+// Fewest bits a ray's largest value keeps in a sheet's fixed point (an added value is off by at most
+// 1.5 units, 1.5 * 2^-kSheetBits of the ray's largest at worst, and the carried remainders keep sums
+// unbiased); rays with smaller values take the direct scatter.
 constexpr int kSheetBits = 8;
 
 // A value in fixed-point units rounded to the nearest integer, halves up: floor(x + 1/2) in one
