@@ -70,3 +70,41 @@ def test_sheet_dynamic_range(gpu):
         err = rel_l2(got[only], r_all[only])
         print(f"{name}: {int(only.sum())} voxels reached by that class only, rel L2 {err:.2e}")
         assert err <= BACK_TOL, name
+
+
+def test_sheet_coarsening_keeps_sums(gpu):
+    """Forty transaxial lines of 15,000 events each, values growing by six orders of magnitude with the
+    TOF bin (the presort orders a line's events by bin, so the later groups of 256 rays of a line carry
+    larger bounds than the first): the sheet's fixed point is coarsened in place as a line continues
+    across groups, and values are rounded with carried remainders.  Checked against the FP64 oracle:
+    relative L2 over the image and the image sum, which plain rounding of small values would bias."""
+    rng = np.random.default_rng(92)
+    n_line, per = 40, 15_000
+    xs, xe, bins, p = [], [], [], []
+    for a in rng.uniform(0.0, np.pi, size=n_line):
+        d = np.array([np.cos(a), np.sin(a)])
+        nrm = np.array([-d[1], d[0]])
+        off = rng.uniform(-60.0, 60.0)
+        e0, e1 = off * nrm - 300.0 * d, off * nrm + 300.0 * d
+        z = rng.uniform(-28.0, 28.0, size=(per, 2))
+        xs.append(np.column_stack([np.full(per, e0[0]), np.full(per, e0[1]), z[:, 0]]))
+        xe.append(np.column_stack([np.full(per, e1[0]), np.full(per, e1[1]), z[:, 1]]))
+        b = rng.integers(4, 25, size=per)
+        bins.append(b)
+        p.append(10.0 ** ((b - 4) * 0.3) * rng.uniform(0.5, 1.5, size=per))
+    xs, xe = np.concatenate(xs).astype(np.float32), np.concatenate(xe).astype(np.float32)
+    bins, p = np.concatenate(bins).astype(np.int16), np.concatenate(p).astype(np.float32)
+    dev = torch.device("cuda")
+    G = gpu.ImageGeom(DIM, VS, ORIGIN)
+    T = gpu.TofParams(TOF["bin_width"], TOF["sigma"], TOF["n_sigmas"], TOF["n_bins"])
+    xs_d, xe_d, b_d = torch.from_numpy(xs).to(dev), torch.from_numpy(xe).to(dev), torch.from_numpy(bins).to(dev)
+    order = gpu.presort(xs_d, xe_d, G, b_d, T)
+    got = gpu.back_tof_lm(xs_d, xe_d, b_d, G, T, torch.from_numpy(p).to(dev), order=order)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy().astype(np.float64)
+    ref = oracle.back_tof_lm(xs, xe, ORIGIN, VS, DIM, TOF, bins, p.astype(np.float64))
+    err = rel_l2(got, ref)
+    sum_err = abs(got.sum() - ref.sum()) / ref.sum()
+    print(f"{xs.shape[0]} events: rel L2 {err:.2e}, image sum rel error {sum_err:.2e}")
+    assert err <= BACK_TOL
+    assert sum_err <= 1e-5
