@@ -499,6 +499,7 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
                     __syncthreads();
                     sh_scale = ldexpf(sh_scale, -sft);
                     sh_used = ldexpf(sh_used, -sft) + 1.0f;  // each entry's rounding adds at most 1/2
+                    res = ldexpf(res, -sft);                  // the lanes' remainders in the new unit
                     fits = true;
                 }
             }
