@@ -54,7 +54,9 @@
  *     over many values lose nothing systematically; an added value is off by
  *     at most 1.5 units, and every ray in the fixed point adds values of at
  *     least 2^8 units at its largest.  Rays whose values are too small for
- *     that beside the line's others are added in float directly.
+ *     that beside the line's others are added in float directly.  Values
+ *     must be finite: with an infinite or NaN value the result of a back
+ *     projection is unspecified (no memory outside the image is touched).
  *   Zero-length or non-finite rays, and listmode bins outside [0, n_bins),
  *     contribute nothing (no error: they are data).  n == 0 is a no-op.
  *
