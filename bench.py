@@ -213,7 +213,7 @@ def lm_leg(args, pp, C, dev):
         lambda: pp.pp_fill(bimg, 0.0), args.steps, args.warmup)
     # the same projector pair in the events' own (unsorted) order (skipped when profiling the step)
     t_fwd_u = t_back_u = float("nan")
-    crys, per_ray, nontof = {}, {}, {}
+    crys, per_ray, nontof, gathered = {}, {}, {}, {}
     if args.only is None:
         _, t_fwd_u, t_back_u = timed_pairs(lambda: pp.pp_fwd_tof_lm(xs, xe, bins, G, T, img, p),
                                            lambda: pp.pp_back_tof_lm(xs, xe, bins, G, T, bimg, p),
@@ -254,6 +254,19 @@ def lm_leg(args, pp, C, dev):
                   "back_alg_gbs": alg_nt / (nb_ * 1e-3) / 1e9}
         log(f"non-TOF LM: presort {ns_:.2f} ms, fwd {nf:.2f} ms, back {nb_:.2f} ms, "
             f"{n_samples_nt / n_ev:.1f} samples/event")
+        # the events stored in presorted order once (pp_gather_events), then the projector pair without
+        # an order array: the regime of iterative reconstruction, where the order is reused
+        pp.pp_lm_presort(xs, xe, bins, G, T, order, sort_ws)
+        xs_g, xe_g, bins_g = pp.gather_events(xs, xe, bins, order)
+        _, t_gather, _ = timed_pairs(lambda: pp.pp_gather_events(xs, xe, bins, order, xs_g, xe_g, bins_g),
+                                     lambda: None, lambda: None, 3, 1)
+        wall_g, gf, gb = timed_pairs(lambda: pp.pp_fwd_tof_lm(xs_g, xe_g, bins_g, G, T, img, p),
+                                     lambda: pp.pp_back_tof_lm(xs_g, xe_g, bins_g, G, T, bimg, p),
+                                     lambda: pp.pp_fill(bimg, 0.0), 5, 1)
+        gathered = {"t_gather_ms": t_gather, "t_fwd_ms": gf, "t_back_ms": gb, "events_per_s_fwd_back": n_ev / (wall_g / 5)}
+        log(f"TOF-LM on events stored in presorted order: gather {t_gather:.2f} ms (once), fwd {gf:.2f} ms, "
+            f"back {gb:.2f} ms")
+        del xs_g, xe_g, bins_g
     log(f"TOF-LM: presort {t_sort:.2f} ms, fwd {t_fwd:.2f} ms, back {t_back:.2f} ms, wall "
         f"{1e3 * wall / args.steps:.2f} ms/step; unsorted order: fwd {t_fwd_u:.2f} ms back {t_back_u:.2f} ms; "
         f"{n_samples / n_ev:.1f} samples/event")
@@ -268,6 +281,7 @@ def lm_leg(args, pp, C, dev):
         "dominant": dom_name, "achieved_gbs": achieved,
         "fwd_alg_gbs": alg_bytes / (t_fwd * 1e-3) / 1e9, "back_alg_gbs": alg_bytes / (t_back * 1e-3) / 1e9,
         "crystal_index_events": crys, "per_event_tof_params": per_ray, "nontof_listmode": nontof,
+        "presorted_events_stored": gathered,
     }
     return res, (xs, xe, bins, img, G, T)
 
