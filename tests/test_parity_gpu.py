@@ -385,6 +385,7 @@ SHEET_GRIDS = [
     ((300, 40, 16), (1.0, 2.0, 2.0)),  # lines along axis 0 longer than 256 planes: direct path
     ((30, 20, 200), (2.0, 2.0, 0.5)),  # axis 2 longer than the LDS column: direct path only
     ((64, 48, 7), (1.5, 2.0, 2.0)),    # ordinary sheets, short lines
+    ((256, 40, 128), (1.0, 2.0, 1.0)),  # the sheet at its limits: 256-plane lines, 128 z rows (151 KB of LDS)
 ]
 
 
