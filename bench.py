@@ -144,7 +144,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the OSEM serving leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=25.0, help="calibrated oracle time for the CPU baseline")
-    ap.add_argument("--only", default=None, help="profiling helper: lm | sino | sino_osem | res | serve")
+    ap.add_argument("--only", default=None, help="profiling helper: lm | sino | sino_osem | res | serve | autograd")
     ap.add_argument("--serve-requests", type=int, default=None, help="requests in the serving leg (default 256)")
     ap.add_argument("--no-res", action="store_true", help="serving leg without the resolution model")
     ap.add_argument("--write-traffic", nargs="+", metavar="ARG", default=None,
@@ -506,7 +506,7 @@ def main():
     result = {"metric": "TOF listmode fwd+back events/s + OSEM frame p50/p99 latency vs plain"}
     extra = {}
     lm = lm_inputs = None
-    if args.only in (None, "lm"):
+    if args.only in (None, "lm", "autograd"):
         lm, lm_inputs = lm_leg(args, pp, C, dev)
     if args.only is not None:
         # a plain device copy of known size (1 GiB read + 1 GiB written), so hardware byte
@@ -527,8 +527,11 @@ def main():
     if args.only in ("sino", "sino_osem"):
         print(json.dumps(extra))
         return
-    if args.only is None:
+    if args.only in (None, "autograd"):
         extra["autograd"] = autograd_leg(args, pp, C, dev, lm_inputs)
+    if args.only == "autograd":
+        print(json.dumps(extra))
+        return
     if args.only in (None, "res"):
         extra["resolution_model"] = resmodel_leg(args, pp, C, dev)
     if args.only == "res":

@@ -75,7 +75,7 @@
 extern "C" {
 #endif
 
-#define PP_ABI_VERSION 6
+#define PP_ABI_VERSION 7
 
 enum pp_status {
     PP_OK = 0,
@@ -176,6 +176,21 @@ int pp_fwd_tof_lm(const float* xstart, const float* xend, const int16_t* tof_bin
 int pp_fwd_tof_lm_batch(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n_events,
                         const pp_image_t* geom, const pp_tof_t* tof, const float* imgs, int32_t n_img, float* p,
                         const int32_t* order, void* stream);
+
+/* pp_back_tof_lm of the same events for n_img value arrays at once (the
+ * adjoint of pp_fwd_tof_lm_batch, Sec. 2.2): imgs float32
+ * [n_img][dim0][dim1][dim2] += the back projection of p[b] (float32
+ * [n_img][n_events]) into image b.  The rays' setup, compaction and runs are
+ * done once per group of events for all images; each image then gets its own
+ * pass of the sheet (flushed at the end of every group, as the sheet cannot
+ * hold several images), 16 images per launch.  Each image's result equals
+ * pp_back_tof_lm of that image alone up to the rounding of the fixed point
+ * and the order of float atomic adds.  n_img in [0, 2^20] (else
+ * PP_EINVAL_N); n_img == 0 or n_events == 0 is a no-op.  Other arguments and
+ * errors as pp_back_tof_lm. */
+int pp_back_tof_lm_batch(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n_events,
+                         const pp_image_t* geom, const pp_tof_t* tof, float* imgs, int32_t n_img, const float* p,
+                         const int32_t* order, void* stream);
 
 /* TOF listmode back projection, adjoint of pp_fwd_tof_lm: img += A^T p. */
 int pp_back_tof_lm(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n_events,

@@ -6,9 +6,9 @@ back projector A^T.  Both are torch.autograd.Functions whose backward pass is
 the other hand-written kernel: d(Ax)/dx^T g = A^T g and d(A^T y)/dy^T g = A g,
 so the pair is exactly adjoint and double backward works.  Leading batch
 dimensions (images [..., n0, n1, n2] <-> projections [..., n] or [..., n,
-n_bins]) go through the batched listmode forward projection (one pass over
-the events for all images) for the TOF listmode kind, and are looped over
-otherwise.
+n_bins]) go through the batched listmode forward and back projections (one
+pass over the events for all images) for the TOF listmode kind, and are
+looped over otherwise.
 """
 from __future__ import annotations
 
@@ -87,8 +87,11 @@ class JosephOperator:
         if tuple(y.shape[-k:]) != self.proj_shape:
             raise ValueError(f"projection shape {tuple(y.shape[-k:])} != {self.proj_shape}")
         yf = y.reshape(-1, *self.proj_shape)
-        out = torch.stack([self._back1(yf[b]) for b in range(yf.shape[0])]) if yf.shape[0] else \
-            y.new_empty((0, *self.geom.dim))
+        if self.kind == "tof_lm" and yf.shape[0] > 1:  # one batched back projection of all value arrays
+            out = P.back_tof_lm_batch(self.xs, self.xe, self.bins, self.geom, self.tof, yf.contiguous(), self.order)
+        else:
+            out = torch.stack([self._back1(yf[b]) for b in range(yf.shape[0])]) if yf.shape[0] else \
+                y.new_empty((0, *self.geom.dim))
         return out.reshape(*lead, *self.geom.dim)
 
     # differentiable applications

@@ -337,6 +337,21 @@ int pp_fwd_tof_lm_batch(const float* xstart, const float* xend, const int16_t* t
         launch_fwd_tof_lm_batch(coords(xstart, xend), tof_bin, n, g, t, imgs, n_img, p, order, as_stream(stream)));
 }
 
+int pp_back_tof_lm_batch(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n,
+                         const pp_image_t* geom, const pp_tof_t* tof, float* imgs, int32_t n_img, const float* p,
+                         const int32_t* order, void* stream) {
+    GeomK g;
+    TofK t;
+    PP_TRY(make_geom(geom, g));
+    PP_TRY(make_tof(tof, t));
+    PP_TRY(check_n(n));
+    if (n_img < 0 || n_img > (1 << 20)) return PP_EINVAL_N;
+    if (n == 0 || n_img == 0) return PP_OK;
+    if (!xstart || !xend || !tof_bin || !imgs || !p) return PP_EINVAL_PTR;
+    return hip_status(
+        launch_back_tof_lm_batch(coords(xstart, xend), tof_bin, n, g, t, imgs, n_img, p, order, as_stream(stream)));
+}
+
 int pp_back_tof_lm(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n, const pp_image_t* geom,
                    const pp_tof_t* tof, float* img, const float* p, const int32_t* order, void* stream) {
     GeomK g;

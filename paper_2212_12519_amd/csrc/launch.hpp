@@ -28,6 +28,9 @@ hipError_t launch_fwd_tof_lm_batch(const RaySrc& src, const int16_t* bins, int64
                                    const float* imgs, int n_img, float* p, const int32_t* order, hipStream_t s);
 hipError_t launch_back_tof_lm(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g,
                               const TofK& t, float* img, const float* p, const int32_t* order, hipStream_t s);
+hipError_t launch_back_tof_lm_batch(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g,
+                                    const TofK& t, float* imgs, int n_img, const float* p, const int32_t* order,
+                                    hipStream_t s);
 size_t presort_workspace_bytes(int64_t n);
 // capacity of the library-owned presort workspace (one per GPU) and its device address on the
 // current GPU

@@ -49,6 +49,7 @@ __host__ __device__ inline int64_t slot_chunks(int64_t n_events, int32_t n_sub) 
 template <int Form>
 struct ModeOsem {
     static constexpr bool kAux = false;
+    static constexpr bool kBatch = false;
     const float* __restrict__ x;
     const int16_t* __restrict__ bins;
     float bg;

@@ -243,7 +243,7 @@ hipError_t launch_fwd(const RaySrc& src, int64_t n, const GeomK& g, const float*
 // Back projections of ray lists go through the run/sheet kernel (sheet.hpp).
 template <class Mode>
 static hipError_t launch_runs(const Mode& m, const RaySrc& src, int64_t n, const GeomK& g, float* img,
-                              const int32_t* order, hipStream_t s) {
+                              const int32_t* order, hipStream_t s, int n_img = 1, int64_t img_stride = 0) {
     const int nw = (g.n[2] <= kSheetMaxW) ? g.n[2] : 0;
     const size_t lds = SheetLayout::bytes(nw, g);
     hipError_t e = hipFuncSetAttribute((const void*)k_back_runs<Mode>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -256,7 +256,8 @@ static hipError_t launch_runs(const Mode& m, const RaySrc& src, int64_t n, const
         cus = 256;
     int64_t groups = (n + (int64_t)kSheetBlock * 4 * cus - 1) / ((int64_t)kSheetBlock * 4 * cus);
     groups = groups < 1 ? 1 : (groups > kSheetGroups ? kSheetGroups : groups);
-    hipLaunchKernelGGL(k_back_runs<Mode>, dim3(grid_for(n, kSheetBlock * groups)), dim3(kSheetBlock), lds, s, m, src, n, g, img, order, nw, (int)groups);
+    hipLaunchKernelGGL(k_back_runs<Mode>, dim3(grid_for(n, kSheetBlock * groups)), dim3(kSheetBlock), lds, s, m, src, n,
+                       g, img, order, nw, (int)groups, n_img, img_stride);
     return hipGetLastError();
 }
 
@@ -309,6 +310,34 @@ hipError_t launch_back_tof_lm(const RaySrc& src, const int16_t* bins, int64_t n,
     if (form == kFormLut) return launch_runs(ModeTofLm<kFormLut>{p, bins, t}, src, n, g, img, order, s);
     if (form == kFormPoly) return launch_runs(ModeTofLm<kFormPoly>{p, bins, t}, src, n, g, img, order, s);
     return launch_runs(ModeTofLm<kFormErf>{p, bins, t}, src, n, g, img, order, s);
+}
+
+// Images per launch of the batched listmode back projection (each launch walks the events once)
+constexpr int kBackBatch = 16;
+
+hipError_t launch_back_tof_lm_batch(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g,
+                                    const TofK& t, float* imgs, int n_img, const float* p, const int32_t* order,
+                                    hipStream_t s) {
+    const int64_t nv = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    const int form = tof_form(t);
+    const bool per = t.sig_ray || t.off_ray;
+    for (int b0 = 0; b0 < n_img; b0 += kBackBatch) {
+        const int cnt = (n_img - b0 < kBackBatch) ? (n_img - b0) : kBackBatch;
+        float* im = imgs + (int64_t)b0 * nv;
+        const float* pb = p + (int64_t)b0 * n;
+        hipError_t e;
+        if (per) {
+            if (form == kFormLut) e = launch_runs(ModeTofLm<kFormLut, true, true>{pb, bins, t}, src, n, g, im, order, s, cnt, nv);
+            else if (form == kFormPoly) e = launch_runs(ModeTofLm<kFormPoly, true, true>{pb, bins, t}, src, n, g, im, order, s, cnt, nv);
+            else e = launch_runs(ModeTofLm<kFormErf, true, true>{pb, bins, t}, src, n, g, im, order, s, cnt, nv);
+        } else {
+            if (form == kFormLut) e = launch_runs(ModeTofLm<kFormLut, false, true>{pb, bins, t}, src, n, g, im, order, s, cnt, nv);
+            else if (form == kFormPoly) e = launch_runs(ModeTofLm<kFormPoly, false, true>{pb, bins, t}, src, n, g, im, order, s, cnt, nv);
+            else e = launch_runs(ModeTofLm<kFormErf, false, true>{pb, bins, t}, src, n, g, im, order, s, cnt, nv);
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 static int sino_block(int nb) { return nb <= 64 ? 256 : 64; }  // LDS tile <= 64 KiB

@@ -106,6 +106,7 @@ __device__ inline float tof_weight_bound(const TofK& t, float* red) {
 //                    the workgroup calls it (a table is reduced with red[4] of LDS)
 struct ModeNonTof {
     static constexpr bool kAux = false;
+    static constexpr bool kBatch = false;
     const float* __restrict__ p;
     __device__ bool setup(int64_t l, const RaySrc& src, const GeomK& g, RayK& r, float& cv,
                           int& /*aux*/) const {
@@ -122,17 +123,20 @@ struct ModeNonTof {
 
 // Listmode TOF, the weight in form Form (TofForm).  With per-ray TOF parameters (PerRay) the ray's
 // offset is folded into its TOF coordinate at setup and aux carries the bits of its erf argument
-// per mm (TofRay::inv).
-template <int Form, bool PerRay = false>
+// per mm (TofRay::inv).  Batch: several value arrays (p[b][l], value()) for one set of rays; setup
+// then gives the value-free constant (cv for a value of 1) and keeps rays of any value.
+template <int Form, bool PerRay = false, bool Batch = false>
 struct ModeTofLm {
     static constexpr bool kAux = PerRay;
+    static constexpr bool kBatch = Batch;
     const float* __restrict__ p;
     const int16_t* __restrict__ bins;
     TofK t;
+    __device__ float value(int64_t l, int b, int64_t n) const { return p[(int64_t)b * n + l]; }
     __device__ bool setup(int64_t l, const RaySrc& src, const GeomK& g, RayK& r, float& cv,
                           int& aux) const {
         const int b = bins[l];
-        const float pl = p[l];
+        const float pl = Batch ? 1.0f : p[l];
         TofRay q;
         // every condition evaluated (no short circuit), so that all of the ray's loads issue together
         const bool geo = ray_setup(src, l, g, r);
@@ -159,6 +163,7 @@ struct ModeTofLm {
 template <bool Lut, bool PerRay = false>
 struct ModeTofSino {
     static constexpr bool kAux = true;
+    static constexpr bool kBatch = false;
     const float* __restrict__ p;  // [n][n_bins]
     TofK t;
     __device__ bool setup(int64_t l, const RaySrc& src, const GeomK& g, RayK& r, float& cv,
@@ -302,7 +307,8 @@ __device__ __forceinline__ void sheet_flush(float* __restrict__ img, int* col, c
 template <class Mode>
 __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
                                 const GeomK& g, float* __restrict__ img, const int32_t* __restrict__ order,
-                                int nw_lds, int groups, int64_t chunk0, double* smem) {
+                                int nw_lds, int groups, int64_t chunk0, double* smem, int n_img = 1,
+                                int64_t img_stride = 0) {
     constexpr int B = kSheetBlock;
     double* W0 = smem;
     double* dW = W0 + B;
@@ -461,50 +467,201 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
             if (f) list[off + __popcll(bal & ((1ull << lane) - 1ull))] = tid;
             if (tid == 0) list[B] = total;
         }
-        // direct path for the other rays: wave-synchronous, run-combined atomics
-        {
-            const bool d = ok && !in_sheet;
-            const int dlo = d ? r.k_lo : (1 << 30), dhi = d ? r.k_hi : -(1 << 30);
-            const int k0 = wave_min(dlo), k1 = wave_max(dhi);
-            for (int k = k0; k <= k1; ++k) {
-                const bool act = k >= dlo && k <= dhi;
-                Stencil stn{};
-                float v = 0.0f;
-                if (act) {
-                    stn = stencil_at(r, k);
-                    v = m.sample(fma((double)k, r.ds, r.s0), cv, ax);
+        // the images of the call: one, or (batch modes) n_img, each with its own values, sharing the
+        // rays' setup, compaction and runs; a batch flushes its sheet at the end of every image's pass
+        for (int bi = 0; bi < (Mode::kBatch ? n_img : 1); ++bi) {
+            float* const imgb = img + (int64_t)bi * img_stride;
+            float cvb = cv;
+            if constexpr (Mode::kBatch) {
+                // this image's values and the inclusive prefix of their bounds (as at the group's start)
+                cvb = ok ? cv * m.value(l, bi, n) : 0.0f;
+                float pb = ok ? m.mag(cvb, ax) * wb : 0.0f;
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    const float o = __shfl_up(pb, off, 64);
+                    if (lane >= off) pb += o;
                 }
-                wave_stencil_scatter(img, act && v != 0.0f, r, stn, v);
+                if (lane == 63) wsum[wave] = pb;
+                __syncthreads();  // also: the previous image's readers of cvs[] and start[] are done
+                for (int w = 0; w < wave; ++w) pb += wsum[w];
+                if (ok) {
+                    cvs[cp] = cvb;
+                    start[cp] = __float_as_int(pb);
+                }
             }
-        }
-        __syncthreads();
-        const int n_long = list[B];
-        for (int li = 0; li < n_long; ++li) {
-            const int h = list[li];
-            const int len = cnt[h], hend = h + len;
-            // bound of the run's added values (margin for the rounding of the two prefix sums)
-            const float pb1 = __int_as_float(start[hend - 1]), pb0 = h > 0 ? __int_as_float(start[h - 1]) : 0.0f;
-            const float bnd = (pb1 - pb0) + pb1 * 0x1p-14f;
-            const bool same_line = sh_on && pax(h) == sh_p && U0[h] == sh_U0 && dU[h] == sh_dU;
-            // the run continues the sheet if its values fit the sheet's fixed-point range, else after
-            // a coarsening of the sheet's fixed point that makes them fit (a flush instead when that
-            // would cost the sheet more than 24 bits or leave the float range of the scale)
-            bool fits = same_line && sh_used + bnd * sh_scale <= kSheetCap;
-            if (same_line && !fits) {
-                int e = 0;
-                frexpf(sh_used + bnd * sh_scale, &e);  // the sum of the bounds < 2^e
-                const int sft = max(e - 30, 1);       // then below 2^30 after the coarsening
-                if (sft <= 24 && sh_scale >= 0x1p-96f) {
-                    sheet_rescale(col, cs, sft, t_klo, t_khi, t_zlo, t_zhi, nw, masks);
+            // direct path for the other rays: wave-synchronous, run-combined atomics
+            {
+                const bool d = ok && !in_sheet;
+                const int dlo = d ? r.k_lo : (1 << 30), dhi = d ? r.k_hi : -(1 << 30);
+                const int k0 = wave_min(dlo), k1 = wave_max(dhi);
+                for (int k = k0; k <= k1; ++k) {
+                    const bool act = k >= dlo && k <= dhi;
+                    Stencil stn{};
+                    float v = 0.0f;
+                    if (act) {
+                        stn = stencil_at(r, k);
+                        v = m.sample(fma((double)k, r.ds, r.s0), cvb, ax);
+                    }
+                    wave_stencil_scatter(imgb, act && v != 0.0f, r, stn, v);
+                }
+            }
+            __syncthreads();
+            const int n_long = list[B];
+            for (int li = 0; li < n_long; ++li) {
+                const int h = list[li];
+                const int len = cnt[h], hend = h + len;
+                // bound of the run's added values (margin for the rounding of the two prefix sums)
+                const float pb1 = __int_as_float(start[hend - 1]), pb0 = h > 0 ? __int_as_float(start[h - 1]) : 0.0f;
+                const float bnd = (pb1 - pb0) + pb1 * 0x1p-14f;
+                const bool same_line = sh_on && pax(h) == sh_p && U0[h] == sh_U0 && dU[h] == sh_dU;
+                // the run continues the sheet if its values fit the sheet's fixed-point range, else after
+                // a coarsening of the sheet's fixed point that makes them fit (a flush instead when that
+                // would cost the sheet more than 24 bits or leave the float range of the scale)
+                bool fits = same_line && sh_used + bnd * sh_scale <= kSheetCap;
+                if (same_line && !fits) {
+                    int e = 0;
+                    frexpf(sh_used + bnd * sh_scale, &e);  // the sum of the bounds < 2^e
+                    const int sft = max(e - 30, 1);       // then below 2^30 after the coarsening
+                    if (sft <= 24 && sh_scale >= 0x1p-96f) {
+                        sheet_rescale(col, cs, sft, t_klo, t_khi, t_zlo, t_zhi, nw, masks);
+                        __syncthreads();
+                        sh_scale = ldexpf(sh_scale, -sft);
+                        sh_used = ldexpf(sh_used, -sft) + 1.0f;  // each entry's rounding adds at most 1/2
+                        res = ldexpf(res, -sft);                  // the lanes' remainders in the new unit
+                        fits = true;
+                    }
+                }
+                if (sh_on && !fits) {
+                    sheet_flush(imgb, col, g, sh_p, sh_U0, sh_dU, 1.0f / sh_scale, t_klo, t_khi, t_zlo, t_zhi, nw, cs,
+                                masks);
+                    t_klo = 255;
+                    t_khi = 0;
+                    t_zlo = INT_MAX;
+                    t_zhi = INT_MIN;
                     __syncthreads();
-                    sh_scale = ldexpf(sh_scale, -sft);
-                    sh_used = ldexpf(sh_used, -sft) + 1.0f;  // each entry's rounding adds at most 1/2
-                    res = ldexpf(res, -sft);                  // the lanes' remainders in the new unit
-                    fits = true;
+                    sh_on = false;
                 }
+                if (!sh_on) {
+                    sh_on = true;
+                    sh_p = pax(h);
+                    sh_U0 = U0[h];
+                    sh_dU = dU[h];
+                    // a power of two that puts the run's bound below 2^30 (later runs of the line coarsen
+                    // it when they do not fit)
+                    int e = 0;
+                    frexpf(bnd, &e);  // bnd < 2^e
+                    sh_scale = ldexpf(1.0f, min(max(30 - e, -126), 126));
+                    sh_used = 0.0f;
+                    res = 0.0f;
+                }
+                sh_used += bnd * sh_scale;
+                // The eight half-waves of the workgroup take the run's rays in turn (half-wave q: rays
+                // h + q, h + q + 8, ...); a half-wave walks its ray's plane window 32 planes per step,
+                // lane i at plane k_lo + i + 32 c, and adds the two W-interpolated values of each sample
+                // to the column entries (j0, k) and (j0 + 1, k) with LDS atomics.  A ray's window fills
+                // its steps up to the last one (about 95% of the lanes carry a sample on clinical TOF
+                // windows), and the waves share no plane ownership, so they need no barrier until the
+                // flush.  Entries outside the grid (j = -1, j = nw, the conservative end planes) go to
+                // the spare row nw, which is never flushed.
+                const int half = lane >> 5, hl = lane & 31;
+                typedef __attribute__((address_space(3))) int lds_int;
+                // LDS byte addresses: row j of plane k at col + 4 (j cs + k)
+                const unsigned cs4 = 4u * (unsigned)cs;
+                const unsigned colb = (unsigned)(uintptr_t)(__attribute__((address_space(3))) char*)col;
+                auto at = [&](unsigned addr) { return (lds_int*)(uintptr_t)addr; };
+                // a half-wave's ray: its records, read one ray ahead of its steps (a ray index past the
+                // run reads the run head's records and gets an empty window)
+                struct Rec {
+                    double W0, dW, s0, ds;
+                    float cv, mg;  // mg: the ray's bound of |an added value| (a difference of the prefix)
+                    int ax, lh;
+                };
+                auto load = [&](int ra) {
+                    const int r = ra + half < hend ? ra + half : h;
+                    const float pr0 = r > 0 ? __int_as_float(start[r - 1]) : 0.0f;
+                    Rec q{W0[r], dW[r], s0[r], ds[r], cvs[r], __int_as_float(start[r]) - pr0, Mode::kAux ? aux[r] : 0,
+                          lohi[r]};
+                    if (ra + half >= hend) q.lh = 0xff;  // k_lo 255 > k_hi 0: no planes
+                    return q;
+                };
+                // the line's in-plane stencil terms, for rays that add to the image directly
+                const int sp = g.stride[sh_p], su = g.stride[sh_p == 0 ? 1 : 0], nu = g.n[sh_p == 0 ? 1 : 0];
+                const float inv_scale = 1.0f / sh_scale;
+                Rec cur = load(h + 2 * wave);
+                // wait for these reads here: the loop then sees them complete on every path and its steps
+                // carry no LDS wait (which, LDS operations completing in order, would also wait for the
+                // previous step's adds)
+                __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+                for (int ra = h + 2 * wave; ra < hend; ra += 8) {  // wave-uniform
+                    const Rec nxt = load(ra + 8);
+                    // a compiler-only barrier: keeps the prefetch here rather than next to its use
+                    asm volatile("" ::: "memory");
+                    const int klo = cur.lh & 0xff, khi = (cur.lh >> 8) & 0xff;
+                    const float cvs_ = cur.cv * sh_scale;  // the sample values in fixed-point units
+                    // a ray whose values would keep fewer than kSheetBits bits in the sheet's fixed point
+                    // (far smaller values than the run's others) adds them to the image directly, with the
+                    // direct path's float atomics
+                    const bool direct = cur.mg * sh_scale < (float)(1 << kSheetBits);
+                    if (klo <= khi) {
+                        t_klo = min(t_klo, klo);
+                        t_khi = max(t_khi, khi);
+                    }
+                    // planes - 1 of the longer of the two rays (wave-uniform)
+                    const int span = max(__builtin_amdgcn_readlane(khi - klo, 0), __builtin_amdgcn_readlane(khi - klo, 32));
+                    // the samples of the two rays, 32 planes per step; Mixed: some lane adds directly
+                    auto steps = [&](auto mixed) {
+                        for (int c = 0; c <= span; c += 32) {
+                            const int k = klo + hl + c;
+                            if (k <= khi) {
+                                const double W = fma((double)k, cur.dW, cur.W0);
+                                const double fj = floor(W);
+                                const int j0 = (int)fj;
+                                const float fw = (float)(W - fj);
+                                const float v = m.sample(fma((double)k, cur.ds, cur.s0), cvs_, cur.ax);
+                                if (!decltype(mixed)::value || !direct) {
+                                    const unsigned kb = 4u * (unsigned)k + colb;
+                                    const unsigned a0 = __umul24(min((unsigned)j0, (unsigned)nw), cs4) + kb;
+                                    const unsigned a1 = __umul24(min((unsigned)(j0 + 1), (unsigned)nw), cs4) + kb;
+                                    // the sample's value with the carried remainder, rounded; the first
+                                    // entry gets its own share rounded, the second the rest, so that the
+                                    // lane's added integers track the exact running sum of its values
+                                    const float tv = v + res;
+                                    const float qt = rintf(tv);
+                                    res = tv - qt;
+                                    const int q0 = round_half_up(fmaf(-fw, v, v));
+                                    const int q1 = (int)qt - q0;
+                                    __hip_atomic_fetch_add(at(a0), q0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                                    __hip_atomic_fetch_add(at(a1), q1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                                    t_zlo = min(t_zlo, j0);
+                                    t_zhi = max(t_zhi, j0 + 1);
+                                } else {
+                                    const float vf = v * inv_scale;  // exact: the scale is a power of two
+                                    const double U = fma((double)k, sh_dU, sh_U0);
+                                    const double fi = floor(U);
+                                    const int i0 = (int)fi;
+                                    const float fu = (float)(U - fi), gu = 1.0f - fu, gw = 1.0f - fw;
+                                    const int base = k * sp + i0 * su + j0;
+                                    const bool i0ok = (unsigned)i0 < (unsigned)nu, i1ok = (unsigned)(i0 + 1) < (unsigned)nu;
+                                    const bool j0ok = (unsigned)j0 < (unsigned)nw, j1ok = (unsigned)(j0 + 1) < (unsigned)nw;
+                                    if (i0ok && j0ok) unsafeAtomicAdd(imgb + base, gu * gw * vf);
+                                    if (i0ok && j1ok) unsafeAtomicAdd(imgb + base + 1, gu * fw * vf);
+                                    if (i1ok && j0ok) unsafeAtomicAdd(imgb + base + su, fu * gw * vf);
+                                    if (i1ok && j1ok) unsafeAtomicAdd(imgb + base + su + 1, fu * fw * vf);
+                                }
+                            }
+                        }
+                    };
+                    if (__ballot(direct && klo <= khi))
+                        steps(std::integral_constant<bool, true>{});
+                    else
+                        steps(std::integral_constant<bool, false>{});
+                    cur = nxt;
+                }
+                // no barrier between runs of one line: the adds are atomic, and the columns are read
+                // only in a flush, whose first barrier follows every wave's last add
             }
-            if (sh_on && !fits) {
-                sheet_flush(img, col, g, sh_p, sh_U0, sh_dU, 1.0f / sh_scale, t_klo, t_khi, t_zlo, t_zhi, nw, cs,
+            if (Mode::kBatch && sh_on) {
+                sheet_flush(imgb, col, g, sh_p, sh_U0, sh_dU, 1.0f / sh_scale, t_klo, t_khi, t_zlo, t_zhi, nw, cs,
                             masks);
                 t_klo = 255;
                 t_khi = 0;
@@ -513,137 +670,20 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
                 __syncthreads();
                 sh_on = false;
             }
-            if (!sh_on) {
-                sh_on = true;
-                sh_p = pax(h);
-                sh_U0 = U0[h];
-                sh_dU = dU[h];
-                // a power of two that puts the run's bound below 2^30 (later runs of the line coarsen
-                // it when they do not fit)
-                int e = 0;
-                frexpf(bnd, &e);  // bnd < 2^e
-                sh_scale = ldexpf(1.0f, min(max(30 - e, -126), 126));
-                sh_used = 0.0f;
-                res = 0.0f;
-            }
-            sh_used += bnd * sh_scale;
-            // The eight half-waves of the workgroup take the run's rays in turn (half-wave q: rays
-            // h + q, h + q + 8, ...); a half-wave walks its ray's plane window 32 planes per step,
-            // lane i at plane k_lo + i + 32 c, and adds the two W-interpolated values of each sample
-            // to the column entries (j0, k) and (j0 + 1, k) with LDS atomics.  A ray's window fills
-            // its steps up to the last one (about 95% of the lanes carry a sample on clinical TOF
-            // windows), and the waves share no plane ownership, so they need no barrier until the
-            // flush.  Entries outside the grid (j = -1, j = nw, the conservative end planes) go to
-            // the spare row nw, which is never flushed.
-            const int half = lane >> 5, hl = lane & 31;
-            typedef __attribute__((address_space(3))) int lds_int;
-            // LDS byte addresses: row j of plane k at col + 4 (j cs + k)
-            const unsigned cs4 = 4u * (unsigned)cs;
-            const unsigned colb = (unsigned)(uintptr_t)(__attribute__((address_space(3))) char*)col;
-            auto at = [&](unsigned addr) { return (lds_int*)(uintptr_t)addr; };
-            // a half-wave's ray: its records, read one ray ahead of its steps (a ray index past the
-            // run reads the run head's records and gets an empty window)
-            struct Rec {
-                double W0, dW, s0, ds;
-                float cv, mg;  // mg: the ray's bound of |an added value| (a difference of the prefix)
-                int ax, lh;
-            };
-            auto load = [&](int ra) {
-                const int r = ra + half < hend ? ra + half : h;
-                const float pr0 = r > 0 ? __int_as_float(start[r - 1]) : 0.0f;
-                Rec q{W0[r], dW[r], s0[r], ds[r], cvs[r], __int_as_float(start[r]) - pr0, Mode::kAux ? aux[r] : 0,
-                      lohi[r]};
-                if (ra + half >= hend) q.lh = 0xff;  // k_lo 255 > k_hi 0: no planes
-                return q;
-            };
-            // the line's in-plane stencil terms, for rays that add to the image directly
-            const int sp = g.stride[sh_p], su = g.stride[sh_p == 0 ? 1 : 0], nu = g.n[sh_p == 0 ? 1 : 0];
-            const float inv_scale = 1.0f / sh_scale;
-            Rec cur = load(h + 2 * wave);
-            // wait for these reads here: the loop then sees them complete on every path and its steps
-            // carry no LDS wait (which, LDS operations completing in order, would also wait for the
-            // previous step's adds)
-            __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
-            for (int ra = h + 2 * wave; ra < hend; ra += 8) {  // wave-uniform
-                const Rec nxt = load(ra + 8);
-                // a compiler-only barrier: keeps the prefetch here rather than next to its use
-                asm volatile("" ::: "memory");
-                const int klo = cur.lh & 0xff, khi = (cur.lh >> 8) & 0xff;
-                const float cvs_ = cur.cv * sh_scale;  // the sample values in fixed-point units
-                // a ray whose values would keep fewer than kSheetBits bits in the sheet's fixed point
-                // (far smaller values than the run's others) adds them to the image directly, with the
-                // direct path's float atomics
-                const bool direct = cur.mg * sh_scale < (float)(1 << kSheetBits);
-                if (klo <= khi) {
-                    t_klo = min(t_klo, klo);
-                    t_khi = max(t_khi, khi);
-                }
-                // planes - 1 of the longer of the two rays (wave-uniform)
-                const int span = max(__builtin_amdgcn_readlane(khi - klo, 0), __builtin_amdgcn_readlane(khi - klo, 32));
-                // the samples of the two rays, 32 planes per step; Mixed: some lane adds directly
-                auto steps = [&](auto mixed) {
-                    for (int c = 0; c <= span; c += 32) {
-                        const int k = klo + hl + c;
-                        if (k <= khi) {
-                            const double W = fma((double)k, cur.dW, cur.W0);
-                            const double fj = floor(W);
-                            const int j0 = (int)fj;
-                            const float fw = (float)(W - fj);
-                            const float v = m.sample(fma((double)k, cur.ds, cur.s0), cvs_, cur.ax);
-                            if (!decltype(mixed)::value || !direct) {
-                                const unsigned kb = 4u * (unsigned)k + colb;
-                                const unsigned a0 = __umul24(min((unsigned)j0, (unsigned)nw), cs4) + kb;
-                                const unsigned a1 = __umul24(min((unsigned)(j0 + 1), (unsigned)nw), cs4) + kb;
-                                // the sample's value with the carried remainder, rounded; the first
-                                // entry gets its own share rounded, the second the rest, so that the
-                                // lane's added integers track the exact running sum of its values
-                                const float tv = v + res;
-                                const float qt = rintf(tv);
-                                res = tv - qt;
-                                const int q0 = round_half_up(fmaf(-fw, v, v));
-                                const int q1 = (int)qt - q0;
-                                __hip_atomic_fetch_add(at(a0), q0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                                __hip_atomic_fetch_add(at(a1), q1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                                t_zlo = min(t_zlo, j0);
-                                t_zhi = max(t_zhi, j0 + 1);
-                            } else {
-                                const float vf = v * inv_scale;  // exact: the scale is a power of two
-                                const double U = fma((double)k, sh_dU, sh_U0);
-                                const double fi = floor(U);
-                                const int i0 = (int)fi;
-                                const float fu = (float)(U - fi), gu = 1.0f - fu, gw = 1.0f - fw;
-                                const int base = k * sp + i0 * su + j0;
-                                const bool i0ok = (unsigned)i0 < (unsigned)nu, i1ok = (unsigned)(i0 + 1) < (unsigned)nu;
-                                const bool j0ok = (unsigned)j0 < (unsigned)nw, j1ok = (unsigned)(j0 + 1) < (unsigned)nw;
-                                if (i0ok && j0ok) unsafeAtomicAdd(img + base, gu * gw * vf);
-                                if (i0ok && j1ok) unsafeAtomicAdd(img + base + 1, gu * fw * vf);
-                                if (i1ok && j0ok) unsafeAtomicAdd(img + base + su, fu * gw * vf);
-                                if (i1ok && j1ok) unsafeAtomicAdd(img + base + su + 1, fu * fw * vf);
-                            }
-                        }
-                    }
-                };
-                if (__ballot(direct && klo <= khi))
-                    steps(std::integral_constant<bool, true>{});
-                else
-                    steps(std::integral_constant<bool, false>{});
-                cur = nxt;
-            }
-            // no barrier between runs of one line: the adds are atomic, and the columns are read
-            // only in a flush, whose first barrier follows every wave's last add
         }
     }
     if (sh_on) sheet_flush(img, col, g, sh_p, sh_U0, sh_dU, 1.0f / sh_scale, t_klo, t_khi, t_zlo, t_zhi, nw, cs, masks);
     __syncthreads();  // the LDS may be reused by the caller
 }
 
+// (batch modes: n_img images at img + b * img_stride, values p[b][l])
 template <class Mode>
 __global__ void __launch_bounds__(kSheetBlock) k_back_runs(Mode m, RaySrc src, int64_t n, GeomK g,
                                                           float* __restrict__ img, const int32_t* __restrict__ order,
-                                                          int nw_lds, int groups) {
+                                                          int nw_lds, int groups, int n_img, int64_t img_stride) {
     extern __shared__ double smem[];
     const int64_t chunk0 = (int64_t)blockIdx.x * groups * kSheetBlock;
-    back_runs_chunk(m, src, n, g, img, order, nw_lds, groups, chunk0, smem);
+    back_runs_chunk(m, src, n, g, img, order, nw_lds, groups, chunk0, smem, n_img, img_stride);
 }
 
 }  // namespace ppmi

@@ -97,6 +97,23 @@ def pp_fwd_tof_lm_batch(xstart, xend, tof_bin, geom, tof, imgs, p, order=None):
     return p
 
 
+def pp_back_tof_lm_batch(xstart, xend, tof_bin, geom, tof, imgs, p, order=None):
+    """pp_back_tof_lm for a batch of value arrays: imgs [B, *dim] += A^T p[b] for p [B, n]."""
+    g, t = as_geom(geom), as_tof(tof)
+    _dev(xstart, xend, tof_bin, imgs, p, order, t.sigma_per_ray, t.offset_per_ray)
+    n = _rays(xstart, xend)
+    _bins(tof_bin, n)
+    _order(order, n)
+    if imgs.dtype != torch.float32 or imgs.numel() % g.n_vox:
+        raise ValueError(f"imgs must be float32 [B, {g.n_vox} voxels]")
+    nb = imgs.numel() // g.n_vox
+    if p.dtype != torch.float32 or p.numel() != nb * n:
+        raise ValueError("p must be float32 [B, n]")
+    check(load().pp_back_tof_lm_batch(ptr(xstart), ptr(xend), ptr(tof_bin), n, g.c(), t.c(n), ptr(imgs), nb, ptr(p),
+                                      ptr(order), stream_of(p)))
+    return imgs
+
+
 def pp_back_tof_lm(xstart, xend, tof_bin, geom, tof, img, p, order=None):
     """TOF listmode back projection, img += A^T p."""
     g, t = as_geom(geom), as_tof(tof)
@@ -293,6 +310,15 @@ def back_tof_sino(xstart, xend, geom, tof, p, img=None):
 def fwd_tof_lm(xstart, xend, tof_bin, geom, tof, img, order=None):
     p = torch.empty(xstart.shape[0], dtype=torch.float32, device=xstart.device)
     return pp_fwd_tof_lm(xstart, xend, tof_bin, geom, tof, img, p, order)
+
+
+def back_tof_lm_batch(xstart, xend, tof_bin, geom, tof, p, order=None):
+    """p [B, n] -> back projections [B, *dim] (new tensors)."""
+    g = as_geom(geom)
+    p = p.contiguous()
+    nb = p.shape[0]
+    imgs = torch.zeros((nb, *g.dim), dtype=torch.float32, device=p.device)
+    return pp_back_tof_lm_batch(xstart, xend, tof_bin, geom, tof, imgs, p, order)
 
 
 def fwd_tof_lm_batch(xstart, xend, tof_bin, geom, tof, imgs, order=None):

@@ -30,7 +30,7 @@ def test_exports_every_declared_symbol(lib):
     assert len(names) >= 12, names
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.pp_abi_version() == 6
+    assert lib.pp_abi_version() == 7
     # the entry points the boundary is specified with: the six projectors, the batched OSEM pair
     for n in ("pp_fwd", "pp_back", "pp_fwd_tof_sino", "pp_back_tof_sino", "pp_fwd_tof_lm", "pp_back_tof_lm",
               "pp_lm_osem_subset_batched", "pp_osem_update_batched", "pp_strerror", "pp_abi_version",
@@ -93,6 +93,14 @@ def test_error_codes(lib):
         assert lib.pp_lm_osem_subset_batched(DUMMY, 3, g, t, None) == PP_EINVAL_TOF
         assert lib.pp_fwd_tof_lm(DUMMY, DUMMY, DUMMY, 0, g, t, DUMMY, DUMMY, None, None) == PP_OK
     assert lib.pp_fwd_tof_lm(DUMMY, DUMMY, None, 5, g, _tof(), DUMMY, DUMMY, None, None) == PP_EINVAL_PTR
+    # batched listmode projections: image count range, pointers, empty batches
+    for f in (lib.pp_fwd_tof_lm_batch, lib.pp_back_tof_lm_batch):
+        assert f(DUMMY, DUMMY, DUMMY, 5, g, _tof(), DUMMY, -1, DUMMY, None, None) == PP_EINVAL_N
+        assert f(DUMMY, DUMMY, DUMMY, 5, g, _tof(), DUMMY, (1 << 20) + 1, DUMMY, None, None) == PP_EINVAL_N
+        assert f(DUMMY, DUMMY, DUMMY, 5, g, _tof(), None, 2, DUMMY, None, None) == PP_EINVAL_PTR
+        assert f(DUMMY, DUMMY, DUMMY, 5, g, _tof(), DUMMY, 2, None, None, None) == PP_EINVAL_PTR
+        assert f(DUMMY, DUMMY, DUMMY, 5, g, _tof(), DUMMY, 0, DUMMY, None, None) == PP_OK
+        assert f(DUMMY, DUMMY, DUMMY, 0, g, _tof(), DUMMY, 2, DUMMY, None, None) == PP_OK
     # crystal-index events: table size, pointers, 8-byte alignment of the pairs
     assert lib.pp_fwd_crystals(DUMMY, 0, DUMMY, 5, g, DUMMY2, DUMMY3, None, None) == PP_EINVAL_N
     assert lib.pp_fwd_crystals(None, 10, DUMMY, 5, g, DUMMY2, DUMMY3, None, None) == PP_EINVAL_PTR
