@@ -77,7 +77,7 @@ def profiled_kernel_bytes(which, kernel):
     k = rec.get("kernels", {}).get(kernel)
     return k["traffic_bytes"] if k else None
 # the device kernel each timed entry point of the listmode step launches
-KERNEL_OF = {"pp_lm_presort": "ppmi::k_lm_keys", "pp_fwd_tof_lm": "ppmi::k_fwd_tof_lm<2, false>",
+KERNEL_OF = {"pp_lm_presort": "ppmi::k_lm_keys<unsigned int>", "pp_fwd_tof_lm": "ppmi::k_fwd_tof_lm<2, false>",
              "pp_back_tof_lm": "ppmi::k_back_runs<ppmi::ModeTofLm<2, false, false> >"}
 
 
