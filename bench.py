@@ -5,9 +5,12 @@ Workload (one step = one pass of the projector pair over one batch):
   ellipsoid/lesion phantom (scanner radius 410 mm, 64 rings x 760 crystals,
   ring difference <= 20, 400 radial bins), image 215 x 215 x 71 voxels of
   1.65 x 1.65 x 2.0 mm, 29 TOF bins of 28 mm, Gaussian FWHM 58.5 mm truncated
-  at 3 sigma.  A step zeroes the back-projection image, runs pp_fwd_tof_lm
-  over all events and pp_back_tof_lm of the result.  Inputs are resident in
-  HBM before timing starts.
+  at 3 sigma.  A step zeroes the back-projection image, presorts the unsorted
+  events (pp_lm_presort), runs pp_fwd_tof_lm_gather over all events in that
+  order (the projections, and the events with their projections written in
+  processing order) and pp_back_tof_lm of the result on those copies (read
+  contiguously, no order array).  Inputs are resident in HBM before timing
+  starts.
 
 Prints ONE JSON line (see the field list in the design notes): value =
 events / s over the timed steps, a live roofline figure for the dominant
@@ -77,7 +80,7 @@ def profiled_kernel_bytes(which, kernel):
     k = rec.get("kernels", {}).get(kernel)
     return k["traffic_bytes"] if k else None
 # the device kernel each timed entry point of the listmode step launches
-KERNEL_OF = {"pp_lm_presort": "ppmi::k_lm_keys<unsigned int>", "pp_fwd_tof_lm": "ppmi::k_fwd_tof_lm<2, false>",
+KERNEL_OF = {"pp_lm_presort": "ppmi::k_lm_keys<unsigned int>", "pp_fwd_tof_lm_gather": "ppmi::k_fwd_tof_lm<2, false, true>",
              "pp_back_tof_lm": "ppmi::k_back_runs<ppmi::ModeTofLm<2, false, false> >"}
 
 
@@ -205,12 +208,16 @@ def lm_leg(args, pp, C, dev):
     order = torch.empty(n_ev, dtype=torch.int32, device=dev)
     sort_ws = pp.presort_workspace(n_ev, dev)
 
-    # one step: presort the unsorted batch, forward project in that order, back project
+    # one step: presort the unsorted batch; forward project in that order, the projection also writing
+    # the events and their values in that order (the gather fused into the forward, which reads every
+    # event anyway); back project those copies, which the back projection then reads contiguously
+    xs_s, xe_s, bins_s, p_s = torch.empty_like(xs), torch.empty_like(xe), torch.empty_like(bins), torch.empty_like(p)
     wall, (t_sort, t_fwd, t_back) = timed_phases(
         [lambda: pp.pp_lm_presort(xs, xe, bins, G, T, order, sort_ws),
-         lambda: pp.pp_fwd_tof_lm(xs, xe, bins, G, T, img, p, order),
-         lambda: pp.pp_back_tof_lm(xs, xe, bins, G, T, bimg, p, order)],
+         lambda: pp.pp_fwd_tof_lm_gather(xs, xe, bins, G, T, img, p, order, xs_s, xe_s, bins_s, p_s),
+         lambda: pp.pp_back_tof_lm(xs_s, xe_s, bins_s, G, T, bimg, p_s)],
         lambda: pp.pp_fill(bimg, 0.0), args.steps, args.warmup)
+    del xs_s, xe_s, bins_s, p_s
     # the same projector pair in the events' own (unsorted) order (skipped when profiling the step)
     t_fwd_u = t_back_u = float("nan")
     crys, per_ray, nontof, gathered = {}, {}, {}, {}
@@ -272,7 +279,7 @@ def lm_leg(args, pp, C, dev):
         f"{n_samples / n_ev:.1f} samples/event")
     per_event = 24 + 2 + 4  # endpoints, bin, projection value
     alg_bytes = per_event * n_ev + 16 * n_samples
-    dom_name, dom_ms = ("pp_back_tof_lm", t_back) if t_back >= t_fwd else ("pp_fwd_tof_lm", t_fwd)
+    dom_name, dom_ms = ("pp_back_tof_lm", t_back) if t_back >= t_fwd else ("pp_fwd_tof_lm_gather", t_fwd)
     achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
     res = {
         "n_events": n_ev, "wall_s": wall, "t_presort_ms": t_sort, "t_fwd_ms": t_fwd, "t_back_ms": t_back,
@@ -553,7 +560,8 @@ def main():
         "value": value, "unit": "events/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * lm["wall_s"] / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "TOF listmode fwd+back, 40M unsorted events (step = presort + fwd + back), clinical "
+        "config": {"workload": "TOF listmode fwd+back, 40M unsorted events (step = presort + fwd writing the events in "
+                               "processing order + back of those), clinical "
                                "phantom 215x215x71 @ 1.65x1.65x2.0 mm, 29 TOF bins x 28 mm, FWHM 58.5 mm, 3 sigma",
                    "n_events": lm["n_events"], "image": list(C.GRID_CLIN.dim), "tof_bins": C.TOF_CLIN.n_bins},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",

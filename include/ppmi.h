@@ -75,7 +75,7 @@
 extern "C" {
 #endif
 
-#define PP_ABI_VERSION 7
+#define PP_ABI_VERSION 8
 
 enum pp_status {
     PP_OK = 0,
@@ -162,6 +162,23 @@ int pp_back_tof_sino(const float* xstart, const float* xend, int64_t n_lors, con
 int pp_fwd_tof_lm(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n_events,
                   const pp_image_t* geom, const pp_tof_t* tof, const float* img, float* p, const int32_t* order,
                   void* stream);
+
+/* pp_fwd_tof_lm (p[e] for every event e, the same values) that also writes
+ * the events and their projections in processing order -- pp_gather_events
+ * fused into the projection, which reads every event anyway:
+ *   xstart_out[i] = xstart[order[i]], xend_out[i] = xend[order[i]]  ([n][3]),
+ *   tof_bin_out[i] = tof_bin[order[i]], p_out[i] = p[order[i]]      ([n]),
+ * so that a following pp_back_tof_lm(xstart_out, xend_out, tof_bin_out, ...,
+ * p_out or other values in that order, order = NULL) walks the events in
+ * the same order without gathering them (Sec. 4's presorting, kept for the
+ * rest of an iteration).  order is required (e.g. from pp_lm_presort); an
+ * entry outside [0, n) gives event i and the value 0 at position i.  All
+ * pointers DEVICE; outputs must not overlap the inputs.  Errors as
+ * pp_fwd_tof_lm, and PP_EINVAL_PTR for a NULL order or output,
+ * PP_EINVAL_TOF with per-event TOF arrays (which are not reordered). */
+int pp_fwd_tof_lm_gather(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n_events,
+                         const pp_image_t* geom, const pp_tof_t* tof, const float* img, float* p, const int32_t* order,
+                         float* xstart_out, float* xend_out, int16_t* tof_bin_out, float* p_out, void* stream);
 
 /* pp_fwd_tof_lm of the same events through n_img images of the grid at once
  * (a batch of images, as in networks that project several images per step,

@@ -159,6 +159,7 @@ def load():
         "pp_fwd_tof_lm": [P, P, P, I64, G, T, P, P, P, P],
         "pp_back_tof_lm": [P, P, P, I64, G, T, P, P, P, P],
         "pp_fwd_tof_lm_batch": [P, P, P, I64, G, T, P, I32, P, P, P],
+        "pp_fwd_tof_lm_gather": [P, P, P, I64, G, T, P, P, P, P, P, P, P, P],
         "pp_back_tof_lm_batch": [P, P, P, I64, G, T, P, I32, P, P, P],
         "pp_lm_presort": [P, P, P, I64, G, T, I32, P, P, ctypes.c_size_t, P],
         "pp_lm_presort_noalloc": [P, P, P, I64, G, T, I32, P, P],

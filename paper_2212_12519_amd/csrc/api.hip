@@ -322,6 +322,22 @@ int pp_fwd_tof_lm(const float* xstart, const float* xend, const int16_t* tof_bin
     return hip_status(launch_fwd_tof_lm(coords(xstart, xend), tof_bin, n, g, t, img, p, order, as_stream(stream)));
 }
 
+int pp_fwd_tof_lm_gather(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n,
+                         const pp_image_t* geom, const pp_tof_t* tof, const float* img, float* p, const int32_t* order,
+                         float* xstart_out, float* xend_out, int16_t* tof_bin_out, float* p_out, void* stream) {
+    GeomK g;
+    TofK t;
+    PP_TRY(make_geom(geom, g));
+    PP_TRY(make_tof(tof, t));
+    PP_TRY(check_n(n));
+    if (t.sig_ray || t.off_ray) return PP_EINVAL_TOF;  // per-event TOF arrays are not reordered
+    if (n == 0) return PP_OK;
+    if (!xstart || !xend || !tof_bin || !img || !p || !order || !xstart_out || !xend_out || !tof_bin_out || !p_out)
+        return PP_EINVAL_PTR;
+    return hip_status(launch_fwd_tof_lm_gather(coords(xstart, xend), tof_bin, n, g, t, img, p, order,
+                                               EventsOut{xstart_out, xend_out, tof_bin_out, p_out}, as_stream(stream)));
+}
+
 int pp_fwd_tof_lm_batch(const float* xstart, const float* xend, const int16_t* tof_bin, int64_t n,
                         const pp_image_t* geom, const pp_tof_t* tof, const float* imgs, int32_t n_img, float* p,
                         const int32_t* order, void* stream) {

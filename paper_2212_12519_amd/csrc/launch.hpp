@@ -12,6 +12,14 @@ struct GeomK;
 struct TofK;
 struct RaySrc;
 
+// Events and projections written in processing order by launch_fwd_tof_lm_gather
+struct EventsOut {
+    float* xs;
+    float* xe;
+    int16_t* bins;
+    float* p;
+};
+
 hipError_t launch_fwd(const RaySrc& src, int64_t n, const GeomK& g, const float* img, float* p,
                       const int32_t* order, hipStream_t s);
 hipError_t launch_back(const RaySrc& src, int64_t n, const GeomK& g, float* img, const float* p,
@@ -24,6 +32,9 @@ hipError_t launch_tof_gauss_table(float* lut, int n, double x0, double dx, doubl
                                   hipStream_t s);
 hipError_t launch_fwd_tof_lm(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g,
                              const TofK& t, const float* img, float* p, const int32_t* order, hipStream_t s);
+hipError_t launch_fwd_tof_lm_gather(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g,
+                                    const TofK& t, const float* img, float* p, const int32_t* order,
+                                    const EventsOut& eo, hipStream_t s);
 hipError_t launch_fwd_tof_lm_batch(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g, const TofK& t,
                                    const float* imgs, int n_img, float* p, const int32_t* order, hipStream_t s);
 hipError_t launch_back_tof_lm(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g,

@@ -46,11 +46,15 @@ __global__ void __launch_bounds__(kBlock) k_fwd(RaySrc src,
 // of a wave gather from the same planes at each step; with per-ray parameters the windows start
 // at different planes, so the loop runs over absolute planes instead (wave-synchronous: all
 // lanes at plane k, each active inside its own window), keeping the gathers of a step coherent.
-template <int Form, bool PerRay>
+// Emit: also write the events and their projections in processing order (thread i: the event order[i];
+// an order entry outside [0, n) gives event i with the value 0), for a back projection that then walks
+// them without an order array.
+template <int Form, bool PerRay, bool Emit = false>
 __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(RaySrc src,
                                                        const int16_t* __restrict__ bins, int64_t n, GeomK g,
                                                        TofK t, const float* __restrict__ img,
-                                                       float* __restrict__ p, const int32_t* __restrict__ order) {
+                                                       float* __restrict__ p, const int32_t* __restrict__ order,
+                                                       EventsOut eo) {
     constexpr bool kWaveSync = PerRay;
     const __amdgpu_buffer_rsrc_t ib = img_buffer(img, g);
     const int64_t l = ray_index(order, n);
@@ -60,7 +64,16 @@ __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(RaySrc src,
     float acc = 0.0f;
     RayK r;
     TofRay q;
-    const bool geo = ray_setup(src, lc, g, r);
+    // Emit: the end points stay in registers for the copy (coordinate events only)
+    float ev[6];
+    bool geo;
+    if constexpr (Emit) {
+        const float *ps = src.xs + 3 * lc, *pe = src.xe + 3 * lc;
+        ev[0] = ps[0], ev[1] = ps[1], ev[2] = ps[2], ev[3] = pe[0], ev[4] = pe[1], ev[5] = pe[2];
+        geo = ray_setup(ev, ev + 3, g, r);
+    } else {
+        geo = ray_setup(src, lc, g, r);
+    }
     const bool tr = tof_ray<PerRay>(t, lc, q);
     bool on = l >= 0 && b >= 0 && b < t.nb && tr && geo;
     if (on) {
@@ -84,6 +97,23 @@ __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(RaySrc src,
     }
     if (on) acc *= r.ell * kTofScale<Form>;
     if (l >= 0) p[l] = acc;
+    if constexpr (Emit) {
+        const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+        if (i < n) {
+            if (l < 0) {  // an order entry outside [0, n): event i
+                const float *ps = src.xs + 3 * i, *pe = src.xe + 3 * i;
+                ev[0] = ps[0], ev[1] = ps[1], ev[2] = ps[2], ev[3] = pe[0], ev[4] = pe[1], ev[5] = pe[2];
+            }
+            eo.xs[3 * i] = ev[0];
+            eo.xs[3 * i + 1] = ev[1];
+            eo.xs[3 * i + 2] = ev[2];
+            eo.xe[3 * i] = ev[3];
+            eo.xe[3 * i + 1] = ev[4];
+            eo.xe[3 * i + 2] = ev[5];
+            eo.bins[i] = l >= 0 ? (int16_t)b : bins[i];
+            eo.p[i] = l >= 0 ? acc : 0.0f;
+        }
+    }
 }
 
 // Batched listmode forward: the same events through `nimg` images of the grid (imgs[b] at b * voxels,
@@ -274,7 +304,19 @@ hipError_t launch_fwd_tof_lm(const RaySrc& src, const int16_t* bins, int64_t n, 
     auto* k = form == kFormLut    ? (per ? k_fwd_tof_lm<kFormLut, true> : k_fwd_tof_lm<kFormLut, false>)
               : form == kFormPoly ? (per ? k_fwd_tof_lm<kFormPoly, true> : k_fwd_tof_lm<kFormPoly, false>)
                                   : (per ? k_fwd_tof_lm<kFormErf, true> : k_fwd_tof_lm<kFormErf, false>);
-    hipLaunchKernelGGL(k, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, src, bins, n, g, t, img, p, order);
+    hipLaunchKernelGGL(k, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, src, bins, n, g, t, img, p, order,
+                       EventsOut{});
+    return hipGetLastError();
+}
+
+hipError_t launch_fwd_tof_lm_gather(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g,
+                                    const TofK& t, const float* img, float* p, const int32_t* order,
+                                    const EventsOut& eo, hipStream_t s) {
+    const int form = tof_form(t);
+    auto* k = form == kFormLut    ? k_fwd_tof_lm<kFormLut, false, true>
+              : form == kFormPoly ? k_fwd_tof_lm<kFormPoly, false, true>
+                                  : k_fwd_tof_lm<kFormErf, false, true>;
+    hipLaunchKernelGGL(k, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, src, bins, n, g, t, img, p, order, eo);
     return hipGetLastError();
 }
 

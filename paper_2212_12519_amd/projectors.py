@@ -80,6 +80,29 @@ def pp_fwd_tof_lm(xstart, xend, tof_bin, geom, tof, img, p, order=None):
     return p
 
 
+def pp_fwd_tof_lm_gather(xstart, xend, tof_bin, geom, tof, img, p, order, xstart_out, xend_out, tof_bin_out, p_out):
+    """pp_fwd_tof_lm into p[n] that also writes the events and projections in processing order
+    (xstart_out[i] = xstart[order[i]], ..., p_out[i] = p[order[i]])."""
+    g, t = as_geom(geom), as_tof(tof)
+    _dev(xstart, xend, tof_bin, img, p, order, xstart_out, xend_out, tof_bin_out, p_out)
+    n = _rays(xstart, xend)
+    _bins(tof_bin, n)
+    _img(img, g)
+    if order is None:
+        raise ValueError("order is required")
+    _order(order, n)
+    if _rays(xstart_out, xend_out) != n:
+        raise ValueError("xstart_out, xend_out must be float32 [n, 3]")
+    _bins(tof_bin_out, n)
+    for a in (p, p_out):
+        if a.dtype != torch.float32 or a.numel() != n:
+            raise ValueError("p and p_out must be float32 [n]")
+    check(load().pp_fwd_tof_lm_gather(ptr(xstart), ptr(xend), ptr(tof_bin), n, g.c(), t.c(n), ptr(img), ptr(p),
+                                      ptr(order), ptr(xstart_out), ptr(xend_out), ptr(tof_bin_out), ptr(p_out),
+                                      stream_of(p)))
+    return p
+
+
 def pp_fwd_tof_lm_batch(xstart, xend, tof_bin, geom, tof, imgs, p, order=None):
     """pp_fwd_tof_lm through a batch of images: imgs [B, *dim] -> p [B, n] (overwritten)."""
     g, t = as_geom(geom), as_tof(tof)
@@ -319,6 +342,17 @@ def back_tof_lm_batch(xstart, xend, tof_bin, geom, tof, p, order=None):
     nb = p.shape[0]
     imgs = torch.zeros((nb, *g.dim), dtype=torch.float32, device=p.device)
     return pp_back_tof_lm_batch(xstart, xend, tof_bin, geom, tof, imgs, p, order)
+
+
+def fwd_tof_lm_gather(xstart, xend, tof_bin, geom, tof, img, order):
+    """-> (p, xstart_sorted, xend_sorted, tof_bin_sorted, p_sorted): the projections indexed by event and
+    the events with their projections in processing order (new tensors)."""
+    n = xstart.shape[0]
+    p, p_out = (torch.empty(n, dtype=torch.float32, device=xstart.device) for _ in range(2))
+    xs_out, xe_out = torch.empty_like(xstart), torch.empty_like(xend)
+    b_out = torch.empty_like(tof_bin)
+    pp_fwd_tof_lm_gather(xstart, xend, tof_bin, geom, tof, img, p, order, xs_out, xe_out, b_out, p_out)
+    return p, xs_out, xe_out, b_out, p_out
 
 
 def fwd_tof_lm_batch(xstart, xend, tof_bin, geom, tof, imgs, order=None):

@@ -30,7 +30,7 @@ def test_exports_every_declared_symbol(lib):
     assert len(names) >= 12, names
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.pp_abi_version() == 7
+    assert lib.pp_abi_version() == 8
     # the entry points the boundary is specified with: the six projectors, the batched OSEM pair
     for n in ("pp_fwd", "pp_back", "pp_fwd_tof_sino", "pp_back_tof_sino", "pp_fwd_tof_lm", "pp_back_tof_lm",
               "pp_lm_osem_subset_batched", "pp_osem_update_batched", "pp_strerror", "pp_abi_version",
@@ -101,6 +101,21 @@ def test_error_codes(lib):
         assert f(DUMMY, DUMMY, DUMMY, 5, g, _tof(), DUMMY, 2, None, None, None) == PP_EINVAL_PTR
         assert f(DUMMY, DUMMY, DUMMY, 5, g, _tof(), DUMMY, 0, DUMMY, None, None) == PP_OK
         assert f(DUMMY, DUMMY, DUMMY, 0, g, _tof(), DUMMY, 2, DUMMY, None, None) == PP_OK
+    # forward projection with the events written in processing order: order and outputs required,
+    # per-event TOF arrays refused
+    gf = lib.pp_fwd_tof_lm_gather
+    outs = (DUMMY2, DUMMY2, DUMMY2, DUMMY2)
+    assert gf(DUMMY, DUMMY, DUMMY, 5, g, _tof(), DUMMY, DUMMY, None, *outs, None) == PP_EINVAL_PTR
+    for k in range(4):
+        o = list(outs)
+        o[k] = None
+        assert gf(DUMMY, DUMMY, DUMMY, 5, g, _tof(), DUMMY, DUMMY, DUMMY3, *o, None) == PP_EINVAL_PTR
+    assert gf(DUMMY, DUMMY, DUMMY, 0, g, _tof(), DUMMY, DUMMY, None, None, None, None, None, None) == PP_OK
+    assert gf(DUMMY, DUMMY, DUMMY, -1, g, _tof(), DUMMY, DUMMY, DUMMY3, *outs, None) == PP_EINVAL_N
+    for field in ("sigma_per_ray", "offset_per_ray"):
+        t = _tof()
+        setattr(t, field, DUMMY2.value)
+        assert gf(DUMMY, DUMMY, DUMMY, 5, g, t, DUMMY, DUMMY, DUMMY3, *outs, None) == PP_EINVAL_TOF
     # crystal-index events: table size, pointers, 8-byte alignment of the pairs
     assert lib.pp_fwd_crystals(DUMMY, 0, DUMMY, 5, g, DUMMY2, DUMMY3, None, None) == PP_EINVAL_N
     assert lib.pp_fwd_crystals(None, 10, DUMMY, 5, g, DUMMY2, DUMMY3, None, None) == PP_EINVAL_PTR
