@@ -64,13 +64,28 @@ __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(RaySrc src,
     float acc = 0.0f;
     RayK r;
     TofRay q;
-    // Emit: the end points stay in registers for the copy (coordinate events only)
-    float ev[6];
+    // Emit: the event is copied from the registers of its setup, before the plane loop (coordinate
+    // events only; an order entry outside [0, n) copies event i)
     bool geo;
     if constexpr (Emit) {
+        float ev[6];
         const float *ps = src.xs + 3 * lc, *pe = src.xe + 3 * lc;
         ev[0] = ps[0], ev[1] = ps[1], ev[2] = ps[2], ev[3] = pe[0], ev[4] = pe[1], ev[5] = pe[2];
         geo = ray_setup(ev, ev + 3, g, r);
+        const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+        if (i < n) {
+            if (l < 0) {
+                const float *qs = src.xs + 3 * i, *qe = src.xe + 3 * i;
+                ev[0] = qs[0], ev[1] = qs[1], ev[2] = qs[2], ev[3] = qe[0], ev[4] = qe[1], ev[5] = qe[2];
+            }
+            eo.xs[3 * i] = ev[0];
+            eo.xs[3 * i + 1] = ev[1];
+            eo.xs[3 * i + 2] = ev[2];
+            eo.xe[3 * i] = ev[3];
+            eo.xe[3 * i + 1] = ev[4];
+            eo.xe[3 * i + 2] = ev[5];
+            eo.bins[i] = l >= 0 ? (int16_t)b : bins[i];
+        }
     } else {
         geo = ray_setup(src, lc, g, r);
     }
@@ -99,20 +114,7 @@ __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(RaySrc src,
     if (l >= 0) p[l] = acc;
     if constexpr (Emit) {
         const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-        if (i < n) {
-            if (l < 0) {  // an order entry outside [0, n): event i
-                const float *ps = src.xs + 3 * i, *pe = src.xe + 3 * i;
-                ev[0] = ps[0], ev[1] = ps[1], ev[2] = ps[2], ev[3] = pe[0], ev[4] = pe[1], ev[5] = pe[2];
-            }
-            eo.xs[3 * i] = ev[0];
-            eo.xs[3 * i + 1] = ev[1];
-            eo.xs[3 * i + 2] = ev[2];
-            eo.xe[3 * i] = ev[3];
-            eo.xe[3 * i + 1] = ev[4];
-            eo.xe[3 * i + 2] = ev[5];
-            eo.bins[i] = l >= 0 ? (int16_t)b : bins[i];
-            eo.p[i] = l >= 0 ? acc : 0.0f;
-        }
+        if (i < n) eo.p[i] = l >= 0 ? acc : 0.0f;
     }
 }
 
