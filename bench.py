@@ -312,7 +312,7 @@ def resmodel_leg(args, pp, C, dev):
         alg = 3 * 8 * src.numel()
         once = 8 * src.numel()
         out[name] = {"t_ms": t, "alg_bytes": alg, "alg_gbs": alg / (t * 1e-3) / 1e9,
-                     "hbm_frac": alg / (t * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "alg_frac": alg / (t * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "compulsory_bytes": once, "compulsory_frac": once / (t * 1e-3) / 1e9 / HBM_PEAK_GBS}
         log(f"resolution model {name}: {t * 1e3:.1f} us, {alg / (t * 1e-3) / 1e9:.0f} GB/s (3 passes), "
             f"{once / (t * 1e-3) / 1e9:.0f} GB/s (image read + written once)")
