@@ -286,31 +286,51 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t img_buffer_n(const float* img,
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(img), (short)0, (int)bytes, 0x00020000);
 }
 
-// bilinear interpolation with zero padding
-__device__ __forceinline__ float stencil_gather(__amdgpu_buffer_rsrc_t ib, const RayK& r, const Stencil& st) {
+// The four neighbours of a sample, zero outside the grid.  When axis w is the contiguous one
+// (stride 1: every ray whose principal axis is 0 or 1) and the grid has at least two voxels along
+// it, each pair (j0, j0 + 1) of a row is read with one 8-byte load: at j0 when both are inside,
+// one voxel earlier when only j0 is (the last voxel of the row), one later when only j0 + 1 is (the
+// first), so that the load never leaves its row; four 4-byte loads otherwise.  Same values either
+// way.  `base` is the flat index of voxel (k, i0, j0) in the buffer.  Pairs = false: always the four
+// loads (kernels bound by arithmetic, where the per-sample choice costs more than the loads save).
+template <bool Pairs = true>
+__device__ __forceinline__ void stencil_load(__amdgpu_buffer_rsrc_t ib, const RayK& r, const Stencil& st, int base,
+                                             float& v00, float& v01, float& v10, float& v11) {
     // the neighbours' indices as additions to the base (an empty asm keeps the compiler from
     // turning them back into products, which are quarter-rate instructions)
-    int base = st.base;
     asm volatile("" : "+v"(base));
-    const int b01 = base + r.sw, b10 = base + r.su;
-    const float v00 = img_load(ib, st.i0ok && st.j0ok, base);
-    const float v01 = img_load(ib, st.i0ok && st.j1ok, b01);
-    const float v10 = img_load(ib, st.i1ok && st.j0ok, b10);
-    const float v11 = img_load(ib, st.i1ok && st.j1ok, b10 + r.sw);
+    const int b10 = base + r.su;
+    if (Pairs && r.sw == 1 && r.nw >= 2) {
+        const int sh = st.j0ok ? (st.j1ok ? 0 : -1) : 1;
+        const auto a = __builtin_amdgcn_raw_buffer_load_b64(ib, st.i0ok ? (unsigned)(base + sh) * 4u : 0xFFFFFFF0u, 0, 0);
+        const auto c = __builtin_amdgcn_raw_buffer_load_b64(ib, st.i1ok ? (unsigned)(b10 + sh) * 4u : 0xFFFFFFF0u, 0, 0);
+        v00 = st.i0ok && st.j0ok ? __uint_as_float(st.j1ok ? a[0] : a[1]) : 0.0f;
+        v01 = st.i0ok && st.j1ok ? __uint_as_float(st.j0ok ? a[1] : a[0]) : 0.0f;
+        v10 = st.i1ok && st.j0ok ? __uint_as_float(st.j1ok ? c[0] : c[1]) : 0.0f;
+        v11 = st.i1ok && st.j1ok ? __uint_as_float(st.j0ok ? c[1] : c[0]) : 0.0f;
+    } else {
+        v00 = img_load(ib, st.i0ok && st.j0ok, base);
+        v01 = img_load(ib, st.i0ok && st.j1ok, base + r.sw);
+        v10 = img_load(ib, st.i1ok && st.j0ok, b10);
+        v11 = img_load(ib, st.i1ok && st.j1ok, b10 + r.sw);
+    }
+}
+
+// bilinear interpolation with zero padding
+template <bool Pairs = true>
+__device__ __forceinline__ float stencil_gather(__amdgpu_buffer_rsrc_t ib, const RayK& r, const Stencil& st) {
+    float v00, v01, v10, v11;
+    stencil_load<Pairs>(ib, r, st, st.base, v00, v01, v10, v11);
     const float gu = 1.0f - st.fu, gw = 1.0f - st.fw;
     return gu * (gw * v00 + st.fw * v01) + st.fu * (gw * v10 + st.fw * v11);
 }
 
 // stencil_gather of the image that starts `img_off` voxels into the buffer (same arithmetic)
+template <bool Pairs = true>
 __device__ __forceinline__ float stencil_gather_at(__amdgpu_buffer_rsrc_t ib, const RayK& r, const Stencil& st,
                                                    int img_off) {
-    int base = st.base + img_off;
-    asm volatile("" : "+v"(base));
-    const int b01 = base + r.sw, b10 = base + r.su;
-    const float v00 = img_load(ib, st.i0ok && st.j0ok, base);
-    const float v01 = img_load(ib, st.i0ok && st.j1ok, b01);
-    const float v10 = img_load(ib, st.i1ok && st.j0ok, b10);
-    const float v11 = img_load(ib, st.i1ok && st.j1ok, b10 + r.sw);
+    float v00, v01, v10, v11;
+    stencil_load<Pairs>(ib, r, st, st.base + img_off, v00, v01, v10, v11);
     const float gu = 1.0f - st.fu, gw = 1.0f - st.fw;
     return gu * (gw * v00 + st.fw * v01) + st.fu * (gw * v10 + st.fw * v11);
 }

@@ -101,13 +101,13 @@ __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(RaySrc src,
         for (int k = k0; k <= k1; ++k) {
             if (k >= lo && k <= hi) {
                 const float w = tof_weight_unscaled<Form>(fma((double)k, r.ds, r.s0), t, q.inv);
-                acc += w * stencil_gather(ib, r, stencil_at(r, k));
+                acc += w * stencil_gather<!PerRay>(ib, r, stencil_at(r, k));  // per-ray: arithmetic-bound
             }
         }
     } else if (on) {
         for (int k = r.k_lo; k <= r.k_hi; ++k) {
             const float w = tof_weight_unscaled<Form>(fma((double)k, r.ds, r.s0), t, q.inv);
-            acc += w * stencil_gather(ib, r, stencil_at(r, k));
+            acc += w * stencil_gather<!PerRay>(ib, r, stencil_at(r, k));
         }
     }
     if (on) acc *= r.ell * kTofScale<Form>;
@@ -153,7 +153,7 @@ __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm_batch(RaySrc src, const i
         const Stencil st = stencil_at(r, k);
 #pragma unroll
         for (int q = 0; q < kFwdBatch; ++q)
-            if (q < nimg) acc[q] += w * stencil_gather_at(ib, r, st, q * nv);  // nimg: uniform
+            if (q < nimg) acc[q] += w * stencil_gather_at<!PerRay>(ib, r, st, q * nv);  // nimg: uniform
     };
     if (kWaveSync) {  // every lane of the wave reaches this point
         const int lo = on ? r.k_lo : (1 << 30), hi = on ? r.k_hi : -(1 << 30);
@@ -194,7 +194,7 @@ __global__ void k_fwd_tof_sino(RaySrc src, int64_t n, GeomK g,
         if (PerRay) r.s0 -= q.shift;
         float* mine = lds + threadIdx.x;
         for (int k = r.k_lo; k <= r.k_hi; ++k) {
-            const float v = stencil_gather(ib, r, stencil_at(r, k));
+            const float v = stencil_gather<false>(ib, r, stencil_at(r, k));  // arithmetic-bound
             if (v == 0.0f) continue;
             const double s = fma((double)k, r.ds, r.s0);
             int b_lo, b_hi;
