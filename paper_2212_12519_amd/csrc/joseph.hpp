@@ -425,6 +425,14 @@ __device__ __forceinline__ float tof_lut(double x, const TofK& t) {
 // transcendental instruction) and the one for y selected; 0 beyond the support.  The host checks
 // the float32 evaluation against the exact weight and falls back to the erf form if it misses
 // its bound.
+// The polynomial constants that meet a second scalar operand in one instruction (the first
+// coefficients of the two Horner chains, the tail variable's offset), moved to vector registers once
+// before a plane loop: an instruction reads at most one scalar register, so otherwise the compiler
+// may copy them to vector registers again in every step.
+__device__ __forceinline__ void tof_poly_to_vgprs(TofK& t) {
+    asm volatile("" : "+v"(t.pc[kPolyCentral]), "+v"(t.pt[kPolyTail]), "+v"(t.pb2));
+}
+
 __device__ __forceinline__ float tof_poly(float x, const TofK& t) {
     const float y = fabsf(x), u = y * t.pq1;
     const float s1 = fmaf(u, u, -1.0f), s2 = fmaf(y, t.pa2, t.pb2);

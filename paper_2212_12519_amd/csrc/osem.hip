@@ -73,6 +73,9 @@ struct ModeOsem {
     __device__ float sample(double x, float cv, int /*aux*/) const {
         return tof_weight_unscaled<Form>(x, t, t.u_per_mm) * cv;
     }
+    __device__ void to_vgprs() {
+        if constexpr (Form == kFormPoly) tof_poly_to_vgprs(t);
+    }
     __device__ float mag(float cv, int /*aux*/) const { return fabsf(cv); }
     __device__ float weight_bound(float* red) const { return tof_weight_bound<Form>(t, red); }
 };

@@ -117,6 +117,7 @@ struct ModeNonTof {
         return true;
     }
     __device__ float sample(double /*x*/, float cv, int /*aux*/) const { return cv; }
+    __device__ void to_vgprs() {}
     __device__ float mag(float cv, int /*aux*/) const { return fabsf(cv); }
     __device__ float weight_bound(float* /*red*/) const { return 1.0f; }
 };
@@ -150,6 +151,9 @@ struct ModeTofLm {
     }
     __device__ float sample(double x, float cv, int aux) const {
         return tof_weight_unscaled<Form>(x, t, PerRay ? __int_as_float(aux) : t.u_per_mm) * cv;
+    }
+    __device__ void to_vgprs() {
+        if constexpr (Form == kFormPoly) tof_poly_to_vgprs(t);
     }
     __device__ float mag(float cv, int /*aux*/) const { return fabsf(cv); }
     __device__ float weight_bound(float* red) const { return tof_weight_bound<Form>(t, red); }
@@ -199,6 +203,7 @@ struct ModeTofSino {
         return c * cv;
     }
     // a bin weight is at most w(0) (1 with per-ray sigma) or the table's largest entry
+    __device__ void to_vgprs() {}
     __device__ float mag(float cv, int aux) const {
         const float* pr = p + (int64_t)aux * t.nb;
         float a = 0.0f;
@@ -342,6 +347,9 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
         for (int q = tid; q < nw * cs; q += B) col[q] = 0;
     // bound of |an added value| per unit of a ray's mag() (margin for float rounding in the bounds)
     const float wb = m.weight_bound(red) * (1.0f + 0x1p-8f);
+    // the mode as the plane loops use it (constants they need in vector registers moved there once)
+    Mode ms = m;
+    ms.to_vgprs();
     // current sheet (block-uniform copies in registers, updated after barriers)
     bool sh_on = false;
     float sh_scale = 1.0f, sh_used = 0.0f;  // fixed-point scale of the sheet; bounds added (scaled)
@@ -362,7 +370,7 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
         RayK r;
         float cv = 0.0f;
         int ax = 0;
-        const bool ok = l >= 0 && m.setup(l, src, g, r, cv, ax);
+        const bool ok = l >= 0 && ms.setup(l, src, g, r, cv, ax);
         // compact the valid rays to the front of the group (stable order), so that rays
         // without a contribution do not break runs
         const unsigned long long vb = __ballot(ok);
@@ -500,7 +508,7 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
                     float v = 0.0f;
                     if (act) {
                         stn = stencil_at(r, k);
-                        v = m.sample(fma((double)k, r.ds, r.s0), cvb, ax);
+                        v = ms.sample(fma((double)k, r.ds, r.s0), cvb, ax);
                     }
                     wave_stencil_scatter(imgb, act && v != 0.0f, r, stn, v);
                 }
@@ -617,7 +625,7 @@ __device__ void back_runs_chunk(const Mode& m, RaySrc src, int64_t n,
                                 const double fj = floor(W);
                                 const int j0 = (int)fj;
                                 const float fw = (float)(W - fj);
-                                const float v = m.sample(fma((double)k, cur.ds, cur.s0), cvs_, cur.ax);
+                                const float v = ms.sample(fma((double)k, cur.ds, cur.s0), cvs_, cur.ax);
                                 if (!decltype(mixed)::value || !direct) {
                                     const unsigned kb = 4u * (unsigned)k + colb;
                                     const unsigned a0 = __umul24(min((unsigned)j0, (unsigned)nw), cs4) + kb;
