@@ -445,6 +445,29 @@ __device__ __forceinline__ float tof_poly(float x, const TofK& t) {
     return y < t.pk1 ? a : (y < t.pk2 ? b : 0.0f);
 }
 
+// tof_poly with the piece chosen for the whole wave when every active lane is on the same one: only
+// that polynomial is evaluated (presorted events of a wave walk through their windows in step, so in
+// the forward loops most steps are uniform).  The same operations per lane, so the same values.
+__device__ __forceinline__ float tof_poly_wave(float x, const TofK& t) {
+    const float y = fabsf(x);
+    const bool central = y < t.pk1;
+    if (__ballot(!central) == 0ull) {
+        const float u = y * t.pq1, s1 = fmaf(u, u, -1.0f);
+        float a = t.pc[kPolyCentral];
+#pragma unroll
+        for (int i = kPolyCentral - 1; i >= 0; --i) a = fmaf(a, s1, t.pc[i]);
+        return a;
+    }
+    if (__ballot(central) == 0ull) {
+        const float s2 = fmaf(y, t.pa2, t.pb2);
+        float b = t.pt[kPolyTail];
+#pragma unroll
+        for (int i = kPolyTail - 1; i >= 0; --i) b = fmaf(b, s2, t.pt[i]);
+        return y < t.pk2 ? b : 0.0f;
+    }
+    return tof_poly(x, t);
+}
+
 // How a kernel evaluates the TOF bin weight: the two clipped erf (any sigma, also per ray), the
 // table, or the fitted polynomial (one sigma for all rays).
 enum TofForm : int { kFormErf = 0, kFormLut = 1, kFormPoly = 2 };
@@ -465,10 +488,12 @@ __host__ __device__ inline int tof_form(const TofK& t) {
 template <int Form>
 constexpr float kTofScale = Form == kFormErf ? 0.5f : 1.0f;
 
-template <int Form>
+// Wave: the polynomial's piece chosen per wave where uniform (tof_poly_wave; any lane pattern is
+// allowed, the ballots see the active lanes)
+template <int Form, bool Wave = false>
 __device__ __forceinline__ float tof_weight_unscaled(double x, const TofK& t, float inv) {
     if (Form == kFormLut) return tof_lut(x, t);
-    if (Form == kFormPoly) return tof_poly((float)x, t);
+    if (Form == kFormPoly) return Wave ? tof_poly_wave((float)x, t) : tof_poly((float)x, t);
     const float xf = (float)x, h = t.hbw * inv;
     return erf_scaled(__builtin_amdgcn_fmed3f(fmaf(xf, inv, h), -t.u_max, t.u_max)) -
            erf_scaled(__builtin_amdgcn_fmed3f(fmaf(xf, inv, -h), -t.u_max, t.u_max));

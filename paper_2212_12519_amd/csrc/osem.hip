@@ -62,7 +62,7 @@ struct ModeOsem {
         const __amdgpu_buffer_rsrc_t ib = img_buffer(x, g);
         float fwd = 0.0f;
         for (int k = r.k_lo; k <= r.k_hi; ++k) {
-            const float w = tof_weight_unscaled<Form>(fma((double)k, r.ds, r.s0), t, t.u_per_mm);
+            const float w = tof_weight_unscaled<Form, true>(fma((double)k, r.ds, r.s0), t, t.u_per_mm);
             fwd += w * stencil_gather(ib, r, stencil_at(r, k));
         }
         const float ybar = r.ell * kTofScale<Form> * fwd + bg;

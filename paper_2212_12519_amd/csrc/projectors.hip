@@ -100,13 +100,13 @@ __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm(RaySrc src,
         const int k0 = wave_min(lo), k1 = wave_max(hi);
         for (int k = k0; k <= k1; ++k) {
             if (k >= lo && k <= hi) {
-                const float w = tof_weight_unscaled<Form>(fma((double)k, r.ds, r.s0), t, q.inv);
+                const float w = tof_weight_unscaled<Form, true>(fma((double)k, r.ds, r.s0), t, q.inv);
                 acc += w * stencil_gather<!PerRay>(ib, r, stencil_at(r, k));  // per-ray: arithmetic-bound
             }
         }
     } else if (on) {
         for (int k = r.k_lo; k <= r.k_hi; ++k) {
-            const float w = tof_weight_unscaled<Form>(fma((double)k, r.ds, r.s0), t, q.inv);
+            const float w = tof_weight_unscaled<Form, true>(fma((double)k, r.ds, r.s0), t, q.inv);
             acc += w * stencil_gather<!PerRay>(ib, r, stencil_at(r, k));
         }
     }
@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(kBlock) k_fwd_tof_lm_batch(RaySrc src, const i
         on = tof_window_rel(r, t.c0 + b * t.bw, tq.lo, tq.hi);
     }
     auto sample = [&](int k) {
-        const float w = tof_weight_unscaled<Form>(fma((double)k, r.ds, r.s0), t, tq.inv);
+        const float w = tof_weight_unscaled<Form, true>(fma((double)k, r.ds, r.s0), t, tq.inv);
         const Stencil st = stencil_at(r, k);
 #pragma unroll
         for (int q = 0; q < kFwdBatch; ++q)
