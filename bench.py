@@ -419,7 +419,7 @@ def autograd_leg(args, pp, C, dev, lm_inputs):
 
     def fwd():
         x = imgs.clone().requires_grad_(True)
-        state["x"], state["loss"] = x, poisson_nll(op(x) + C.BG_DL, y)
+        state["x"], state["loss"] = x, poisson_nll(op(x), y, C.BG_DL)
 
     def bwd():
         state["loss"].backward()

@@ -75,7 +75,7 @@
 extern "C" {
 #endif
 
-#define PP_ABI_VERSION 8
+#define PP_ABI_VERSION 9
 
 enum pp_status {
     PP_OK = 0,
@@ -451,6 +451,22 @@ int pp_tof_sino_osem_subset(const float* xstart, const float* xend, const float*
  * fwhm: host array of 3 values in mm.  Errors: PP_EINVAL_PTR (NULL or
  * overlapping arrays), PP_EINVAL_GEOM, PP_EINVAL_RES. */
 int pp_gauss3d(const float* src, float* dst, float* tmp, const pp_image_t* geom, const float* fwhm, void* stream);
+
+/* Poisson data fidelity of listmode or sinogram projections p with a constant
+ * background bg and data y (the loss whose gradient the differentiable
+ * projectors back-project, Sec. 1 and 4): with ybar_e = p_e + bg (float32
+ * addition), in float64 per element
+ *   L = sum_e (ybar_e - y_e log ybar_e),   grad_e = 1 - y_e / ybar_e,
+ * grad stored as float32 [n].  One pass: workgroup b of the n_partial
+ * workgroups (grid-stride over the elements) writes its float64 partial sum
+ * to partial[b]; L = sum_b partial[b] (left to the caller, so the result
+ * does not depend on atomic order).  ybar_e <= 0 gives what the formula
+ * gives in IEEE arithmetic (infinite or NaN terms).  p, y, grad: DEVICE
+ * float32 [n]; partial: DEVICE float64 [n_partial].  Errors: PP_EINVAL_N
+ * (n < 0, n_partial outside [1, 65536], bg not finite), PP_EINVAL_PTR.
+ * n == 0 writes zero partial sums. */
+int pp_poisson_nll(const float* p, float bg, const float* y, int64_t n, float* grad, double* partial,
+                   int32_t n_partial, void* stream);
 
 /* Sets n floats at dst to value (a kernel, safe inside captured graphs). */
 int pp_fill(float* dst, int64_t n, float value, void* stream);

@@ -169,6 +169,7 @@ def load():
         "pp_osem_update_batched": [P, I32, G, P, P],
         "pp_gauss3d": [P, P, P, G, P, P],
         "pp_fill": [P, I64, ctypes.c_float, P],
+        "pp_poisson_nll": [P, ctypes.c_float, P, I64, P, P, I32, P],
         "pp_count_samples": [P, P, P, I64, G, T, P, P],
         "pp_fwd_crystals": [P, I32, P, I64, G, P, P, P, P],
         "pp_back_crystals": [P, I32, P, I64, G, P, P, P, P],

@@ -128,6 +128,36 @@ class JosephBack(torch.autograd.Function):
         return JosephFwd.apply(g, ctx.op), None
 
 
-def poisson_nll(ybar, y):
-    """Poisson negative log-likelihood (up to a constant): sum(ybar - y log ybar), summed in float64."""
-    return (ybar.double() - y.double() * torch.log(ybar.double())).sum()
+class PoissonNLL(torch.autograd.Function):
+    """L = sum(ybar - y log ybar), ybar = p + bg: the loss and its gradient 1 - y / ybar in one pass of
+    the library's kernel (float64 per element, the gradient stored as float32).  A backward that is
+    itself differentiated (create_graph) recomputes the gradient with torch operations instead."""
+
+    @staticmethod
+    def forward(ctx, p, y, bg):
+        pc = p.contiguous()
+        yc = y.to(device=p.device, dtype=torch.float32).contiguous()
+        grad = torch.empty_like(pc)
+        n_partial = max(1, min(2048, (pc.numel() + 255) // 256))
+        partial = torch.empty(n_partial, dtype=torch.float64, device=p.device)
+        P.pp_poisson_nll(pc, bg, yc, grad, partial)
+        ctx.save_for_backward(pc, yc, grad)
+        ctx.bg = bg
+        return partial.sum()
+
+    @staticmethod
+    def backward(ctx, g):
+        p, y, grad = ctx.saved_tensors
+        if torch.is_grad_enabled():  # differentiable form for higher derivatives
+            ybar = (p + ctx.bg).double()
+            return (g * (1.0 - y.double() / ybar)).to(p.dtype), None, None
+        return grad * g.to(grad.dtype), None, None
+
+
+def poisson_nll(ybar, y, bg=0.0):
+    """Poisson negative log-likelihood (up to a constant) of the expectation ybar + bg against the data
+    y: sum(ybar + bg - y log(ybar + bg)), accumulated in float64 (float32 ybar; the constant background
+    is added inside the kernel, in float32, as ``ybar + bg`` would)."""
+    if ybar.dtype != torch.float32:
+        raise TypeError("ybar must be float32")
+    return PoissonNLL.apply(ybar, y, float(bg))

@@ -655,6 +655,14 @@ int pp_gauss3d(const float* src, float* dst, float* tmp, const pp_image_t* geom,
     return hip_status(launch_gauss3d(src, dst, tmp, g, k, device_cus(), as_stream(stream)));
 }
 
+int pp_poisson_nll(const float* p, float bg, const float* y, int64_t n, float* grad, double* partial,
+                   int32_t n_partial, void* stream) {
+    if (n < 0 || n_partial < 1 || n_partial > 65536) return PP_EINVAL_N;
+    if (!std::isfinite(bg)) return PP_EINVAL_N;
+    if (!partial || (n > 0 && (!p || !y || !grad))) return PP_EINVAL_PTR;
+    return hip_status(launch_poisson_nll(p, bg, y, n, grad, partial, n_partial, as_stream(stream)));
+}
+
 int pp_fill(float* dst, int64_t n, float value, void* stream) {
     if (n < 0) return PP_EINVAL_N;
     if (n == 0) return PP_OK;

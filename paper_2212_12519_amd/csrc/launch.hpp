@@ -42,6 +42,8 @@ hipError_t launch_back_tof_lm(const RaySrc& src, const int16_t* bins, int64_t n,
 hipError_t launch_back_tof_lm_batch(const RaySrc& src, const int16_t* bins, int64_t n, const GeomK& g,
                                     const TofK& t, float* imgs, int n_img, const float* p, const int32_t* order,
                                     hipStream_t s);
+hipError_t launch_poisson_nll(const float* p, float bg, const float* y, int64_t n, float* grad, double* partial,
+                              int n_partial, hipStream_t s);
 size_t presort_workspace_bytes(int64_t n);
 // capacity of the library-owned presort workspace (one per GPU) and its device address on the
 // current GPU

@@ -217,6 +217,21 @@ def gather_events(xstart, xend, tof_bin, order):
     return xs, xe, tb
 
 
+def pp_poisson_nll(p, bg, y, grad, partial):
+    """Poisson loss of p + bg against y: grad[:] = 1 - y / (p + bg), partial[b] = the float64 partial
+    sums of sum(ybar - y log ybar) (library kernel, one pass); returns partial."""
+    _dev(p, y, grad, partial)
+    n = p.numel()
+    for a in (p, y, grad):
+        if a.dtype != torch.float32 or a.numel() != n or not a.is_contiguous():
+            raise ValueError("p, y, grad must be contiguous float32 of one size")
+    if partial.dtype != torch.float64 or partial.dim() != 1 or not partial.is_contiguous():
+        raise ValueError("partial must be a contiguous float64 vector")
+    check(load().pp_poisson_nll(ptr(p), float(bg), ptr(y), n, ptr(grad), ptr(partial), partial.numel(),
+                                stream_of(p)))
+    return partial
+
+
 def pp_fill(dst, value):
     """dst[:] = value with the library's fill kernel (graph-capture safe)."""
     _dev(dst)

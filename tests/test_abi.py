@@ -30,7 +30,7 @@ def test_exports_every_declared_symbol(lib):
     assert len(names) >= 12, names
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.pp_abi_version() == 8
+    assert lib.pp_abi_version() == 9
     # the entry points the boundary is specified with: the six projectors, the batched OSEM pair
     for n in ("pp_fwd", "pp_back", "pp_fwd_tof_sino", "pp_back_tof_sino", "pp_fwd_tof_lm", "pp_back_tof_lm",
               "pp_lm_osem_subset_batched", "pp_osem_update_batched", "pp_strerror", "pp_abi_version",
@@ -101,6 +101,14 @@ def test_error_codes(lib):
         assert f(DUMMY, DUMMY, DUMMY, 5, g, _tof(), DUMMY, 2, None, None, None) == PP_EINVAL_PTR
         assert f(DUMMY, DUMMY, DUMMY, 5, g, _tof(), DUMMY, 0, DUMMY, None, None) == PP_OK
         assert f(DUMMY, DUMMY, DUMMY, 0, g, _tof(), DUMMY, 2, DUMMY, None, None) == PP_OK
+    # Poisson loss: sizes, background, pointers; no elements still writes the partial sums
+    pl = lib.pp_poisson_nll
+    assert pl(DUMMY, 0.1, DUMMY, -1, DUMMY, DUMMY2, 4, None) == PP_EINVAL_N
+    assert pl(DUMMY, 0.1, DUMMY, 5, DUMMY, DUMMY2, 0, None) == PP_EINVAL_N
+    assert pl(DUMMY, 0.1, DUMMY, 5, DUMMY, DUMMY2, 65537, None) == PP_EINVAL_N
+    assert pl(DUMMY, float("inf"), DUMMY, 5, DUMMY, DUMMY2, 4, None) == PP_EINVAL_N
+    assert pl(DUMMY, 0.1, DUMMY, 5, None, DUMMY2, 4, None) == PP_EINVAL_PTR
+    assert pl(DUMMY, 0.1, DUMMY, 0, DUMMY, None, 4, None) == PP_EINVAL_PTR
     # forward projection with the events written in processing order: order and outputs required,
     # per-event TOF arrays refused
     gf = lib.pp_fwd_tof_lm_gather

@@ -143,3 +143,55 @@ def test_sinogram_least_squares_gradient(gpu, kind):
                                 img.numpy()) - y.numpy()
         ref = oracle.back_tof_sino(xs.numpy(), xe.numpy(), g["origin"], g["voxsize"], g["dim"], tof, r)
     assert rel_l2(np64(x.grad), ref) <= 1e-4
+
+
+def test_poisson_loss_kernel(gpu):
+    """pp_poisson_nll against the loss and gradient written out in float64 torch operations: a size that
+    is no multiple of the workgroup, zero data, a background, non-positive expectations (the IEEE
+    results of the formula), no elements; and the loss's Hessian-vector product through a
+    differentiated backward (y / ybar^2 times v)."""
+    from paper_2212_12519_amd.autograd import poisson_nll
+
+    dev = torch.device("cuda")
+    gen = torch.Generator().manual_seed(95)
+    n = 1_000_003
+    p = (torch.rand(n, generator=gen) * 3.0).to(dev)
+    y = torch.poisson(torch.rand(n, generator=gen) * 2.0).to(dev)
+    bg = 0.1
+    grad = torch.empty_like(p)
+    partial = torch.empty(1000, dtype=torch.float64, device=dev)
+    gpu.pp_poisson_nll(p, bg, y, grad, partial)
+    torch.cuda.synchronize()
+    yb = (p + bg).double()
+    ref = (yb - y.double() * torch.log(yb)).sum()
+    assert abs(float(partial.sum()) - float(ref)) <= 1e-12 * abs(float(ref))
+    assert torch.equal(grad, (1.0 - y.double() / yb).float())
+    # through autograd: the loss and its gradient
+    pr = p.clone().requires_grad_(True)
+    loss = poisson_nll(pr, y, bg)
+    loss.backward()
+    assert abs(float(loss.detach()) - float(ref)) <= 1e-12 * abs(float(ref))
+    assert torch.equal(pr.grad, grad)
+    # Hessian-vector product of the loss: d2L/dp2 = y / ybar^2
+    pr2 = p[:1000].clone().requires_grad_(True)
+    v = torch.rand(1000, generator=gen).to(dev)
+    (g1,) = torch.autograd.grad(poisson_nll(pr2, y[:1000], bg), pr2, create_graph=True)
+    (hv,) = torch.autograd.grad((g1 * v).sum(), pr2)
+    yb2 = (p[:1000] + bg).double()
+    assert rel_l2(np64(hv), (y[:1000].double() / yb2 ** 2 * v.double()).cpu().numpy()) <= 1e-6
+    # non-positive expectations: the formula's IEEE values
+    q = torch.tensor([-0.1, 0.0, 1.0], device=dev) - bg
+    yq = torch.tensor([1.0, 1.0, 0.0], device=dev)
+    gq, pq = torch.empty(3, device=dev), torch.empty(1, dtype=torch.float64, device=dev)
+    gpu.pp_poisson_nll(q, bg, yq, gq, pq)
+    torch.cuda.synchronize()
+    ybq = (q + bg).double()
+    rq = 1.0 - yq.double() / ybq
+    assert torch.equal(torch.isnan(gq), torch.isnan(rq.float())) and torch.equal(gq[2:], rq[2:].float())
+    assert not torch.isfinite(pq[0])
+    # no elements: zero partial sums
+    e = torch.empty(0, device=dev)
+    pz = torch.full((3,), 5.0, dtype=torch.float64, device=dev)
+    gpu.pp_poisson_nll(e, bg, e, e, pz)
+    torch.cuda.synchronize()
+    assert not torch.any(pz)
